@@ -1,0 +1,206 @@
+/*
+ * crl.h -- C ABI of the contrastive-RL (CRL) update hot path on MI355X (gfx950).
+ *
+ * One critic update of contrastive RL (Algorithm 1, the update loop):
+ *   1. draw a batch of (s, a) uniformly from a GPU-resident replay buffer and
+ *      relabel each goal to a future state of the same trajectory at a
+ *      geometric offset (Section 2.2 "Policy Learning"; Preliminaries, the
+ *      discounted state-visitation law; Appendix E)        -> crl_sample_relabel
+ *   2. run the encoders phi(s, a) and psi(g), form the B x B critic matrix
+ *      with the dot or L2 energy (Section 2.1; Appendix B energy table), and
+ *      the InfoNCE loss with the logsumexp penalty (Section 2.1 critic
+ *      objective; Appendix B InfoNCE-forward/backward/symmetric)
+ *                                                          -> crl_critic_fwd
+ *   3. the gradient of that loss w.r.t. every encoder parameter
+ *                                                          -> crl_critic_bwd
+ *   4. the optimiser step on the flat parameter vector     -> crl_adam_step
+ *
+ * Conventions shared by every call
+ *  - Pointers named "device" point to device memory on the current HIP device;
+ *    the caller owns every buffer (inputs, outputs, parameters, optimiser
+ *    state and the workspace).  The compute calls allocate nothing; only
+ *    crl_create allocates (a small device table) and crl_destroy frees it.
+ *  - All compute calls are asynchronous and ordered on the `stream` argument
+ *    (a hipStream_t passed as void*; NULL is the legacy default stream).  No
+ *    call synchronises with the host, so every call may be captured into a
+ *    HIP graph.
+ *  - Return value: CRL_OK (0) or a negative crl_status.  Arguments are checked
+ *    on the host before anything is launched: a bad argument launches nothing
+ *    and returns CRL_EINVAL / CRL_EUNSUPPORTED; a failed launch returns
+ *    CRL_EHIP.  crl_last_error() then holds a message (thread-local).
+ *  - Matrices are row-major.  BF16 values are stored as uint16 bit patterns
+ *    (round-to-nearest-even from FP32).
+ *
+ * Flat parameter layout (crl_param_count / crl_layer_layout): phi's layers
+ * first, then psi's; each layer holds W [fan_in][fan_out], b [fan_out] and,
+ * for LayerNorm layers, ln_g [fan_out] and ln_b [fan_out].  Every tensor
+ * starts at an element offset that is a multiple of 64; the gaps are padding
+ * whose gradient is written as 0.
+ */
+#ifndef CRL_H
+#define CRL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CRL_API __attribute__((visibility("default")))
+
+typedef enum {
+  CRL_OK = 0,
+  CRL_EINVAL = -1,        /* bad argument (null pointer, size, alignment) */
+  CRL_EUNSUPPORTED = -2,  /* valid but not supported by this build */
+  CRL_EHIP = -3           /* a HIP runtime call or launch failed */
+} crl_status;
+
+enum { CRL_ACT_RELU = 0, CRL_ACT_LN_SWISH = 1 };
+enum { CRL_ENERGY_DOT = 0, CRL_ENERGY_L2 = 1 };
+enum { CRL_LOSS_FWD = 0, CRL_LOSS_SYM = 1 };
+enum { CRL_PREC_FP32 = 0, CRL_PREC_BF16 = 1 };
+/* materialised: the B x B critic matrix is written to the workspace (FP32);
+ * fused: online log-sum-exp over tiles, the matrix never exists in memory. */
+enum { CRL_LOGITS_MATERIALISED = 0, CRL_LOGITS_FUSED = 1 };
+
+typedef struct crl_config {
+  int32_t batch;          /* B >= 1 */
+  int32_t obs_dim;        /* d_s: state features per buffer row */
+  int32_t act_dim;        /* d_a */
+  int32_t goal_dim;       /* d_g: goal = obs[goal_lo : goal_lo + d_g] */
+  int32_t goal_lo;
+  int32_t n_hidden;       /* hidden layers per encoder (>= 1) */
+  int32_t hidden;         /* hidden width (multiple of 8) */
+  int32_t repr_dim;       /* D, multiple of 8 (fused logits: 64 or 256) */
+  int32_t activation;     /* CRL_ACT_* : ReLU, or LayerNorm then Swish */
+  int32_t energy;         /* CRL_ENERGY_*: <phi,psi> or -||phi - psi||_2 */
+  int32_t loss;           /* CRL_LOSS_*: InfoNCE forward, or symmetric */
+  int32_t precision;      /* CRL_PREC_*: arithmetic of GEMM and logit tiles */
+  int32_t logits;         /* CRL_LOGITS_* */
+  float logsumexp_penalty;/* beta of beta * mean_i (LSE_j F_ij)^2 */
+  float ln_eps;           /* LayerNorm epsilon (added to the variance) */
+  double discount;        /* gamma in (0,1) of the relabel offset law */
+  int32_t max_episode_len;/* longest episode crl_sample_relabel will see */
+  int32_t reserved[7];    /* must be zero */
+} crl_config;
+
+typedef struct crl_ctx crl_ctx;
+
+typedef struct crl_layer_info {
+  int64_t w, b, ln_g, ln_b; /* element offsets in the flat vector, -1 if absent */
+  int32_t fan_in, fan_out;
+} crl_layer_info;
+
+/* Create a context on the current HIP device: validates the configuration,
+ * plans the workspace and uploads the geometric-offset threshold table for
+ * `discount` (see crl_sample_relabel).  On success *out owns that table. */
+CRL_API int crl_create(const crl_config* cfg, crl_ctx** out);
+CRL_API int crl_destroy(crl_ctx* ctx);
+
+/* Number of floats of the flat parameter (and gradient, Adam m, v) vector. */
+CRL_API int crl_param_count(const crl_ctx* ctx, int64_t* n);
+/* Offsets of layer `layer` (0 = first) of encoder 0 (phi) or 1 (psi). */
+CRL_API int crl_layer_layout(const crl_ctx* ctx, int32_t encoder, int32_t layer,
+                             crl_layer_info* out);
+/* Bytes of the device workspace that crl_critic_fwd / _bwd use (256-aligned). */
+CRL_API int crl_workspace_size(const crl_ctx* ctx, int64_t* bytes);
+/* Row strides (elements) of the encoder inputs x_sa [B][ld_sa], x_g [B][ld_g],
+ * x_sg [B][ld_sg], and their element size: 4 (FP32) or 2 (BF16).  Columns
+ * past the real width are zero. */
+CRL_API int crl_input_layout(const crl_ctx* ctx, int32_t* ld_sa, int32_t* ld_g,
+                             int32_t* ld_sg, int32_t* elem_bytes);
+
+/* Step 1: sample and relabel one batch (Section 2.2; Algorithm 1, batch
+ * sampling "with discount"; Preliminaries: the offset T ~ Geom(1 - gamma)).
+ *   obs    device FP32 [num_envs][episode_len][obs_dim], one episode per row
+ *   act    device FP32 [num_envs][episode_len][act_dim]
+ *   seed   Philox key word 0 (key = (seed, 0))
+ *   step   device int64: the batch counter n (read, not modified)
+ *   idx    device int32 [B][3] out: (e, t, t_g)
+ *   x_sa   device out [B][ld_sa]: [obs[e,t,:], act[e,t,:], 0...]
+ *   x_g    device out [B][ld_g]:  [obs[e,t_g,goal_lo:goal_lo+d_g], 0...]
+ *   x_sg   device out [B][ld_sg] or NULL: [obs[e,t,:], goal, 0...]
+ * For sample b, Philox4x64-10 with counter (b, n, 0, 0) gives words w0..w3:
+ *   e = floor(w0 * E / 2^64), t = floor(w1 * (T-1) / 2^64),
+ *   k = 1 + #{m >= 1 : w2 < thr[m]}, thr[1] = G = floor(gamma * 2^64),
+ *   thr[m] = floor(thr[m-1] * G / 2^64), and t_g = min(t + k, T - 1),
+ * so k is geometric on {1, 2, ...} with P(k) ~ (1-gamma) gamma^(k-1) and the
+ * goal is a strictly future state clipped to the episode end.
+ * Requires 2 <= episode_len <= cfg.max_episode_len, num_envs >= 1. */
+CRL_API int crl_sample_relabel(crl_ctx* ctx, const float* obs, const float* act,
+                               int32_t num_envs, int32_t episode_len,
+                               uint64_t seed, const int64_t* step, int32_t* idx,
+                               void* x_sa, void* x_g, void* x_sg, void* stream);
+
+/* Step 2: encoders, critic matrix and loss (Section 2.1 objective; Appendix B
+ * energies and InfoNCE variants; Algorithm 1 critic update with the
+ * logsumexp penalty).
+ *   params       device FP32 flat parameters (layout above)
+ *   params_bf16  device BF16 copy of params (same layout); required when
+ *                precision is BF16, ignored for FP32
+ *   x_sa, x_g    device inputs as written by crl_sample_relabel
+ *   ws           device workspace of crl_workspace_size bytes; keeps the
+ *                activations that crl_critic_bwd needs
+ *   loss_out     device FP32 [8] out: {total, L_fwd, L_bwd, L_pen,
+ *                mean_i r_i, mean_j c_j, #non-finite row/col terms, 0}
+ * with F_ij = <phi_i, psi_j> or -||phi_i - psi_j||, r_i = LSE_j F_ij,
+ * c_j = LSE_i F_ij, L_fwd = mean_i (r_i - F_ii), L_bwd = mean_j (c_j - F_jj),
+ * L_pen = beta * mean_i r_i^2 and total = L_fwd (+ L_bwd if symmetric) + L_pen. */
+CRL_API int crl_critic_fwd(crl_ctx* ctx, const float* params,
+                           const uint16_t* params_bf16, const void* x_sa,
+                           const void* x_g, void* ws, float* loss_out,
+                           void* stream);
+
+/* Step 3: gradient of loss_out[0] w.r.t. every parameter, written (not
+ * accumulated) into grads (device FP32, crl_param_count floats, padding set
+ * to 0), by the chain rule through the loss, the energy and both MLPs.  Uses
+ * the activations crl_critic_fwd left in ws, so it must follow a
+ * crl_critic_fwd with the same params, x_sa, x_g and ws on the same stream. */
+CRL_API int crl_critic_bwd(crl_ctx* ctx, const float* params,
+                           const uint16_t* params_bf16, const void* x_sa,
+                           const void* x_g, void* ws, float* grads,
+                           void* stream);
+
+/* Step 4: Adam (Kingma & Ba) on n floats, the optimiser read into the
+ * gradient steps of Algorithm 1:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+ * with t = *step (device int64, t >= 1, read only).  If p_bf16 is not NULL
+ * the BF16 copy of the new p is written there too.  p, g, m, v, p_bf16 must
+ * be 16-byte aligned. */
+CRL_API int crl_adam_step(float* p, const float* g, float* m, float* v,
+                          uint16_t* p_bf16, int64_t n, const int64_t* step,
+                          float lr, float b1, float b2, float eps, void* stream);
+
+/* *counter += inc on the device (stream-ordered; for step counters that a
+ * captured graph advances on every replay). */
+CRL_API int crl_counter_add(int64_t* counter, int64_t inc, void* stream);
+
+/* dst[i] = BF16(src[i]) (round to nearest even), n floats, device pointers. */
+CRL_API int crl_cast_bf16(const float* src, uint16_t* dst, int64_t n,
+                          void* stream);
+
+/* Location of intermediate results inside the workspace, for inspection:
+ * byte offset and size of the buffer `which` (CRL_WS_*).  FP32 unless noted. */
+enum {
+  CRL_WS_PHI = 0,     /* [B][D] phi(s, a) */
+  CRL_WS_PSI = 1,     /* [B][D] psi(g) */
+  CRL_WS_ROW_LSE = 2, /* [B] r_i */
+  CRL_WS_COL_LSE = 3, /* [B] c_j */
+  CRL_WS_DIAG = 4,    /* [B] F_ii */
+  CRL_WS_DPHI = 5,    /* [B][D] dL/dphi (after crl_critic_bwd) */
+  CRL_WS_DPSI = 6,    /* [B][D] dL/dpsi */
+  CRL_WS_LOGITS = 7   /* [B][ldF] F, ldF = B rounded up to a multiple of 8
+                         (materialised logits only) */
+};
+CRL_API int crl_workspace_view(const crl_ctx* ctx, int32_t which,
+                               int64_t* offset, int64_t* bytes);
+
+/* Message for the last non-OK status returned on this thread. */
+CRL_API const char* crl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CRL_H */

@@ -1,0 +1,209 @@
+"""Python binding of the CRL update library: argument marshalling only.
+
+Every step of the update runs in libcrl.so; this module turns torch tensors
+into device pointers and the current HIP stream, and calls the C ABI
+(include/crl.h) with the same names.  PyTorch supplies device memory and
+streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, List, Tuple
+
+import numpy as np
+import torch
+
+from ._lib import (ACT, ENERGY, LOGITS, LOSS, PREC, WS, check, crl_config,
+                   crl_layer_info, lib)
+
+
+def _ptr(t) -> C.c_void_p:
+    if t is None:
+        return C.c_void_p(None)
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_config(w, max_episode_len: int | None = None) -> crl_config:
+    """crl_config for a workload record (synthetic.Workload or alike)."""
+    hid = tuple(w.hidden)
+    if len(set(hid)) != 1:
+        raise ValueError("all hidden layers must have the same width")
+    c = crl_config()
+    c.batch = w.batch_size
+    c.obs_dim = w.obs_dim
+    c.act_dim = w.act_dim
+    c.goal_dim = w.goal_dim
+    c.goal_lo = w.goal_lo
+    c.n_hidden = len(hid)
+    c.hidden = hid[0]
+    c.repr_dim = w.repr_dim
+    c.activation = ACT[w.activation]
+    c.energy = ENERGY[w.energy_function]
+    c.loss = LOSS[w.contrastive_loss_function]
+    c.precision = PREC[w.precision]
+    c.logits = LOGITS[w.logits]
+    c.logsumexp_penalty = w.logsumexp_penalty
+    c.ln_eps = w.ln_eps
+    c.discount = w.discounting
+    c.max_episode_len = max_episode_len or w.episode_len
+    return c
+
+
+class Critic:
+    """One crl_ctx plus the layouts it defines."""
+
+    def __init__(self, w, max_episode_len: int | None = None):
+        self.w = w
+        self.cfg = make_config(w, max_episode_len)
+        self.ctx = C.c_void_p()
+        check(lib().crl_create(C.byref(self.cfg), C.byref(self.ctx)))
+        n = C.c_int64()
+        check(lib().crl_param_count(self.ctx, C.byref(n)))
+        self.nparam = n.value
+        ws = C.c_int64()
+        check(lib().crl_workspace_size(self.ctx, C.byref(ws)))
+        self.ws_bytes = ws.value
+        a, b, c, e = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().crl_input_layout(self.ctx, C.byref(a), C.byref(b), C.byref(c), C.byref(e)))
+        self.ld_sa, self.ld_g, self.ld_sg, self.elem_bytes = a.value, b.value, c.value, e.value
+        self.layers: List[List[crl_layer_info]] = []
+        for enc in range(2):
+            row = []
+            for l in range(self.cfg.n_hidden + 1):
+                info = crl_layer_info()
+                check(lib().crl_layer_layout(self.ctx, enc, l, C.byref(info)))
+                row.append(info)
+            self.layers.append(row)
+
+    def close(self):
+        if self.ctx:
+            lib().crl_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ layouts
+    @property
+    def act_dtype(self):
+        return torch.bfloat16 if self.elem_bytes == 2 else torch.float32
+
+    def pack(self, phi_layers, psi_layers) -> np.ndarray:
+        """Flat FP32 parameter vector (zero padding) from per-layer arrays."""
+        flat = np.zeros(self.nparam, np.float32)
+        for enc, layers in enumerate((phi_layers, psi_layers)):
+            for l, L in enumerate(layers):
+                info = self.layers[enc][l]
+                W = np.asarray(L["W"], np.float32)
+                assert W.shape == (info.fan_in, info.fan_out), (W.shape, info.fan_in, info.fan_out)
+                flat[info.w:info.w + W.size] = W.reshape(-1)
+                flat[info.b:info.b + info.fan_out] = L["b"]
+                if info.ln_g >= 0:
+                    flat[info.ln_g:info.ln_g + info.fan_out] = L["ln_g"]
+                    flat[info.ln_b:info.ln_b + info.fan_out] = L["ln_b"]
+        return flat
+
+    def unpack(self, flat) -> Tuple[list, list]:
+        """Per-layer dicts (numpy FP32) from a flat vector (params or grads)."""
+        flat = np.asarray(flat)
+        out = []
+        for enc in range(2):
+            layers = []
+            for info in self.layers[enc]:
+                L: Dict[str, np.ndarray] = {
+                    "W": flat[info.w:info.w + info.fan_in * info.fan_out].reshape(
+                        info.fan_in, info.fan_out),
+                    "b": flat[info.b:info.b + info.fan_out]}
+                if info.ln_g >= 0:
+                    L["ln_g"] = flat[info.ln_g:info.ln_g + info.fan_out]
+                    L["ln_b"] = flat[info.ln_b:info.ln_b + info.fan_out]
+                layers.append(L)
+            out.append(layers)
+        return out[0], out[1]
+
+    def inputs(self, device="cuda"):
+        """Empty x_sa, x_g, x_sg in the storage type and strides of this ctx."""
+        B = self.cfg.batch
+        dt = self.act_dtype
+        return (torch.zeros(B, self.ld_sa, dtype=dt, device=device),
+                torch.zeros(B, self.ld_g, dtype=dt, device=device),
+                torch.zeros(B, self.ld_sg, dtype=dt, device=device))
+
+    def workspace(self, device="cuda"):
+        return torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def view(self, ws: torch.Tensor, name: str) -> torch.Tensor:
+        off, nb = C.c_int64(), C.c_int64()
+        check(lib().crl_workspace_view(self.ctx, WS[name], C.byref(off), C.byref(nb)))
+        v = ws[off.value:off.value + nb.value].view(torch.float32)
+        B, D = self.cfg.batch, self.cfg.repr_dim
+        if name in ("phi", "psi", "dphi", "dpsi"):
+            return v.view(B, D)
+        if name == "logits":
+            ld = (B + 7) // 8 * 8
+            return v.view(B, ld)[:, :B]
+        return v
+
+    # ------------------------------------------------------------ entry points
+    def crl_sample_relabel(self, obs, act, seed: int, step, idx, x_sa, x_g, x_sg=None,
+                           stream=None):
+        E, T = obs.shape[0], obs.shape[1]
+        check(lib().crl_sample_relabel(self.ctx, _ptr(obs), _ptr(act), E, T, seed,
+                                       _ptr(step), _ptr(idx), _ptr(x_sa), _ptr(x_g),
+                                       _ptr(x_sg), _stream(stream)))
+
+    def crl_critic_fwd(self, params, params_bf16, x_sa, x_g, ws, loss_out, stream=None):
+        check(lib().crl_critic_fwd(self.ctx, _ptr(params), _ptr(params_bf16), _ptr(x_sa),
+                                   _ptr(x_g), _ptr(ws), _ptr(loss_out), _stream(stream)))
+
+    def crl_critic_bwd(self, params, params_bf16, x_sa, x_g, ws, grads, stream=None):
+        check(lib().crl_critic_bwd(self.ctx, _ptr(params), _ptr(params_bf16), _ptr(x_sa),
+                                   _ptr(x_g), _ptr(ws), _ptr(grads), _stream(stream)))
+
+
+def crl_adam_step(p, g, m, v, p_bf16, step, lr: float, b1: float = 0.9, b2: float = 0.999,
+                  eps: float = 1e-8, stream=None):
+    check(lib().crl_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(p_bf16), p.numel(),
+                              _ptr(step), lr, b1, b2, eps, _stream(stream)))
+
+
+def crl_counter_add(counter, inc: int = 1, stream=None):
+    check(lib().crl_counter_add(_ptr(counter), inc, _stream(stream)))
+
+
+def crl_cast_bf16(src, dst, stream=None):
+    check(lib().crl_cast_bf16(_ptr(src), _ptr(dst), src.numel(), _stream(stream)))
+
+
+class CriticLoss(torch.autograd.Function):
+    """loss = CriticLoss.apply(params, critic, params_bf16, x_sa, x_g, ws).
+
+    Forward runs crl_critic_fwd; backward runs crl_critic_bwd, which re-uses
+    the activations left in ``ws`` and returns d(loss)/d(params) as a flat
+    vector (padding entries are zero).
+    """
+
+    @staticmethod
+    def forward(ctx, params, critic: Critic, params_bf16, x_sa, x_g, ws):
+        loss = torch.empty(8, dtype=torch.float32, device=params.device)
+        critic.crl_critic_fwd(params, params_bf16, x_sa, x_g, ws, loss)
+        ctx.critic = critic
+        ctx.save_for_backward(params, params_bf16 if params_bf16 is not None else params,
+                              x_sa, x_g, ws)
+        ctx.has_bf16 = params_bf16 is not None
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        params, pb, x_sa, x_g, ws = ctx.saved_tensors
+        grads = torch.empty_like(params)
+        ctx.critic.crl_critic_bwd(params, pb if ctx.has_bf16 else None, x_sa, x_g, ws, grads)
+        return grads * grad_out, None, None, None, None, None

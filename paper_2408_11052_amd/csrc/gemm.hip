@@ -1,0 +1,84 @@
+// Instantiations and host dispatch of the MFMA GEMM.
+#include "internal.hpp"
+
+namespace crl {
+
+// Sum of split-K partials: C[m][n] (+)= sum_s partial[s][m][n] (FP32 out).
+__global__ void splitk_reduce_kernel(GemmParams P) {
+  const int g = blockIdx.y;
+  const GemmDesc& D = P.d[g];
+  const int64_t MN = (int64_t)D.M * D.N;
+  const float* src = P.partial + (int64_t)g * P.partial_len;
+  float* C = reinterpret_cast<float*>(D.C);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < MN;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int k = 0; k < P.splits; ++k) s += src[k * MN + i];
+    int64_t row = i / D.N, col = i % D.N;
+    int64_t o = row * D.ldc + col;
+    if (D.accumulate) s += C[o];
+    C[o] = s;
+  }
+}
+
+
+template <typename T, int LA, int LB, typename OutT>
+static hipError_t run(GemmParams& P, hipStream_t s) {
+  int maxt = 0;
+  for (int g = 0; g < P.count; ++g) maxt = P.tiles[g] > maxt ? P.tiles[g] : maxt;
+  if (maxt == 0) return hipSuccess;
+  dim3 grid(maxt, P.splits, P.count), block(kGemmThreads);
+  gemm_kernel<T, LA, LB, OutT><<<grid, block, 0, s>>>(P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || P.splits <= 1) return e;
+  int64_t mn = 0;
+  for (int g = 0; g < P.count; ++g) {
+    int64_t v = (int64_t)P.d[g].M * P.d[g].N;
+    mn = v > mn ? v : mn;
+  }
+  int64_t blocks = (mn + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  splitk_reduce_kernel<<<dim3((unsigned)blocks, P.count), 256, 0, s>>>(P);
+  return hipGetLastError();
+}
+
+template <typename T, typename OutT>
+static hipError_t run_layout(GemmParams& P, int la, int lb, hipStream_t s) {
+  if (la == LAY_KC && lb == LAY_KC) return run<T, LAY_KC, LAY_KC, OutT>(P, s);
+  if (la == LAY_KC && lb == LAY_MC) return run<T, LAY_KC, LAY_MC, OutT>(P, s);
+  if (la == LAY_MC && lb == LAY_KC) return run<T, LAY_MC, LAY_KC, OutT>(P, s);
+  return run<T, LAY_MC, LAY_MC, OutT>(P, s);
+}
+
+void plan_split_k(GemmParams& P, bool bf16, int target_wgs) {
+  const int BK = bf16 ? GemmCfg<bf16_t>::BK : GemmCfg<float>::BK;
+  int tiles = 0, kmax = 0;
+  for (int g = 0; g < P.count; ++g) {
+    P.tiles_n[g] = (P.d[g].N + kBN - 1) / kBN;
+    P.tiles[g] = ((P.d[g].M + kBM - 1) / kBM) * P.tiles_n[g];
+    tiles += P.tiles[g];
+    kmax = P.d[g].K > kmax ? P.d[g].K : kmax;
+  }
+  int splits = 1;
+  if (tiles > 0 && P.partial != nullptr) {
+    // at least 4 K steps per split
+    int max_splits = kmax / (4 * BK);
+    while (splits * 2 <= max_splits && tiles * splits * 2 <= target_wgs) splits *= 2;
+  }
+  int kc = (kmax + splits - 1) / splits;
+  kc = (kc + BK - 1) / BK * BK;
+  if (kc == 0) kc = BK;
+  P.splits = splits;
+  P.k_chunk = kc;
+}
+
+hipError_t launch_gemm(GemmParams& P, bool bf16, int la, int lb, bool out_bf16, hipStream_t s) {
+  if (bf16) {
+    if (out_bf16) return run_layout<bf16_t, bf16_t>(P, la, lb, s);
+    return run_layout<bf16_t, float>(P, la, lb, s);
+  }
+  if (out_bf16) return run_layout<float, bf16_t>(P, la, lb, s);
+  return run_layout<float, float>(P, la, lb, s);
+}
+
+}  // namespace crl

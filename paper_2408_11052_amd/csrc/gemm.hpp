@@ -1,0 +1,325 @@
+// MFMA GEMM for the encoder layers and the logit products (gfx950).
+//
+// C[M][N] = epilogue(alpha * A[M][K] . B[K][N]) for up to two independent
+// problems per launch (the phi and psi encoders run side by side).
+//
+// Operands are either "KC" (the contraction index is contiguous:
+// A(m,k) = A[m*lda + k], B(k,n) = B[n*ldb + k]) or "MC" (the row/column index
+// is contiguous: A(m,k) = A[k*lda + m], B(k,n) = B[k*ldb + n]).  Tiles are
+// staged through LDS in one layout, [row][k] with a 16-byte pad, so that every
+// MFMA operand fragment is one 16-byte LDS read; MC operands are transposed on
+// the way in (4 k-rows per thread, repacked in registers).
+//
+// Tile: 128 x 128 per workgroup of 256 threads (4 waves, 2 x 2), 64 x 64 per
+// wave as 4 x 4 MFMA 16x16 blocks.  K step: 128 bytes of each row per stage
+// (64 BF16 or 32 FP32), double-buffered in LDS with one barrier per stage.
+//   BF16: v_mfma_f32_16x16x32_bf16, FP32 accumulation.
+//   FP32: v_mfma_f32_16x16x4_f32.
+#pragma once
+
+#include "common.hpp"
+
+namespace crl {
+
+enum : int { LAY_KC = 0, LAY_MC = 1 };
+enum : int {
+  EPI_NONE = 0,      // v
+  EPI_BIAS = 1,      // v + bias[n]
+  EPI_BIAS_RELU = 2, // max(v + bias[n], 0)
+  EPI_MASK_POS = 3,  // aux(m,n) > 0 ? v : 0      (ReLU backward)
+  EPI_L2 = 4         // -sqrt(max(rowv[m] + colv[n] - 2 v, 0))
+};
+
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  const float* bias;
+  const void* aux;    // same storage type and leading dim as C
+  const float* rowv;
+  const float* colv;
+  int M, N, K;
+  int lda, ldb, ldc;
+  int epi;
+  float alpha;
+  int accumulate;     // C += result (read-modify-write of C)
+};
+
+constexpr int kGemmMaxGroup = 2;
+constexpr int kBM = 128, kBN = 128, kGemmThreads = 256;
+
+struct GemmParams {
+  GemmDesc d[kGemmMaxGroup];
+  int count;
+  int tiles_n[kGemmMaxGroup];
+  int tiles[kGemmMaxGroup];
+  int splits;          // split-K factor (>= 1)
+  int k_chunk;         // K range per split (multiple of the K step)
+  float* partial;      // splits > 1: partial[g][s][M][N] (FP32, no epilogue)
+  int64_t partial_len; // floats per problem in `partial`
+};
+
+template <typename T> struct GemmCfg;
+template <> struct GemmCfg<bf16_t> { static constexpr int BK = 64, VEC = 8; };
+template <> struct GemmCfg<float> { static constexpr int BK = 32, VEC = 4; };
+
+// ---------------------------------------------------------------------------
+// global -> register staging
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline uint4 load_vec_guarded(const T* base, int64_t off, int valid) {
+  // `valid` = number of in-range elements of the VEC-wide vector at base+off
+  constexpr int VEC = GemmCfg<T>::VEC;
+  if (valid >= VEC) return *reinterpret_cast<const uint4*>(base + off);
+  uint4 r = {0u, 0u, 0u, 0u};
+  if (valid > 0) {
+    T tmp[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) tmp[i] = (i < valid) ? base[off + i] : T(0);
+    __builtin_memcpy(&r, tmp, 16);
+  }
+  return r;
+}
+
+// KC operand tile: rows [r0, r0+128), k [k0, k0+BK).  4 vectors per thread.
+template <typename T>
+__device__ inline void load_kc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
+                               int r0, int R, int k0, int kend, int tid) {
+  constexpr int VEC = GemmCfg<T>::VEC;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int v = tid + i * kGemmThreads;
+    int row = v >> 3, c = v & 7;
+    int gr = r0 + row, gk = k0 + c * VEC;
+    int valid = (gr < R) ? min(VEC, kend - gk) : 0;
+    reg[i] = load_vec_guarded<T>(X, (int64_t)gr * ld + gk, valid);
+  }
+}
+
+// MC operand tile: k-rows [k0, k0+BK), row/col index [r0, r0+128).
+// Thread (q, mv) loads k-rows 4q..4q+3 at columns mv*VEC..+VEC.
+template <typename T>
+__device__ inline void load_mc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
+                               int r0, int R, int k0, int kend, int tid) {
+  constexpr int BK = GemmCfg<T>::BK, VEC = GemmCfg<T>::VEC;
+  constexpr int QN = BK / 4;
+  int q = tid % QN, mv = tid / QN;
+  int gm = r0 + mv * VEC;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int gk = k0 + 4 * q + j;
+    int valid = (gk < kend) ? min(VEC, R - gm) : 0;
+    reg[j] = load_vec_guarded<T>(X, (int64_t)gk * ld + gm, valid);
+  }
+}
+
+// LDS row stride in elements: 128 data bytes + 16 pad bytes.
+template <typename T> constexpr int lds_ld() { return (128 + 16) / (int)sizeof(T); }
+
+template <typename T>
+__device__ inline void store_kc(T* __restrict__ S, const uint4 (&reg)[4], int tid) {
+  constexpr int VEC = GemmCfg<T>::VEC, LD = lds_ld<T>();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int v = tid + i * kGemmThreads;
+    int row = v >> 3, c = v & 7;
+    *reinterpret_cast<uint4*>(S + row * LD + c * VEC) = reg[i];
+  }
+}
+
+__device__ inline void store_mc(bf16_t* __restrict__ S, const uint4 (&reg)[4], int tid) {
+  constexpr int LD = lds_ld<bf16_t>();
+  constexpr int QN = GemmCfg<bf16_t>::BK / 4;  // 16
+  int q = tid % QN, mv = tid / QN;
+  const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&reg[0]);
+  const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&reg[1]);
+  const uint32_t* w2 = reinterpret_cast<const uint32_t*>(&reg[2]);
+  const uint32_t* w3 = reinterpret_cast<const uint32_t*>(&reg[3]);
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    // elements 2d (low halves) and 2d+1 (high halves) of each k-row
+    uint2 lo, hi;
+    lo.x = (w0[d] & 0xffffu) | (w1[d] << 16);
+    lo.y = (w2[d] & 0xffffu) | (w3[d] << 16);
+    hi.x = (w0[d] >> 16) | (w1[d] & 0xffff0000u);
+    hi.y = (w2[d] >> 16) | (w3[d] & 0xffff0000u);
+    int m = mv * 8 + 2 * d;
+    *reinterpret_cast<uint2*>(S + m * LD + 4 * q) = lo;
+    *reinterpret_cast<uint2*>(S + (m + 1) * LD + 4 * q) = hi;
+  }
+}
+
+__device__ inline void store_mc(float* __restrict__ S, const uint4 (&reg)[4], int tid) {
+  constexpr int LD = lds_ld<float>();
+  constexpr int QN = GemmCfg<float>::BK / 4;  // 8
+  int q = tid % QN, mv = tid / QN;
+  const float* r0 = reinterpret_cast<const float*>(&reg[0]);
+  const float* r1 = reinterpret_cast<const float*>(&reg[1]);
+  const float* r2 = reinterpret_cast<const float*>(&reg[2]);
+  const float* r3 = reinterpret_cast<const float*>(&reg[3]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float4 v = make_float4(r0[i], r1[i], r2[i], r3[i]);
+    *reinterpret_cast<float4*>(S + (mv * 4 + i) * LD + 4 * q) = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA inner product over one LDS stage
+// ---------------------------------------------------------------------------
+__device__ inline void mma_stage(floatx4 (&acc)[4][4], const bf16_t* __restrict__ As,
+                                 const bf16_t* __restrict__ Bs, int wm, int wn, int lane) {
+  constexpr int LD = lds_ld<bf16_t>();
+  int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(As + (wm * 64 + i * 16 + r16) * LD + g * 16 + h * 8);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(Bs + (wn * 64 + j * 16 + r16) * LD + g * 16 + h * 8);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+__device__ inline void mma_stage(floatx4 (&acc)[4][4], const float* __restrict__ As,
+                                 const float* __restrict__ Bs, int wm, int wn, int lane) {
+  constexpr int LD = lds_ld<float>();
+  int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float4 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a[i] = *reinterpret_cast<const float4*>(As + (wm * 64 + i * 16 + r16) * LD + g * 8 + h * 4);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      b[j] = *reinterpret_cast<const float4*>(Bs + (wn * 64 + j * 16 + r16) * LD + g * 8 + h * 4);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].x, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, b[j].y, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].z, b[j].z, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].w, b[j].w, acc[i][j], 0, 0, 0);
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the kernel
+// ---------------------------------------------------------------------------
+template <typename T, int LA, int LB, typename OutT>
+__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmParams P) {
+  constexpr int BK = GemmCfg<T>::BK;
+  constexpr int LD = lds_ld<T>();
+  constexpr int STAGE = (kBM + kBN) * LD;
+  __shared__ __attribute__((aligned(16))) T smem[2 * STAGE];
+
+  const int g = blockIdx.z;
+  const GemmDesc& D = P.d[g];
+  const int ntile = P.tiles[g];
+  int pid = blockIdx.x;
+  if (pid >= ntile) return;
+  // XCD-aware order: consecutive workgroup ids go round-robin over the 8
+  // XCDs; give each XCD a contiguous run of tiles so its L2 sees few panels.
+  if ((ntile & 7) == 0 && gridDim.x == (unsigned)ntile) pid = (pid & 7) * (ntile >> 3) + (pid >> 3);
+  const int tm = pid / P.tiles_n[g], tn = pid % P.tiles_n[g];
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int kbeg = blockIdx.y * P.k_chunk;
+  const int kend = min(D.K, kbeg + P.k_chunk);
+
+  const T* __restrict__ A = reinterpret_cast<const T*>(D.A);
+  const T* __restrict__ B = reinterpret_cast<const T*>(D.B);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  uint4 ra[4], rb[4];
+  auto gload = [&](int k0) {
+    if (LA == LAY_KC) load_kc<T>(ra, A, D.lda, m0, D.M, k0, kend, tid);
+    else              load_mc<T>(ra, A, D.lda, m0, D.M, k0, kend, tid);
+    if (LB == LAY_KC) load_kc<T>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
+    else              load_mc<T>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
+  };
+  auto sstore = [&](int buf) {
+    T* As = smem + buf * STAGE;
+    T* Bs = As + kBM * LD;
+    if (LA == LAY_KC) store_kc<T>(As, ra, tid); else store_mc(As, ra, tid);
+    if (LB == LAY_KC) store_kc<T>(Bs, rb, tid); else store_mc(Bs, rb, tid);
+  };
+
+  const int nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+      const T* As = smem + cur * STAGE;
+      mma_stage(acc, As, As + kBM * LD, wm, wn, lane);
+      if (kt + 1 < nk) sstore(cur ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 block
+  const int r16 = lane & 15, gq = lane >> 4;
+  if (P.splits > 1) {
+    float* out = P.partial + (int64_t)g * P.partial_len + (int64_t)blockIdx.y * D.M * D.N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int col = n0 + wn * 64 + j * 16 + r16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int row = m0 + wm * 64 + i * 16 + gq * 4 + r;
+          if (row < D.M && col < D.N) out[(int64_t)row * D.N + col] = acc[i][j][r];
+        }
+      }
+    return;
+  }
+  OutT* __restrict__ C = reinterpret_cast<OutT*>(D.C);
+  const OutT* __restrict__ aux = reinterpret_cast<const OutT*>(D.aux);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int col = n0 + wn * 64 + j * 16 + r16;
+      if (col >= D.N) continue;
+      float bcol = (D.epi == EPI_BIAS || D.epi == EPI_BIAS_RELU) ? D.bias[col] : 0.f;
+      float ccol = (D.epi == EPI_L2) ? D.colv[col] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = m0 + wm * 64 + i * 16 + gq * 4 + r;
+        if (row >= D.M) continue;
+        int64_t o = (int64_t)row * D.ldc + col;
+        float v = acc[i][j][r] * D.alpha;
+        switch (D.epi) {
+          case EPI_BIAS: v += bcol; break;
+          case EPI_BIAS_RELU: v = fmaxf(v + bcol, 0.f); break;
+          case EPI_MASK_POS: v = (Store<OutT>::to_f(aux[o]) > 0.f) ? v : 0.f; break;
+          case EPI_L2: v = -sqrtf(fmaxf(D.rowv[row] + ccol - 2.f * v, 0.f)); break;
+          default: break;
+        }
+        if (D.accumulate) v += Store<OutT>::to_f(C[o]);
+        C[o] = Store<OutT>::from_f(v);
+      }
+    }
+}
+
+}  // namespace crl

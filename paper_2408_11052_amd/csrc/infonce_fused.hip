@@ -1,0 +1,408 @@
+// Fused InfoNCE over the B x B critic matrix without storing it.
+//
+// Forward: each workgroup owns 64 rows of phi (4 wavefronts x 16 rows, held
+// in registers as MFMA A fragments) and one split of the columns.  For every
+// 64-column tile of psi (staged in LDS) it forms the tile F = phi . psi^T with
+// v_mfma_f32_16x16x32_bf16, applies the energy, and keeps
+//   - per row: an online (max, sum exp) pair over its columns,
+//   - per column: the (max, sum exp) over the workgroup's 64 rows,
+//   - the diagonal F_ii.
+// Row pairs of all splits and column pairs of all row blocks are merged by
+// lse_merge_kernel; the loss is then a reduction over r, c and the diagonal.
+//
+// Backward: G_ij = dL/dF_ij = (1/B)[(Pr_ij - d_ij)(...)] is recomputed tile by
+// tile from r and c (never stored) and multiplied into the streamed operand
+// with a second MFMA:  dphi = G psi  (row pass)  and  dpsi = G^T phi (column
+// pass, the same kernel with the roles of phi and psi exchanged).  For the L2
+// energy H = G / d replaces G and the row sums of H give the
+// -(sum_j H_ij) phi_i term.  Each split writes its own partial, summed in a
+// fixed order afterwards (no atomics).
+#include "internal.hpp"
+
+namespace crl {
+
+constexpr int kFRows = 64;   // rows per workgroup
+constexpr int kFCols = 64;   // columns per tile
+
+int fused_splits(int B) {
+  int nrb = (B + kFRows - 1) / kFRows;
+  int S = 512 / nrb;
+  if (S < 1) S = 1;
+  if (S > 8) S = 8;
+  int cps = (B + S - 1) / S;
+  cps = (cps + kFCols - 1) / kFCols * kFCols;
+  return (B + cps - 1) / cps;
+}
+static inline int cols_per_split(int B, int S) {
+  int cps = (B + S - 1) / S;
+  return (cps + kFCols - 1) / kFCols * kFCols;
+}
+
+// BF16 copies of phi, psi and the squared norms of the rounded rows.
+__global__ void fused_prep_kernel(FusedArgs a, int B, int D) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int which = blockIdx.y;
+  if (row >= B) return;
+  const float* X = which ? a.psi : a.phi;
+  bf16_t* Xb = which ? a.psi_b : a.phi_b;
+  float* nrm = which ? a.npsi : a.nphi;
+  float s = 0.f;
+  for (int d = lane; d < D; d += 64) {
+    bf16_t h = f2bf(X[(int64_t)row * D + d]);
+    Xb[(int64_t)row * D + d] = h;
+    float v = bf2f(h);
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if (lane == 0) nrm[row] = s;
+}
+
+// Stage a 64-row tile of Y [B][D] (BF16) into LDS rows [64][LDY]; rows past B are 0.
+template <int D, int LDY>
+__device__ inline void stage_rows(bf16_t* __restrict__ Ys, const bf16_t* __restrict__ Y, int j0,
+                                  int B, int tid) {
+  constexpr int VPR = D / 8;  // 16-byte vectors per row
+  for (int v = tid; v < kFCols * VPR; v += 256) {
+    int r = v / VPR, c = v % VPR;
+    uint4 val = {0u, 0u, 0u, 0u};
+    if (j0 + r < B) val = *reinterpret_cast<const uint4*>(Y + (int64_t)(j0 + r) * D + c * 8);
+    *reinterpret_cast<uint4*>(Ys + r * LDY + c * 8) = val;
+  }
+}
+
+template <int KS, int L2>
+__global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, int cps) {
+  constexpr int D = KS * 32;
+  constexpr int LDY = D + 8;
+  __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDY];
+  __shared__ float cm_s[4][kFCols], cs_s[4][kFCols];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int rb = blockIdx.x;
+  const int row_base = rb * kFRows + wave * 16;
+  const int c0 = blockIdx.y * cps, c1 = min(B, c0 + cps);
+
+  bf16x8 xa[KS];
+  {
+    const int row = row_base + r16;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (row < B) xa[ks] = *reinterpret_cast<const bf16x8*>(a.phi_b + (int64_t)row * D + ks * 32 + g * 8);
+      else xa[ks] = bf16x8{};
+    }
+  }
+  float nx[4], rm[4], rsum[4];
+  bool rvalid[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int row = row_base + 4 * g + r;
+    rvalid[r] = row < B;
+    nx[r] = (L2 && rvalid[r]) ? a.nphi[row] : 0.f;
+    rm[r] = -INFINITY;
+    rsum[r] = 0.f;
+  }
+
+  for (int j0 = c0; j0 < c1; j0 += kFCols) {
+    __syncthreads();
+    stage_rows<D, LDY>(Ys, a.psi_b, j0, B, tid);
+    __syncthreads();
+    floatx4 acc[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      acc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        bf16x8 b = *reinterpret_cast<const bf16x8*>(Ys + (jb * 16 + r16) * LDY + ks * 32 + g * 8);
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b, acc[jb], 0, 0, 0);
+      }
+    }
+    // energies; invalid rows/columns become -inf
+    float f[4][4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      const int col = j0 + jb * 16 + r16;
+      const bool cv = col < c1;
+      const float ny = (L2 && cv) ? a.npsi[col] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = acc[jb][r];
+        if (L2) v = -sqrtf(fmaxf(nx[r] + ny - 2.f * v, 0.f));
+        f[jb][r] = (cv && rvalid[r]) ? v : -INFINITY;
+        const int row = row_base + 4 * g + r;
+        if (cv && rvalid[r] && row == col) a.diag[row] = v;
+      }
+    }
+    // rows: online (max, sum)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float ml = fmaxf(fmaxf(f[0][r], f[1][r]), fmaxf(f[2][r], f[3][r]));
+      if (ml > rm[r]) {
+        rsum[r] = (rm[r] == -INFINITY) ? 0.f : rsum[r] * __expf(rm[r] - ml);
+        rm[r] = ml;
+      }
+      if (rm[r] != -INFINITY) {
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) rsum[r] += __expf(f[jb][r] - rm[r]);
+      }
+    }
+    // columns: (max, sum) over this wave's 16 rows, then over the 4 waves
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      float cm = fmaxf(fmaxf(f[jb][0], f[jb][1]), fmaxf(f[jb][2], f[jb][3]));
+      float cs = 0.f;
+      if (cm != -INFINITY) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cs += __expf(f[jb][r] - cm);
+      }
+#pragma unroll
+      for (int o = 16; o <= 32; o <<= 1) {
+        float m2 = __shfl_xor(cm, o, 64), s2 = __shfl_xor(cs, o, 64);
+        lse_merge(cm, cs, m2, s2);
+      }
+      if (g == 0) { cm_s[wave][jb * 16 + r16] = cm; cs_s[wave][jb * 16 + r16] = cs; }
+    }
+    __syncthreads();
+    if (tid < kFCols && j0 + tid < c1) {
+      float cm = cm_s[0][tid], cs = cs_s[0][tid];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) lse_merge(cm, cs, cm_s[w][tid], cs_s[w][tid]);
+      a.col_m[(int64_t)rb * B + j0 + tid] = cm;
+      a.col_s[(int64_t)rb * B + j0 + tid] = cs;
+    }
+  }
+  // merge the row states across the 16 lanes that share each row
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float m = rm[r], s = rsum[r];
+#pragma unroll
+    for (int o = 1; o <= 8; o <<= 1) {
+      float m2 = __shfl_xor(m, o, 64), s2 = __shfl_xor(s, o, 64);
+      lse_merge(m, s, m2, s2);
+    }
+    const int row = row_base + 4 * g + r;
+    if (r16 == 0 && row < B) {
+      a.row_m[(int64_t)blockIdx.y * B + row] = m;
+      a.row_s[(int64_t)blockIdx.y * B + row] = s;
+    }
+  }
+}
+
+// TRANS = 0: rows are phi, streamed operand psi -> partials of dphi.
+// TRANS = 1: rows are psi, streamed operand phi -> partials of dpsi.
+template <int KS, int L2, int TRANS>
+__global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, int cps,
+                                                          float beta, int symmetric) {
+  constexpr int D = KS * 32;
+  constexpr int LDY = D + 8;
+  constexpr int LDT = kFCols + 8;
+  constexpr int NB = D / 16;  // 16-wide output blocks of dX
+  __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDY];
+  __shared__ __attribute__((aligned(16))) bf16_t YsT[D * LDT];
+  __shared__ __attribute__((aligned(16))) bf16_t Gs[4][16 * LDT];
+
+  const bf16_t* Xb = TRANS ? a.psi_b : a.phi_b;
+  const bf16_t* Yb = TRANS ? a.phi_b : a.psi_b;
+  const float* nX = TRANS ? a.npsi : a.nphi;
+  const float* nY = TRANS ? a.nphi : a.npsi;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int rb = blockIdx.x;
+  const int row_base = rb * kFRows + wave * 16;
+  const int c0 = blockIdx.y * cps, c1 = min(B, c0 + cps);
+  const float inv = 1.f / (float)B;
+
+  bf16x8 xa[KS];
+  {
+    const int row = row_base + r16;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (row < B) xa[ks] = *reinterpret_cast<const bf16x8*>(Xb + (int64_t)row * D + ks * 32 + g * 8);
+      else xa[ks] = bf16x8{};
+    }
+  }
+  float nx[4], lse_a[4], pen_a[4], hsum[4];
+  bool rvalid[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = row_base + 4 * g + r;
+    rvalid[r] = row < B;
+    nx[r] = (L2 && rvalid[r]) ? nX[row] : 0.f;
+    // TRANS=0: the row owns r_i (and the penalty); TRANS=1: the row owns c_j
+    lse_a[r] = rvalid[r] ? (TRANS ? a.c[row] : a.r[row]) : 0.f;
+    pen_a[r] = rvalid[r] ? (TRANS ? 0.f : 2.f * beta * a.r[row]) : 0.f;
+    hsum[r] = 0.f;
+  }
+  floatx4 acc_dx[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc_dx[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int j0 = c0; j0 < c1; j0 += kFCols) {
+    __syncthreads();
+    stage_rows<D, LDY>(Ys, Yb, j0, B, tid);
+    // transposed copy YsT[d][j]
+    for (int v = tid; v < kFCols * (D / 8); v += 256) {
+      int r = v / (D / 8), c = v % (D / 8);
+      uint4 val = {0u, 0u, 0u, 0u};
+      if (j0 + r < B) val = *reinterpret_cast<const uint4*>(Yb + (int64_t)(j0 + r) * D + c * 8);
+      const bf16_t* e = reinterpret_cast<const bf16_t*>(&val);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) YsT[(c * 8 + i) * LDT + r] = e[i];
+    }
+    __syncthreads();
+    floatx4 acc[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      acc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        bf16x8 b = *reinterpret_cast<const bf16x8*>(Ys + (jb * 16 + r16) * LDY + ks * 32 + g * 8);
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b, acc[jb], 0, 0, 0);
+      }
+    }
+    // G (or H = G/d for L2) for this tile, written to the wave's LDS strip
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      const int col = j0 + jb * 16 + r16;
+      const bool cv = col < c1;
+      const float ny = (L2 && cv) ? nY[col] : 0.f;
+      // TRANS=0: the column owns c_j; TRANS=1: the column owns r_i (+ penalty)
+      const float lse_b = cv ? (TRANS ? a.r[col] : a.c[col]) : 0.f;
+      const float pen_b = (cv && TRANS) ? 2.f * beta * a.r[col] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_base + 4 * g + r;
+        float v = acc[jb][r];
+        float d = 0.f;
+        if (L2) { d = sqrtf(fmaxf(nx[r] + ny - 2.f * v, 0.f)); v = -d; }
+        float gv = 0.f;
+        if (cv && rvalid[r]) {
+          const float dl = (row == col) ? 1.f : 0.f;
+          // rows-side and columns-side softmax terms
+          const float pa = __expf(v - lse_a[r]);
+          const float pb = __expf(v - lse_b);
+          if (TRANS == 0) {
+            gv = pa * (1.f + pen_a[r]) - dl;
+            if (symmetric) gv += pb - dl;
+          } else {
+            gv = pb * (1.f + pen_b) - dl;
+            if (symmetric) gv += pa - dl;
+          }
+          gv *= inv;
+          if (L2) gv = d > 0.f ? gv / d : 0.f;
+        }
+        hsum[r] += gv;
+        Gs[wave][(4 * g + r) * LDT + jb * 16 + r16] = f2bf(gv);
+      }
+    }
+    __syncthreads();
+    // dX[16 rows][D] += G[16][64] . Y[64][D]
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      bf16x8 ga = *reinterpret_cast<const bf16x8*>(&Gs[wave][r16 * LDT + kk * 32 + g * 8]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        bf16x8 yb = *reinterpret_cast<const bf16x8*>(YsT + (nb * 16 + r16) * LDT + kk * 32 + g * 8);
+        acc_dx[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, yb, acc_dx[nb], 0, 0, 0);
+      }
+    }
+  }
+  // write this split's partials
+  float* dst = a.dX_part + (int64_t)blockIdx.y * B * D;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row_base + 4 * g + r;
+      if (row < B) dst[(int64_t)row * D + nb * 16 + r16] = acc_dx[nb][r];
+    }
+  if (L2) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float s = hsum[r];
+#pragma unroll
+      for (int o = 1; o <= 8; o <<= 1) s += __shfl_xor(s, o, 64);
+      const int row = row_base + 4 * g + r;
+      if (r16 == 0 && row < B) a.rs_part[(int64_t)blockIdx.y * B + row] = s;
+    }
+  }
+}
+
+// dX = sum_s part[s] (- (sum_s rs[s]) * X_bf16 for L2), FP32 and storage copy.
+template <typename OutT>
+__global__ void bwd_reduce_kernel(const float* __restrict__ part, const float* __restrict__ rs,
+                                  const bf16_t* __restrict__ Xb, int S, int B, int D, int l2,
+                                  float* __restrict__ out, OutT* __restrict__ out_t) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)B * D;
+  if (k >= n) return;
+  float s = 0.f;
+  for (int i = 0; i < S; ++i) s += part[i * n + k];
+  if (l2) {
+    const int64_t row = k / D;
+    float h = 0.f;
+    for (int i = 0; i < S; ++i) h += rs[(int64_t)i * B + row];
+    s -= h * bf2f(Xb[k]);
+  }
+  out[k] = s;
+  out_t[k] = Store<OutT>::from_f(s);
+}
+
+#define CRL_FUSED_DISPATCH(KS_, BODY)                      \
+  switch (D) {                                              \
+    case 32:  { constexpr int KS_ = 1; BODY; } break;      \
+    case 64:  { constexpr int KS_ = 2; BODY; } break;      \
+    case 128: { constexpr int KS_ = 4; BODY; } break;      \
+    case 256: { constexpr int KS_ = 8; BODY; } break;      \
+    default: return hipErrorInvalidValue;                   \
+  }
+
+hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, hipStream_t s) {
+  fused_prep_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, B, D);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int S = fused_splits(B), cps = cols_per_split(B, S);
+  const int nrb = (B + kFRows - 1) / kFRows;
+  dim3 grid(nrb, S);
+  if (l2) { CRL_FUSED_DISPATCH(KS, (infonce_fwd_kernel<KS, 1><<<grid, 256, 0, s>>>(a, B, cps))) }
+  else    { CRL_FUSED_DISPATCH(KS, (infonce_fwd_kernel<KS, 0><<<grid, 256, 0, s>>>(a, B, cps))) }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_lse_merge(a.row_m, a.row_s, S, B, a.r, s);
+  if (e != hipSuccess) return e;
+  return launch_lse_merge(a.col_m, a.col_s, nrb, B, a.c, s);
+}
+
+hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmetric,
+                            float beta, bool out_bf16, hipStream_t s) {
+  const int S = fused_splits(B), cps = cols_per_split(B, S);
+  const int nrb = (B + kFRows - 1) / kFRows;
+  dim3 grid(nrb, S);
+  const int64_t n = (int64_t)B * D;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 0) {
+      if (l2) { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 1, 0><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
+      else    { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 0, 0><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
+    } else {
+      if (l2) { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 1, 1><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
+      else    { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 0, 1><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const bf16_t* Xb = pass ? a.psi_b : a.phi_b;
+    float* out = pass ? a.dpsi : a.dphi;
+    void* out_t = pass ? a.dpsi_t : a.dphi_t;
+    const int blocks = (int)((n + 255) / 256);
+    if (out_bf16)
+      bwd_reduce_kernel<bf16_t><<<blocks, 256, 0, s>>>(a.dX_part, a.rs_part, Xb, S, B, D, l2, out, (bf16_t*)out_t);
+    else
+      bwd_reduce_kernel<float><<<blocks, 256, 0, s>>>(a.dX_part, a.rs_part, Xb, S, B, D, l2, out, (float*)out_t);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace crl

@@ -1,0 +1,107 @@
+// Internal launch wrappers shared by the C-ABI layer (not part of the ABI).
+#pragma once
+
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace crl {
+
+// gemm.hip: dispatch on storage type / operand layouts / output type.
+hipError_t launch_gemm(GemmParams& P, bool bf16, int la, int lb, bool out_bf16,
+                       hipStream_t s);
+// Split factor and chunk for a batch of problems (fills P.splits, P.k_chunk).
+void plan_split_k(GemmParams& P, bool bf16, int target_wgs);
+
+// kernels.hip
+hipError_t launch_relabel(const float* obs, const float* act, int E, int T,
+                          int d_s, int d_a, int d_g, int goal_lo, uint64_t seed,
+                          const int64_t* step, const uint64_t* thr, int B,
+                          int32_t* idx, void* x_sa, int ld_sa, void* x_g, int ld_g,
+                          void* x_sg, int ld_sg, bool bf16, hipStream_t s);
+
+struct LnArgs {
+  const void* Z[2];     // [B][N] pre-LN values
+  void* H[2];           // [B][N] Swish(LN(z)) out
+  float* mu[2];
+  float* rstd[2];
+  const float* g[2];    // LN scale
+  const float* b[2];    // LN offset
+  // backward
+  const void* dH[2];
+  void* dZ[2];
+  float* part[2];       // [nwaves][3][N] column partials
+};
+hipError_t launch_ln_swish_fwd(const LnArgs& a, int count, int B, int N, float eps,
+                               bool bf16, hipStream_t s);
+hipError_t launch_ln_swish_bwd(const LnArgs& a, int count, int B, int N, bool bf16,
+                               int rows_per_wave, hipStream_t s);
+int ln_bwd_partials(int B, int rows_per_wave);
+
+// out[k][n] = sum_w part[w][k][n] for k < nk; the three sums go to out0/1/2.
+struct ColReduceArgs {
+  const float* part[2];
+  float* out[2][3];
+};
+hipError_t launch_partial_reduce(const ColReduceArgs& a, int count, int nparts, int nk,
+                                 int N, hipStream_t s);
+
+// column sums of X [B][N] (FP32 or BF16), written to out[N] (FP32).
+struct ColSumArgs {
+  const void* X[2];
+  float* out[2];
+  float* part[2];   // [ceil(B/64)][N]
+};
+hipError_t launch_colsum(const ColSumArgs& a, int count, int B, int N, int ld,
+                         bool bf16, hipStream_t s);
+
+hipError_t launch_sqnorm(const float* X, float* out, int B, int D, hipStream_t s);
+hipError_t launch_cast_bf16(const float* src, bf16_t* dst, int64_t n, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, bf16_t* pb,
+                       int64_t n, const int64_t* step, float lr, float b1, float b2,
+                       float eps, hipStream_t s);
+hipError_t launch_counter_add(int64_t* c, int64_t inc, hipStream_t s);
+hipError_t launch_zero_ranges(float* base, const int64_t* ranges, int nranges,
+                              hipStream_t s);
+
+// materialised InfoNCE (FP32 B x B in the workspace, row stride ld)
+hipError_t launch_row_lse(const float* F, int B, int ld, float* r, float* diag, hipStream_t s);
+hipError_t launch_col_lse_partial(const float* F, int B, int ld, int rchunks, float* pm,
+                                  float* ps, hipStream_t s);
+hipError_t launch_lse_merge(const float* pm, const float* ps, int nparts, int B,
+                            float* out, hipStream_t s);
+hipError_t launch_loss(const float* r, const float* c, const float* diag, int B,
+                       int symmetric, float beta, float* loss_out, hipStream_t s);
+hipError_t launch_grad_matrix(float* F, int B, int ld, const float* r, const float* c,
+                              int symmetric, float beta, int l2, float* rowsum,
+                              hipStream_t s);
+hipError_t launch_l2_fix(float* dX, const float* X, const float* rs, int B, int D,
+                         hipStream_t s);
+
+// fused InfoNCE (BF16 tiles, FP32 online LSE)
+struct FusedArgs {
+  const float* phi;
+  const float* psi;
+  bf16_t* phi_b;      // BF16 copies written by the prep kernel
+  bf16_t* psi_b;
+  float* nphi;        // squared norms of the BF16-rounded rows (L2)
+  float* npsi;
+  float* row_m;       // [S][B]
+  float* row_s;
+  float* col_m;       // [B/64][B]
+  float* col_s;
+  float* r;
+  float* c;
+  float* diag;
+  float* dX_part;     // [S][B][D] backward partials
+  float* rs_part;     // [S][B]   sum_b H_ab (L2)
+  float* dphi;        // [B][D] FP32 out
+  float* dpsi;
+  void* dphi_t;       // storage-type copies for the encoder GEMMs
+  void* dpsi_t;
+};
+int fused_splits(int B);
+hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, hipStream_t s);
+hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmetric,
+                            float beta, bool out_bf16, hipStream_t s);
+
+}  // namespace crl

@@ -1,0 +1,605 @@
+// Relabel/gather, LayerNorm+Swish, column reductions, materialised InfoNCE,
+// Adam and small utility kernels (gfx950, wave64).
+#include "internal.hpp"
+
+namespace crl {
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11): 10 rounds of two 64x64->128 products,
+// key bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ inline void philox4x64_10(uint64_t (&x)[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    uint64_t lo0 = M0 * x[0], hi0 = __umul64hi(M0, x[0]);
+    uint64_t lo1 = M1 * x[2], hi1 = __umul64hi(M1, x[2]);
+    uint64_t y0 = hi1 ^ x[1] ^ k0;
+    uint64_t y2 = hi0 ^ x[3] ^ k1;
+    x[0] = y0; x[1] = lo1; x[2] = y2; x[3] = lo0;
+  }
+}
+
+// One wavefront per sample: draw (e, t, k), then copy the rows.
+template <typename T>
+__global__ __launch_bounds__(256) void relabel_kernel(
+    const float* __restrict__ obs, const float* __restrict__ act, int E, int T_,
+    int d_s, int d_a, int d_g, int goal_lo, uint64_t seed, const int64_t* __restrict__ step,
+    const uint64_t* __restrict__ thr, int B, int32_t* __restrict__ idx,
+    T* __restrict__ x_sa, int ld_sa, T* __restrict__ x_g, int ld_g,
+    T* __restrict__ x_sg, int ld_sg) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= B) return;
+  uint64_t x[4] = {(uint64_t)b, (uint64_t)(*step), 0ull, 0ull};
+  philox4x64_10(x, seed, 0ull);
+  const int e = (int)__umul64hi(x[0], (uint64_t)E);
+  const int t = (int)__umul64hi(x[1], (uint64_t)(T_ - 1));
+  // k = 1 + #{m in [1, T-2] : w2 < thr[m]}; the table is non-increasing, so
+  // the count is the length of its prefix that exceeds w2.
+  const uint64_t w2 = x[2];
+  int lo = 0, hi = T_ - 2;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (thr[mid] > w2) lo = mid + 1; else hi = mid;
+  }
+  const int tg = min(t + 1 + lo, T_ - 1);
+  if (lane == 0) {
+    idx[3 * b + 0] = e;
+    idx[3 * b + 1] = t;
+    idx[3 * b + 2] = tg;
+  }
+  const float* s_row = obs + ((int64_t)e * T_ + t) * d_s;
+  const float* a_row = act + ((int64_t)e * T_ + t) * d_a;
+  const float* g_row = obs + ((int64_t)e * T_ + tg) * d_s + goal_lo;
+  for (int c = lane; c < ld_sa; c += 64) {
+    float v = c < d_s ? s_row[c] : (c < d_s + d_a ? a_row[c - d_s] : 0.f);
+    x_sa[(int64_t)b * ld_sa + c] = Store<T>::from_f(v);
+  }
+  for (int c = lane; c < ld_g; c += 64)
+    x_g[(int64_t)b * ld_g + c] = Store<T>::from_f(c < d_g ? g_row[c] : 0.f);
+  if (x_sg) {
+    for (int c = lane; c < ld_sg; c += 64) {
+      float v = c < d_s ? s_row[c] : (c < d_s + d_g ? g_row[c - d_s] : 0.f);
+      x_sg[(int64_t)b * ld_sg + c] = Store<T>::from_f(v);
+    }
+  }
+}
+
+hipError_t launch_relabel(const float* obs, const float* act, int E, int T, int d_s,
+                          int d_a, int d_g, int goal_lo, uint64_t seed,
+                          const int64_t* step, const uint64_t* thr, int B,
+                          int32_t* idx, void* x_sa, int ld_sa, void* x_g, int ld_g,
+                          void* x_sg, int ld_sg, bool bf16, hipStream_t s) {
+  dim3 grid((B + 3) / 4), block(256);
+  if (bf16)
+    relabel_kernel<bf16_t><<<grid, block, 0, s>>>(obs, act, E, T, d_s, d_a, d_g, goal_lo,
+        seed, step, thr, B, idx, (bf16_t*)x_sa, ld_sa, (bf16_t*)x_g, ld_g,
+        (bf16_t*)x_sg, ld_sg);
+  else
+    relabel_kernel<float><<<grid, block, 0, s>>>(obs, act, E, T, d_s, d_a, d_g, goal_lo,
+        seed, step, thr, B, idx, (float*)x_sa, ld_sa, (float*)x_g, ld_g,
+        (float*)x_sg, ld_sg);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 8-element row chunks
+// ---------------------------------------------------------------------------
+__device__ inline void load8(const float* p, float (&o)[8]) {
+  float4 a = *reinterpret_cast<const float4*>(p);
+  float4 b = *reinterpret_cast<const float4*>(p + 4);
+  o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+  o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+}
+__device__ inline void load8(const bf16_t* p, float (&o)[8]) {
+  uint4 u = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    o[2 * i] = __builtin_bit_cast(float, w[i] << 16);
+    o[2 * i + 1] = __builtin_bit_cast(float, w[i] & 0xffff0000u);
+  }
+}
+__device__ inline void store8(float* p, const float (&o)[8]) {
+  *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  *reinterpret_cast<float4*>(p + 4) = make_float4(o[4], o[5], o[6], o[7]);
+}
+__device__ inline void store8(bf16_t* p, const float (&o)[8]) {
+  uint4 u;
+  u.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
+  u.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
+  u.z = (uint32_t)f2bf(o[4]) | ((uint32_t)f2bf(o[5]) << 16);
+  u.w = (uint32_t)f2bf(o[6]) | ((uint32_t)f2bf(o[7]) << 16);
+  *reinterpret_cast<uint4*>(p) = u;
+}
+
+// ---------------------------------------------------------------------------
+// LayerNorm (biased variance over the N features) -> affine -> Swish.
+// One wavefront per row; lane owns chunks lane, lane+64, ... of 8 features.
+// ---------------------------------------------------------------------------
+template <typename T, int CH>
+__global__ __launch_bounds__(256) void ln_swish_fwd_kernel(LnArgs a, int B, int N, float eps) {
+  const int e = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= B) return;
+  const int nch = N >> 3;
+  const T* z = reinterpret_cast<const T*>(a.Z[e]) + (int64_t)row * N;
+  T* h = reinterpret_cast<T*>(a.H[e]) + (int64_t)row * N;
+  float v[CH][8];
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    int ch = lane + 64 * c;
+    if (ch < nch) {
+      load8(z + ch * 8, v[c]);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s += v[c][i];
+    }
+  }
+  const float mean = wave_sum(s) / (float)N;
+  float q = 0.f;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    int ch = lane + 64 * c;
+    if (ch < nch) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) { float d = v[c][i] - mean; q += d * d; }
+    }
+  }
+  const float var = wave_sum(q) / (float)N;
+  const float rstd = 1.f / sqrtf(var + eps);
+  const float* gg = a.g[e];
+  const float* bb = a.b[e];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    int ch = lane + 64 * c;
+    if (ch < nch) {
+      float gv[8], bv[8], o[8];
+      load8(gg + ch * 8, gv);
+      load8(bb + ch * 8, bv);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        float y = gv[i] * ((v[c][i] - mean) * rstd) + bv[i];
+        o[i] = y * sigmoidf_(y);
+      }
+      store8(h + ch * 8, o);
+    }
+  }
+  if (lane == 0) { a.mu[e][row] = mean; a.rstd[e][row] = rstd; }
+}
+
+hipError_t launch_ln_swish_fwd(const LnArgs& a, int count, int B, int N, float eps,
+                               bool bf16, hipStream_t s) {
+  dim3 grid((B + 3) / 4, count), block(256);
+  int ch = (N / 8 + 63) / 64;
+#define LNF(T, C) ln_swish_fwd_kernel<T, C><<<grid, block, 0, s>>>(a, B, N, eps)
+  if (bf16) { if (ch <= 1) LNF(bf16_t, 1); else if (ch <= 2) LNF(bf16_t, 2); else LNF(bf16_t, 4); }
+  else      { if (ch <= 1) LNF(float, 1);  else if (ch <= 2) LNF(float, 2);  else LNF(float, 4); }
+#undef LNF
+  return hipGetLastError();
+}
+
+// Backward of h = Swish(g * zhat + b), zhat = (z - mu) * rstd, for R rows per
+// wavefront.  Writes dZ and per-wavefront column partials of
+// dg = sum dy*zhat, db_ln = sum dy and db_linear = sum dz.
+template <typename T, int CH>
+__global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int N, int R) {
+  const int e = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int row0 = w * R;
+  if (row0 >= B) return;
+  const int nch = N >> 3;
+  float gv[CH][8], bv[CH][8], cg[CH][8], cb[CH][8], cz[CH][8];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    int ch = lane + 64 * c;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { cg[c][i] = 0.f; cb[c][i] = 0.f; cz[c][i] = 0.f; gv[c][i] = 0.f; bv[c][i] = 0.f; }
+    if (ch < nch) { load8(a.g[e] + ch * 8, gv[c]); load8(a.b[e] + ch * 8, bv[c]); }
+  }
+  const T* Zb = reinterpret_cast<const T*>(a.Z[e]);
+  const T* dHb = reinterpret_cast<const T*>(a.dH[e]);
+  T* dZb = reinterpret_cast<T*>(a.dZ[e]);
+  const int rend = min(B, row0 + R);
+  for (int row = row0; row < rend; ++row) {
+    const float mu = a.mu[e][row], rstd = a.rstd[e][row];
+    float zh[CH][8], dzh[CH][8];
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      int ch = lane + 64 * c;
+      if (ch < nch) {
+        float z[8], dh[8];
+        load8(Zb + (int64_t)row * N + ch * 8, z);
+        load8(dHb + (int64_t)row * N + ch * 8, dh);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          float xh = (z[i] - mu) * rstd;
+          float y = gv[c][i] * xh + bv[c][i];
+          float sg = sigmoidf_(y);
+          float dy = dh[i] * (sg * (1.f + y * (1.f - sg)));
+          cg[c][i] += dy * xh;
+          cb[c][i] += dy;
+          float d = dy * gv[c][i];
+          zh[c][i] = xh;
+          dzh[c][i] = d;
+          s1 += d;
+          s2 += d * xh;
+        }
+      }
+    }
+    const float m1 = wave_sum(s1) / (float)N;
+    const float m2 = wave_sum(s2) / (float)N;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      int ch = lane + 64 * c;
+      if (ch < nch) {
+        float o[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          o[i] = rstd * (dzh[c][i] - m1 - zh[c][i] * m2);
+          cz[c][i] += o[i];
+        }
+        store8(dZb + (int64_t)row * N + ch * 8, o);
+      }
+    }
+  }
+  float* part = a.part[e] + (int64_t)w * 3 * N;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    int ch = lane + 64 * c;
+    if (ch < nch) {
+      store8(part + ch * 8, cg[c]);
+      store8(part + N + ch * 8, cb[c]);
+      store8(part + 2 * N + ch * 8, cz[c]);
+    }
+  }
+}
+
+int ln_bwd_partials(int B, int rows_per_wave) { return (B + rows_per_wave - 1) / rows_per_wave; }
+
+hipError_t launch_ln_swish_bwd(const LnArgs& a, int count, int B, int N, bool bf16,
+                               int R, hipStream_t s) {
+  int nw = ln_bwd_partials(B, R);
+  dim3 grid((nw + 3) / 4, count), block(256);
+  int ch = (N / 8 + 63) / 64;
+#define LNB(T, C) ln_swish_bwd_kernel<T, C><<<grid, block, 0, s>>>(a, B, N, R)
+  if (bf16) { if (ch <= 1) LNB(bf16_t, 1); else if (ch <= 2) LNB(bf16_t, 2); else LNB(bf16_t, 4); }
+  else      { if (ch <= 1) LNB(float, 1);  else if (ch <= 2) LNB(float, 2);  else LNB(float, 4); }
+#undef LNB
+  return hipGetLastError();
+}
+
+// out[k][n] = sum over w (in order) of part[w][k][n]
+__global__ void partial_reduce_kernel(ColReduceArgs a, int nparts, int nk, int N) {
+  const int e = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nk * N) return;
+  const int k = i / N, n = i % N;
+  const float* p = a.part[e] + (int64_t)k * N + n;
+  float s = 0.f;
+  for (int w = 0; w < nparts; ++w) s += p[(int64_t)w * nk * N];
+  a.out[e][k][n] = s;
+}
+
+hipError_t launch_partial_reduce(const ColReduceArgs& a, int count, int nparts, int nk,
+                                 int N, hipStream_t s) {
+  dim3 grid((nk * N + 255) / 256, count), block(256);
+  partial_reduce_kernel<<<grid, block, 0, s>>>(a, nparts, nk, N);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void colsum_partial_kernel(ColSumArgs a, int B, int N, int ld) {
+  const int e = blockIdx.z;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int r0 = blockIdx.y * 64, r1 = min(B, r0 + 64);
+  const T* X = reinterpret_cast<const T*>(a.X[e]);
+  float s = 0.f;
+  for (int r = r0; r < r1; ++r) s += Store<T>::to_f(X[(int64_t)r * ld + n]);
+  a.part[e][(int64_t)blockIdx.y * N + n] = s;
+}
+
+hipError_t launch_colsum(const ColSumArgs& a, int count, int B, int N, int ld, bool bf16,
+                         hipStream_t s) {
+  int nrb = (B + 63) / 64;
+  dim3 grid((N + 255) / 256, nrb, count), block(256);
+  if (bf16) colsum_partial_kernel<bf16_t><<<grid, block, 0, s>>>(a, B, N, ld);
+  else      colsum_partial_kernel<float><<<grid, block, 0, s>>>(a, B, N, ld);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  ColReduceArgs r{};
+  for (int e = 0; e < count; ++e) { r.part[e] = a.part[e]; r.out[e][0] = a.out[e]; }
+  return launch_partial_reduce(r, count, nrb, 1, N, s);
+}
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+__global__ void sqnorm_kernel(const float* __restrict__ X, float* __restrict__ out, int B, int D) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= B) return;
+  float s = 0.f;
+  for (int d = lane; d < D; d += 64) { float v = X[(int64_t)row * D + d]; s += v * v; }
+  s = wave_sum(s);
+  if (lane == 0) out[row] = s;
+}
+hipError_t launch_sqnorm(const float* X, float* out, int B, int D, hipStream_t s) {
+  sqnorm_kernel<<<(B + 3) / 4, 256, 0, s>>>(X, out, B, D);
+  return hipGetLastError();
+}
+
+__global__ void cast_bf16_kernel(const float* __restrict__ src, bf16_t* __restrict__ dst, int64_t n) {
+  int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * 4;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x * 4) {
+    if (i + 4 <= n) {
+      float4 v = *reinterpret_cast<const float4*>(src + i);
+      uint2 u;
+      u.x = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+      u.y = (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+      *reinterpret_cast<uint2*>(dst + i) = u;
+    } else {
+      for (int64_t j = i; j < n; ++j) dst[j] = f2bf(src[j]);
+    }
+  }
+}
+hipError_t launch_cast_bf16(const float* src, bf16_t* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 1023) / 1024;
+  if (blocks > 8192) blocks = 8192;
+  cast_bf16_kernel<<<(int)blocks, 256, 0, s>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+// Adam on a flat vector; bias corrections 1 - b^t = -expm1(t log b), which
+// keeps full FP32 relative accuracy (no cancellation in 1 - b^t).
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v,
+                                                   bf16_t* __restrict__ pb, int64_t n,
+                                                   const int64_t* __restrict__ step, float lr,
+                                                   float b1, float b2, float eps) {
+  const float t = (float)(*step);
+  const float bc1 = -expm1f(t * logf(b1));
+  const float bc2 = -expm1f(t * logf(b2));
+  const float c1 = 1.f / bc1, c2 = 1.f / bc2;
+  const int64_t n4 = n >> 2;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float4 pp = reinterpret_cast<float4*>(p)[i];
+    float4 gg = reinterpret_cast<const float4*>(g)[i];
+    float4 mm = reinterpret_cast<float4*>(m)[i];
+    float4 vv = reinterpret_cast<float4*>(v)[i];
+    float* pa = &pp.x; float* ga = &gg.x; float* ma = &mm.x; float* va = &vv.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      ma[k] = b1 * ma[k] + (1.f - b1) * ga[k];
+      va[k] = b2 * va[k] + (1.f - b2) * ga[k] * ga[k];
+      pa[k] -= lr * (ma[k] * c1) / (sqrtf(va[k] * c2) + eps);
+    }
+    reinterpret_cast<float4*>(p)[i] = pp;
+    reinterpret_cast<float4*>(m)[i] = mm;
+    reinterpret_cast<float4*>(v)[i] = vv;
+    if (pb) {
+      uint2 u;
+      u.x = (uint32_t)f2bf(pp.x) | ((uint32_t)f2bf(pp.y) << 16);
+      u.y = (uint32_t)f2bf(pp.z) | ((uint32_t)f2bf(pp.w) << 16);
+      reinterpret_cast<uint2*>(pb)[i] = u;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+    int64_t k = n4 * 4 + threadIdx.x;
+    float mk = b1 * m[k] + (1.f - b1) * g[k];
+    float vk = b2 * v[k] + (1.f - b2) * g[k] * g[k];
+    m[k] = mk; v[k] = vk;
+    p[k] -= lr * (mk * c1) / (sqrtf(vk * c2) + eps);
+    if (pb) pb[k] = f2bf(p[k]);
+  }
+}
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, bf16_t* pb, int64_t n,
+                       const int64_t* step, float lr, float b1, float b2, float eps,
+                       hipStream_t s) {
+  int64_t blocks = (n / 4 + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 16384) blocks = 16384;
+  adam_kernel<<<(int)blocks, 256, 0, s>>>(p, g, m, v, pb, n, step, lr, b1, b2, eps);
+  return hipGetLastError();
+}
+
+__global__ void counter_add_kernel(int64_t* c, int64_t inc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c += inc;
+}
+hipError_t launch_counter_add(int64_t* c, int64_t inc, hipStream_t s) {
+  counter_add_kernel<<<1, 64, 0, s>>>(c, inc);
+  return hipGetLastError();
+}
+
+// ranges: [nranges][2] = (offset, length) in floats
+__global__ void zero_ranges_kernel(float* base, const int64_t* ranges) {
+  const int64_t off = ranges[2 * blockIdx.x], len = ranges[2 * blockIdx.x + 1];
+  for (int64_t i = threadIdx.x; i < len; i += blockDim.x) base[off + i] = 0.f;
+}
+hipError_t launch_zero_ranges(float* base, const int64_t* ranges, int nranges, hipStream_t s) {
+  if (nranges <= 0) return hipSuccess;
+  zero_ranges_kernel<<<nranges, 64, 0, s>>>(base, ranges);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// materialised InfoNCE: F [B][B] FP32 in memory
+// ---------------------------------------------------------------------------
+// r_i = log sum_j exp(F_ij) (max-subtracted, two passes over the row); F_ii.
+__global__ __launch_bounds__(256) void row_lse_kernel(const float* __restrict__ F, int B, int ld,
+                                                      float* __restrict__ r, float* __restrict__ diag) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= B) return;
+  const float* row = F + (int64_t)i * ld;
+  float m = -INFINITY;
+  for (int j = lane; j < B; j += 64) m = fmaxf(m, row[j]);
+  m = wave_max(m);
+  float s = 0.f;
+  for (int j = lane; j < B; j += 64) s += __expf(row[j] - m);
+  s = wave_sum(s);
+  if (lane == 0) { r[i] = m + __logf(s); diag[i] = row[i]; }
+}
+hipError_t launch_row_lse(const float* F, int B, int ld, float* r, float* diag, hipStream_t s) {
+  row_lse_kernel<<<(B + 3) / 4, 256, 0, s>>>(F, B, ld, r, diag);
+  return hipGetLastError();
+}
+
+// per (row chunk, column) online (max, sum) over the chunk's rows
+__global__ void col_lse_partial_kernel(const float* __restrict__ F, int B, int ld, int rows_per,
+                                       float* __restrict__ pm, float* __restrict__ ps) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= B) return;
+  const int i0 = blockIdx.y * rows_per, i1 = min(B, i0 + rows_per);
+  float m = -INFINITY, s = 0.f;
+  for (int i = i0; i < i1; ++i) {
+    float f = F[(int64_t)i * ld + j];
+    if (f > m) { s = s * __expf(m - f) + 1.f; m = f; }
+    else s += __expf(f - m);
+  }
+  pm[(int64_t)blockIdx.y * B + j] = m;
+  ps[(int64_t)blockIdx.y * B + j] = s;
+}
+hipError_t launch_col_lse_partial(const float* F, int B, int ld, int rchunks, float* pm, float* ps,
+                                  hipStream_t s) {
+  int rows_per = (B + rchunks - 1) / rchunks;
+  dim3 grid((B + 255) / 256, rchunks);
+  col_lse_partial_kernel<<<grid, 256, 0, s>>>(F, B, ld, rows_per, pm, ps);
+  return hipGetLastError();
+}
+
+__global__ void lse_merge_kernel(const float* __restrict__ pm, const float* __restrict__ ps,
+                                 int nparts, int B, float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= B) return;
+  float m = -INFINITY;
+  for (int p = 0; p < nparts; ++p)
+    if (ps[(int64_t)p * B + j] > 0.f) m = fmaxf(m, pm[(int64_t)p * B + j]);
+  float s = 0.f;
+  for (int p = 0; p < nparts; ++p) {
+    float sp = ps[(int64_t)p * B + j];
+    if (sp > 0.f) s += sp * __expf(pm[(int64_t)p * B + j] - m);
+  }
+  out[j] = m + __logf(s);
+}
+hipError_t launch_lse_merge(const float* pm, const float* ps, int nparts, int B, float* out,
+                            hipStream_t s) {
+  lse_merge_kernel<<<(B + 255) / 256, 256, 0, s>>>(pm, ps, nparts, B, out);
+  return hipGetLastError();
+}
+
+// Loss from r, c, diag in one workgroup: per-thread Kahan sums, then an
+// ordered pairwise tree over the threads (deterministic).
+__device__ inline void kahan_add(float& s, float& comp, float x) {
+  float y = x - comp;
+  float t = s + y;
+  comp = (t - s) - y;
+  s = t;
+}
+__global__ __launch_bounds__(1024) void loss_kernel(const float* __restrict__ r,
+                                                    const float* __restrict__ c,
+                                                    const float* __restrict__ diag, int B,
+                                                    int symmetric, float beta,
+                                                    float* __restrict__ loss_out) {
+  __shared__ float sh[6][1024];
+  float acc[6] = {0, 0, 0, 0, 0, 0}, cmp[6] = {0, 0, 0, 0, 0, 0};
+  float bad = 0.f;
+  for (int i = threadIdx.x; i < B; i += 1024) {
+    float ri = r[i], ci = c[i], di = diag[i];
+    float t[5] = {ri - di, ci - di, ri * ri, ri, ci};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) kahan_add(acc[k], cmp[k], t[k]);
+    if (!isfinite(ri) || !isfinite(ci) || !isfinite(di)) bad += 1.f;
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] = acc[k] - cmp[k];
+  sh[5][threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float inv = 1.f / (float)B;
+    float lf = sh[0][0] * inv, lb = sh[1][0] * inv, lp = beta * sh[2][0] * inv;
+    loss_out[0] = lf + (symmetric ? lb : 0.f) + lp;
+    loss_out[1] = lf;
+    loss_out[2] = lb;
+    loss_out[3] = lp;
+    loss_out[4] = sh[3][0] * inv;
+    loss_out[5] = sh[4][0] * inv;
+    loss_out[6] = sh[5][0];
+    loss_out[7] = 0.f;
+  }
+}
+hipError_t launch_loss(const float* r, const float* c, const float* diag, int B, int symmetric,
+                       float beta, float* loss_out, hipStream_t s) {
+  loss_kernel<<<1, 1024, 0, s>>>(r, c, diag, B, symmetric, beta, loss_out);
+  return hipGetLastError();
+}
+
+// In place: F_ij -> G_ij = dL/dF_ij, or for the L2 energy H_ij = G_ij / d_ij
+// (d_ij = -F_ij; 0 where d_ij = 0) together with rowsum_i = sum_j H_ij.
+__global__ __launch_bounds__(256) void grad_matrix_kernel(float* __restrict__ F, int B, int ld,
+                                                          const float* __restrict__ r,
+                                                          const float* __restrict__ c,
+                                                          int symmetric, float beta, int l2,
+                                                          float* __restrict__ rowsum) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= B) return;
+  const float inv = 1.f / (float)B;
+  const float ri = r[i];
+  const float pen = 2.f * beta * ri;
+  float* row = F + (int64_t)i * ld;
+  float rs = 0.f;
+  for (int j = lane; j < B; j += 64) {
+    float f = row[j];
+    float pr = __expf(f - ri);
+    float g = pr * (1.f + pen) - (j == i ? 1.f : 0.f);
+    if (symmetric) g += __expf(f - c[j]) - (j == i ? 1.f : 0.f);
+    g *= inv;
+    if (l2) {
+      float d = -f;
+      g = d > 0.f ? g / d : 0.f;
+      rs += g;
+    }
+    row[j] = g;
+  }
+  if (l2) {
+    rs = wave_sum(rs);
+    if (lane == 0) rowsum[i] = rs;
+  }
+}
+hipError_t launch_grad_matrix(float* F, int B, int ld, const float* r, const float* c, int symmetric,
+                              float beta, int l2, float* rowsum, hipStream_t s) {
+  grad_matrix_kernel<<<(B + 3) / 4, 256, 0, s>>>(F, B, ld, r, c, symmetric, beta, l2, rowsum);
+  return hipGetLastError();
+}
+
+// dX[i][d] -= rs[i] * X[i][d]
+__global__ void l2_fix_kernel(float* __restrict__ dX, const float* __restrict__ X,
+                              const float* __restrict__ rs, int B, int D) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= (int64_t)B * D) return;
+  dX[k] -= rs[k / D] * X[k];
+}
+hipError_t launch_l2_fix(float* dX, const float* X, const float* rs, int B, int D,
+                         hipStream_t s) {
+  int64_t n = (int64_t)B * D;
+  l2_fix_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(dX, X, rs, B, D);
+  return hipGetLastError();
+}
+
+}  // namespace crl
