@@ -1,0 +1,261 @@
+"""Benchmark of the contrastive-RL critic update on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one whole update: relabel + gather from the GPU-resident replay
+buffer, phi/psi encoders, critic matrix + InfoNCE + logsumexp penalty,
+backward through everything, Adam.  The default workload is the B=4096,
+4x1024 LayerNorm+Swish, dot-energy, symmetric-InfoNCE update with BF16 MFMA
+tiles and the fused (never materialised) logits; its K steps are replayed
+from one captured HIP graph.  Beside it the same update is timed on the plain
+FP32 path (FP32 MFMA tiles, materialised B x B logits, eager launches), the
+per-kernel times are taken with HIP events in an instrumented eager pass, and
+the FP64 oracle is timed on the host cores on a bounded sample.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("CRL update steps/s and MFMA TFLOP/s at B=4096, BF16-fused vs plain FP32")
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 matrix
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="b4096_lnswish4x1024_dot_sym")
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="consecutive updates captured in one HIP graph")
+    ap.add_argument("--fp32-steps", type=int, default=20)
+    ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    return ap.parse_args()
+
+
+def time_steps(upd, steps, warmup, graph_steps):
+    import torch
+    for _ in range(warmup):
+        upd.enqueue()
+    torch.cuda.synchronize()
+    if graph_steps > 0:
+        g = upd.capture(graph_steps)
+        reps = max(1, steps // graph_steps)
+        g.replay()  # one untimed replay
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, reps * graph_steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        upd.enqueue()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, steps
+
+
+def kernel_table(upd, steps):
+    """Per-kernel HIP-event times over `steps` eager updates."""
+    import torch
+    from paper_2408_11052_amd import crl_timing_enable, crl_timing_read, crl_timing_reset
+    crl_timing_reset()
+    crl_timing_enable(True)
+    for _ in range(steps):
+        upd.enqueue()
+    torch.cuda.synchronize()
+    crl_timing_enable(False)
+    rows = crl_timing_read()
+    crl_timing_reset()
+    return rows
+
+
+def cpu_baseline(w, obs, act, phi, psi, budget_s):
+    """The FP64 oracle's update on the host cores, on a bounded sample."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import adam as oadam
+    from oracle import critic as ocritic
+    from oracle import relabel as orelabel
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    flat_p = [(k, L) for layers in (phi, psi) for L in layers for k in L]
+    m = [np.zeros(L[k].shape) for k, L in flat_p]
+    v = [np.zeros(L[k].shape) for k, L in flat_p]
+    phi = [{k: a.astype(np.float64) for k, a in L.items()} for L in phi]
+    psi = [{k: a.astype(np.float64) for k, a in L.items()} for L in psi]
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        _, x_sa, x_g, _ = orelabel.sample_relabel(obs, act, w.batch_size, w.discounting, 2,
+                                                  steps, w.goal_lo, w.goal_dim)
+        out = ocritic.critic_loss_and_grads(phi, psi, x_sa, x_g, w)
+        i = 0
+        for side, layers in (("phi", phi), ("psi", psi)):
+            for l, L in enumerate(layers):
+                for k in L:
+                    L[k], m[i], v[i] = oadam.adam_step(L[k], out["g_" + side][l][k], m[i], v[i],
+                                                       steps + 1, w.critic_lr)
+                    i += 1
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or steps >= 50:
+            break
+    return {"value": steps / dt, "unit": "update-steps/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{steps} full FP64 updates (relabel, critic fwd+bwd, Adam) of the "
+                      f"same workload in {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(this build runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2408_11052_amd import lib
+    from paper_2408_11052_amd.update import CriticUpdate, critic_step_flops, adam_bytes
+    from synthetic import WORKLOADS, buffer_for, critic_params_for
+
+    lib()  # fail loudly if the library is not built
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    w = WORKLOADS[args.workload]
+    log(f"[bench] workload {w.name}: generating the replay buffer "
+        f"({w.num_envs} x {w.episode_len} x {w.obs_dim})")
+    t0 = time.perf_counter()
+    obs, act = buffer_for(w, seed=0)
+    phi, psi = critic_params_for(w, seed=1)
+    log(f"[bench] buffer ready in {time.perf_counter() - t0:.1f} s; uploading")
+    dev = torch.device("cuda:0")
+    d_obs = torch.from_numpy(obs).to(dev)
+    d_act = torch.from_numpy(act).to(dev)
+    torch.cuda.synchronize()
+
+    flops = critic_step_flops(w)
+    upd = CriticUpdate(w, d_obs, d_act, phi, psi, seed=2)
+    nparam = upd.crit.nparam
+    log(f"[bench] {w.precision}/{w.logits}: {upd.crit.nparam} params, workspace "
+        f"{upd.crit.ws_bytes / 2**20:.1f} MiB; timing {args.steps} steps "
+        f"(graphs of {args.graph_steps})")
+    dt, n = time_steps(upd, args.steps, args.warmup, args.graph_steps)
+    ms = 1e3 * dt / n
+    sps = n / dt
+    tflops = flops["total"] * sps / 1e12
+    loss = upd.loss.cpu().numpy().tolist()
+    log(f"[bench] {sps:.1f} steps/s, {ms:.3f} ms/step, {tflops:.1f} TFLOP/s algorithmic; "
+        f"loss parts after {int(upd.n.item())} steps: {[round(x, 4) for x in loss[:4]]}")
+    peak_mem = torch.cuda.max_memory_allocated() / 2**30
+
+    roofline, kernels = None, []
+    if not args.no_profile:
+        rows = kernel_table(upd, args.profile_steps)
+        tot = sum(r[2] for r in rows) or 1.0
+        for name, la, kms, kfl, kby in sorted(rows, key=lambda r: -r[2]):
+            kernels.append({"kernel": name, "launches": la, "ms_total": round(kms, 4),
+                            "us_avg": round(1e3 * kms / max(la, 1), 2),
+                            "share": round(kms / tot, 4),
+                            "tflops": round(kfl / (kms * 1e-3) / 1e12, 2) if kfl else None,
+                            "gbs": round(kby / (kms * 1e-3) / 1e9, 1) if kby else None})
+            log(f"[kernels] {name:34s} n={la:4d} avg {1e3 * kms / max(la, 1):9.2f} us "
+                f"share {kms / tot:6.1%} "
+                + (f"{kfl / (kms * 1e-3) / 1e12:8.1f} TFLOP/s " if kfl else "")
+                + (f"{kby / (kms * 1e-3) / 1e9:8.1f} GB/s" if kby else ""))
+        top = max(rows, key=lambda r: r[2])
+        name, la, kms, kfl, kby = top
+        if kfl > 0:
+            peak = PEAK_BF16_TFLOPS if "bf16" in name else PEAK_FP32_TFLOPS
+            ach = kfl / la / (kms * 1e-3 / la) / 1e12
+            roofline = {"bound": "mfma", "kernel": name, "achieved": round(ach, 2),
+                        "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                        "flops_per_launch": kfl / la, "us_per_launch": 1e3 * kms / la,
+                        "traffic": None}
+        else:
+            ach = kby / la / (kms * 1e-3 / la) / 1e9
+            roofline = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1),
+                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                        "bytes_per_launch": kby / la, "us_per_launch": 1e3 * kms / la,
+                        "traffic": None}
+    upd.close()
+    del upd
+    torch.cuda.empty_cache()
+
+    fp32 = None
+    if not args.no_fp32:
+        wf = w.with_(precision="fp32", logits="materialised")
+        upf = CriticUpdate(wf, d_obs, d_act, phi, psi, seed=2)
+        log(f"[bench] plain FP32 path (materialised logits, eager): {args.fp32_steps} steps")
+        dtf, nf = time_steps(upf, args.fp32_steps, 2, 0)
+        dtg, ng = time_steps(upf, args.fp32_steps, 0, 5)
+        fp32 = {"steps_per_s": round(nf / dtf, 2), "ms_per_step": round(1e3 * dtf / nf, 3),
+                "graph_steps_per_s": round(ng / dtg, 2),
+                "tflops": round(flops["total"] * nf / dtf / 1e12, 2)}
+        log(f"[bench] FP32 plain: {nf / dtf:.1f} steps/s eager, {ng / dtg:.1f} steps/s graph")
+        upf.close()
+        del upf
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"[bench] FP64 oracle on the host cores (~{args.cpu_seconds:.0f} s)")
+        cpu = cpu_baseline(w, obs, act, phi, psi, args.cpu_seconds)
+        log(f"[bench] oracle: {cpu['value']:.3f} steps/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(sps, 2),
+        "unit": "update-steps/s",
+        "n_gpus": 1,
+        "steps": n,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if w.precision == "bf16" else "fp32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "batch": w.batch_size, "obs_dim": w.obs_dim,
+                   "act_dim": w.act_dim, "goal_dim": w.goal_dim,
+                   "hidden": list(w.hidden), "repr_dim": w.repr_dim,
+                   "activation": w.activation, "energy": w.energy_function,
+                   "loss": w.contrastive_loss_function, "logits": w.logits,
+                   "buffer": [w.num_envs, w.episode_len], "graph_steps": args.graph_steps,
+                   "parallelism": "single GPU"},
+        "tflops": round(tflops, 2),
+        "tflops_frac_bf16_peak": round(tflops / PEAK_BF16_TFLOPS, 4),
+        "gflop_per_step": round(flops["total"] / 1e9, 3),
+        "adam_bytes_per_step": adam_bytes(nparam, w.precision == "bf16"),
+        "fp32_plain": fp32,
+        "speedup_vs_fp32_plain": round(sps / fp32["steps_per_s"], 2) if fp32 else None,
+        "peak_hbm_gib": round(peak_mem, 2),
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -197,6 +197,19 @@ enum {
 CRL_API int crl_workspace_view(const crl_ctx* ctx, int32_t which,
                                int64_t* offset, int64_t* bytes);
 
+/* Opt-in kernel timing, for measurement.  While enabled, every kernel that
+ * the calls above launch outside graph capture is bracketed by HIP events on
+ * its own stream and accounted under the kernel's name together with its
+ * algorithmic FLOPs and HBM bytes (the minimum the operation must move).
+ * crl_timing_read waits for the recorded events (it synchronises with them);
+ * nothing else here synchronises.  Process-wide state, guarded by a mutex. */
+CRL_API int crl_timing_enable(int32_t enable);
+CRL_API int crl_timing_reset(void);
+CRL_API int crl_timing_count(int32_t* n);
+CRL_API int crl_timing_read(int32_t index, char* name, int32_t name_len,
+                            int64_t* launches, double* ms, double* flops,
+                            double* bytes);
+
 /* Message for the last non-OK status returned on this thread. */
 CRL_API const char* crl_last_error(void);
 

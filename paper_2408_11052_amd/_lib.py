@@ -57,6 +57,12 @@ SIGNATURES = {
     "crl_counter_add": (C.c_int, [P, I64, P]),
     "crl_cast_bf16": (C.c_int, [P, P, I64, P]),
     "crl_workspace_view": (C.c_int, [P, I32, C.POINTER(I64), C.POINTER(I64)]),
+    "crl_timing_enable": (C.c_int, [I32]),
+    "crl_timing_reset": (C.c_int, []),
+    "crl_timing_count": (C.c_int, [C.POINTER(I32)]),
+    "crl_timing_read": (C.c_int, [I32, C.c_char_p, I32, C.POINTER(I64),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]),
     "crl_last_error": (C.c_char_p, []),
 }
 

@@ -183,6 +183,28 @@ def crl_cast_bf16(src, dst, stream=None):
     check(lib().crl_cast_bf16(_ptr(src), _ptr(dst), src.numel(), _stream(stream)))
 
 
+def crl_timing_enable(enable: bool = True):
+    check(lib().crl_timing_enable(1 if enable else 0))
+
+
+def crl_timing_reset():
+    check(lib().crl_timing_reset())
+
+
+def crl_timing_read() -> list:
+    """[(kernel name, launches, ms, algorithmic FLOPs, HBM bytes)] (synchronises)."""
+    n = C.c_int32()
+    check(lib().crl_timing_count(C.byref(n)))
+    out = []
+    buf = C.create_string_buffer(256)
+    for i in range(n.value):
+        la, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        check(lib().crl_timing_read(i, buf, 256, C.byref(la), C.byref(ms), C.byref(fl),
+                                    C.byref(by)))
+        out.append((buf.value.decode(), la.value, ms.value, fl.value, by.value))
+    return out
+
+
 class CriticLoss(torch.autograd.Function):
     """loss = CriticLoss.apply(params, critic, params_bf16, x_sa, x_g, ws).
 

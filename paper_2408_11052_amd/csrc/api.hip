@@ -196,7 +196,7 @@ void plan_workspace(crl_ctx* x) {
     }
     x->out[e] = take(B * D * 4);
     x->dout[e] = take(B * D * 4);
-    x->dout_t[e] = take(B * D * es);
+    x->dout_t[e] = x->bf16 ? take(B * D * es) : x->dout[e];  // FP32: the same buffer
     x->dH[e] = take(B * H * es);
     x->dZ[e][0] = take(B * H * es);
     x->dZ[e][1] = take(B * H * es);
@@ -542,9 +542,6 @@ CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* para
     if (x->bf16) {
       CRL_HIP(launch_cast_bf16(dphi, reinterpret_cast<bf16_t*>(W(ws, x->dout_t[0])), (int64_t)B * D, s), "cast");
       CRL_HIP(launch_cast_bf16(dpsi, reinterpret_cast<bf16_t*>(W(ws, x->dout_t[1])), (int64_t)B * D, s), "cast");
-    } else {
-      CRL_HIP(hipMemcpyAsync(W(ws, x->dout_t[0]), dphi, (size_t)B * D * 4, hipMemcpyDeviceToDevice, s), "copy");
-      CRL_HIP(hipMemcpyAsync(W(ws, x->dout_t[1]), dpsi, (size_t)B * D * 4, hipMemcpyDeviceToDevice, s), "copy");
     }
   } else {
     FusedArgs a{};

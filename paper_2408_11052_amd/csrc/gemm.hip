@@ -23,12 +23,35 @@ __global__ void splitk_reduce_kernel(GemmParams P) {
 
 
 template <typename T, int LA, int LB, typename OutT>
+static const char* kernel_name() {
+  static const char* names[2][2][2][2] = {
+      {{{"gemm_kernel<f32,KC,KC,f32>", "gemm_kernel<f32,KC,KC,bf16>"},
+        {"gemm_kernel<f32,KC,MC,f32>", "gemm_kernel<f32,KC,MC,bf16>"}},
+       {{"gemm_kernel<f32,MC,KC,f32>", "gemm_kernel<f32,MC,KC,bf16>"},
+        {"gemm_kernel<f32,MC,MC,f32>", "gemm_kernel<f32,MC,MC,bf16>"}}},
+      {{{"gemm_kernel<bf16,KC,KC,f32>", "gemm_kernel<bf16,KC,KC,bf16>"},
+        {"gemm_kernel<bf16,KC,MC,f32>", "gemm_kernel<bf16,KC,MC,bf16>"}},
+       {{"gemm_kernel<bf16,MC,KC,f32>", "gemm_kernel<bf16,MC,KC,bf16>"},
+        {"gemm_kernel<bf16,MC,MC,f32>", "gemm_kernel<bf16,MC,MC,bf16>"}}}};
+  return names[sizeof(T) == 2][LA][LB][sizeof(OutT) == 2];
+}
+
+template <typename T, int LA, int LB, typename OutT>
 static hipError_t run(GemmParams& P, hipStream_t s) {
   int maxt = 0;
   for (int g = 0; g < P.count; ++g) maxt = P.tiles[g] > maxt ? P.tiles[g] : maxt;
   if (maxt == 0) return hipSuccess;
   dim3 grid(maxt, P.splits, P.count), block(kGemmThreads);
+  double flops = 0.0, bytes = 0.0;
+  for (int g = 0; g < P.count; ++g) {
+    const GemmDesc& d = P.d[g];
+    flops += 2.0 * d.M * d.N * d.K;
+    bytes += (double)sizeof(T) * ((double)d.M * d.K + (double)d.K * d.N) +
+             (double)(P.splits > 1 ? 4 : sizeof(OutT)) * d.M * d.N;
+  }
+  KTimer t = timing_begin(kernel_name<T, LA, LB, OutT>(), flops, bytes, s);
   gemm_kernel<T, LA, LB, OutT><<<grid, block, 0, s>>>(P);
+  timing_end(t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || P.splits <= 1) return e;
   int64_t mn = 0;
@@ -38,7 +61,9 @@ static hipError_t run(GemmParams& P, hipStream_t s) {
   }
   int64_t blocks = (mn + 255) / 256;
   if (blocks > 4096) blocks = 4096;
+  KTimer tr = timing_begin("splitk_reduce_kernel", 0.0, (double)(P.splits + 1) * 4.0 * mn * P.count, s);
   splitk_reduce_kernel<<<dim3((unsigned)blocks, P.count), 256, 0, s>>>(P);
+  timing_end(tr);
   return hipGetLastError();
 }
 

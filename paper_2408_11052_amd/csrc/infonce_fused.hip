@@ -360,14 +360,19 @@ __global__ void bwd_reduce_kernel(const float* __restrict__ part, const float* _
   }
 
 hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, hipStream_t s) {
-  fused_prep_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, B, D);
+  CRL_TIMED("fused_prep_kernel", 0.0, 2.0 * B * D * 6.0, s,
+            fused_prep_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, B, D));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int S = fused_splits(B), cps = cols_per_split(B, S);
   const int nrb = (B + kFRows - 1) / kFRows;
   dim3 grid(nrb, S);
+  const double fw_flops = 2.0 * B * B * D;
+  const double fw_bytes = 2.0 * 2.0 * B * D + 4.0 * 2.0 * ((double)S * B + (double)nrb * B);
+  KTimer t = timing_begin(l2 ? "infonce_fwd_kernel<l2>" : "infonce_fwd_kernel<dot>", fw_flops, fw_bytes, s);
   if (l2) { CRL_FUSED_DISPATCH(KS, (infonce_fwd_kernel<KS, 1><<<grid, 256, 0, s>>>(a, B, cps))) }
   else    { CRL_FUSED_DISPATCH(KS, (infonce_fwd_kernel<KS, 0><<<grid, 256, 0, s>>>(a, B, cps))) }
+  timing_end(t);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = launch_lse_merge(a.row_m, a.row_s, S, B, a.r, s);
@@ -381,7 +386,11 @@ hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmet
   const int nrb = (B + kFRows - 1) / kFRows;
   dim3 grid(nrb, S);
   const int64_t n = (int64_t)B * D;
+  const double bw_flops = 2.0 * B * B * D;  // G . Y per pass; the tile recompute is not counted
+  const double bw_bytes = 2.0 * 2.0 * B * D + 4.0 * 2.0 * B + 4.0 * (double)S * B * (D + 1.0);
   for (int pass = 0; pass < 2; ++pass) {
+    KTimer t = timing_begin(pass ? "infonce_bwd_kernel<cols>" : "infonce_bwd_kernel<rows>",
+                            bw_flops, bw_bytes, s);
     if (pass == 0) {
       if (l2) { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 1, 0><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
       else    { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 0, 0><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
@@ -389,16 +398,20 @@ hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmet
       if (l2) { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 1, 1><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
       else    { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 0, 1><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
     }
+    timing_end(t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const bf16_t* Xb = pass ? a.psi_b : a.phi_b;
     float* out = pass ? a.dpsi : a.dphi;
     void* out_t = pass ? a.dpsi_t : a.dphi_t;
     const int blocks = (int)((n + 255) / 256);
+    const double rb = 4.0 * (double)n * (S + 1.0) + (double)n * (out_bf16 ? 2 : 4);
     if (out_bf16)
-      bwd_reduce_kernel<bf16_t><<<blocks, 256, 0, s>>>(a.dX_part, a.rs_part, Xb, S, B, D, l2, out, (bf16_t*)out_t);
+      CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
+                bwd_reduce_kernel<bf16_t><<<blocks, 256, 0, s>>>(a.dX_part, a.rs_part, Xb, S, B, D, l2, out, (bf16_t*)out_t));
     else
-      bwd_reduce_kernel<float><<<blocks, 256, 0, s>>>(a.dX_part, a.rs_part, Xb, S, B, D, l2, out, (float*)out_t);
+      CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
+                bwd_reduce_kernel<float><<<blocks, 256, 0, s>>>(a.dX_part, a.rs_part, Xb, S, B, D, l2, out, (float*)out_t));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -6,6 +6,23 @@
 
 namespace crl {
 
+// timing.hip: opt-in HIP-event timing of single launches (see crl_timing_*).
+struct KTimer {
+  bool on;
+  int slot;
+  hipEvent_t a, b;
+  hipStream_t s;
+  double flops, bytes;
+};
+KTimer timing_begin(const char* name, double flops, double bytes, hipStream_t s);
+void timing_end(KTimer& t);
+#define CRL_TIMED(name, flops, bytes, stream, ...)                   \
+  do {                                                               \
+    ::crl::KTimer _crl_t = ::crl::timing_begin(name, flops, bytes, stream); \
+    __VA_ARGS__;                                                     \
+    ::crl::timing_end(_crl_t);                                       \
+  } while (0)
+
 // gemm.hip: dispatch on storage type / operand layouts / output type.
 hipError_t launch_gemm(GemmParams& P, bool bf16, int la, int lb, bool out_bf16,
                        hipStream_t s);

@@ -74,14 +74,19 @@ hipError_t launch_relabel(const float* obs, const float* act, int E, int T, int 
                           int32_t* idx, void* x_sa, int ld_sa, void* x_g, int ld_g,
                           void* x_sg, int ld_sg, bool bf16, hipStream_t s) {
   dim3 grid((B + 3) / 4), block(256);
+  const double es = bf16 ? 2.0 : 4.0;
+  const double bytes = (double)B * (4.0 * (d_s + d_a + d_g + (x_sg ? d_s + d_g : 0)) +
+                                    es * (ld_sa + ld_g + (x_sg ? ld_sg : 0)) + 12.0);
   if (bf16)
-    relabel_kernel<bf16_t><<<grid, block, 0, s>>>(obs, act, E, T, d_s, d_a, d_g, goal_lo,
+    CRL_TIMED("relabel_kernel", 0.0, bytes, s,
+      relabel_kernel<bf16_t><<<grid, block, 0, s>>>(obs, act, E, T, d_s, d_a, d_g, goal_lo,
         seed, step, thr, B, idx, (bf16_t*)x_sa, ld_sa, (bf16_t*)x_g, ld_g,
-        (bf16_t*)x_sg, ld_sg);
+        (bf16_t*)x_sg, ld_sg));
   else
-    relabel_kernel<float><<<grid, block, 0, s>>>(obs, act, E, T, d_s, d_a, d_g, goal_lo,
+    CRL_TIMED("relabel_kernel", 0.0, bytes, s,
+      relabel_kernel<float><<<grid, block, 0, s>>>(obs, act, E, T, d_s, d_a, d_g, goal_lo,
         seed, step, thr, B, idx, (float*)x_sa, ld_sa, (float*)x_g, ld_g,
-        (float*)x_sg, ld_sg);
+        (float*)x_sg, ld_sg));
   return hipGetLastError();
 }
 
@@ -176,7 +181,9 @@ hipError_t launch_ln_swish_fwd(const LnArgs& a, int count, int B, int N, float e
                                bool bf16, hipStream_t s) {
   dim3 grid((B + 3) / 4, count), block(256);
   int ch = (N / 8 + 63) / 64;
-#define LNF(T, C) ln_swish_fwd_kernel<T, C><<<grid, block, 0, s>>>(a, B, N, eps)
+  const double lnf_bytes = (double)count * B * N * 2.0 * (bf16 ? 2 : 4);
+#define LNF(T, C) CRL_TIMED("ln_swish_fwd_kernel", 0.0, lnf_bytes, s, \
+                            ln_swish_fwd_kernel<T, C><<<grid, block, 0, s>>>(a, B, N, eps))
   if (bf16) { if (ch <= 1) LNF(bf16_t, 1); else if (ch <= 2) LNF(bf16_t, 2); else LNF(bf16_t, 4); }
   else      { if (ch <= 1) LNF(float, 1);  else if (ch <= 2) LNF(float, 2);  else LNF(float, 4); }
 #undef LNF
@@ -268,7 +275,9 @@ hipError_t launch_ln_swish_bwd(const LnArgs& a, int count, int B, int N, bool bf
   int nw = ln_bwd_partials(B, R);
   dim3 grid((nw + 3) / 4, count), block(256);
   int ch = (N / 8 + 63) / 64;
-#define LNB(T, C) ln_swish_bwd_kernel<T, C><<<grid, block, 0, s>>>(a, B, N, R)
+  const double lnb_bytes = (double)count * ((double)B * N * 3.0 * (bf16 ? 2 : 4) + 12.0 * nw * N);
+#define LNB(T, C) CRL_TIMED("ln_swish_bwd_kernel", 0.0, lnb_bytes, s, \
+                            ln_swish_bwd_kernel<T, C><<<grid, block, 0, s>>>(a, B, N, R))
   if (bf16) { if (ch <= 1) LNB(bf16_t, 1); else if (ch <= 2) LNB(bf16_t, 2); else LNB(bf16_t, 4); }
   else      { if (ch <= 1) LNB(float, 1);  else if (ch <= 2) LNB(float, 2);  else LNB(float, 4); }
 #undef LNB
@@ -290,7 +299,8 @@ __global__ void partial_reduce_kernel(ColReduceArgs a, int nparts, int nk, int N
 hipError_t launch_partial_reduce(const ColReduceArgs& a, int count, int nparts, int nk,
                                  int N, hipStream_t s) {
   dim3 grid((nk * N + 255) / 256, count), block(256);
-  partial_reduce_kernel<<<grid, block, 0, s>>>(a, nparts, nk, N);
+  CRL_TIMED("partial_reduce_kernel", 0.0, 4.0 * count * (nparts + 1.0) * nk * N, s,
+            partial_reduce_kernel<<<grid, block, 0, s>>>(a, nparts, nk, N));
   return hipGetLastError();
 }
 
@@ -310,8 +320,11 @@ hipError_t launch_colsum(const ColSumArgs& a, int count, int B, int N, int ld, b
                          hipStream_t s) {
   int nrb = (B + 63) / 64;
   dim3 grid((N + 255) / 256, nrb, count), block(256);
-  if (bf16) colsum_partial_kernel<bf16_t><<<grid, block, 0, s>>>(a, B, N, ld);
-  else      colsum_partial_kernel<float><<<grid, block, 0, s>>>(a, B, N, ld);
+  const double cs_bytes = (double)count * B * N * (bf16 ? 2 : 4);
+  if (bf16) CRL_TIMED("colsum_partial_kernel", 0.0, cs_bytes, s,
+                      colsum_partial_kernel<bf16_t><<<grid, block, 0, s>>>(a, B, N, ld));
+  else      CRL_TIMED("colsum_partial_kernel", 0.0, cs_bytes, s,
+                      colsum_partial_kernel<float><<<grid, block, 0, s>>>(a, B, N, ld));
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   ColReduceArgs r{};
@@ -332,7 +345,8 @@ __global__ void sqnorm_kernel(const float* __restrict__ X, float* __restrict__ o
   if (lane == 0) out[row] = s;
 }
 hipError_t launch_sqnorm(const float* X, float* out, int B, int D, hipStream_t s) {
-  sqnorm_kernel<<<(B + 3) / 4, 256, 0, s>>>(X, out, B, D);
+  CRL_TIMED("sqnorm_kernel", 2.0 * B * D, 4.0 * B * (D + 1.0), s,
+            sqnorm_kernel<<<(B + 3) / 4, 256, 0, s>>>(X, out, B, D));
   return hipGetLastError();
 }
 
@@ -354,7 +368,8 @@ hipError_t launch_cast_bf16(const float* src, bf16_t* dst, int64_t n, hipStream_
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 1023) / 1024;
   if (blocks > 8192) blocks = 8192;
-  cast_bf16_kernel<<<(int)blocks, 256, 0, s>>>(src, dst, n);
+  CRL_TIMED("cast_bf16_kernel", 0.0, 6.0 * n, s,
+            cast_bf16_kernel<<<(int)blocks, 256, 0, s>>>(src, dst, n));
   return hipGetLastError();
 }
 
@@ -408,7 +423,8 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, bf16_t* pb,
   int64_t blocks = (n / 4 + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 16384) blocks = 16384;
-  adam_kernel<<<(int)blocks, 256, 0, s>>>(p, g, m, v, pb, n, step, lr, b1, b2, eps);
+  CRL_TIMED("adam_kernel", 0.0, (28.0 + (pb ? 2.0 : 0.0)) * n, s,
+            adam_kernel<<<(int)blocks, 256, 0, s>>>(p, g, m, v, pb, n, step, lr, b1, b2, eps));
   return hipGetLastError();
 }
 
@@ -450,7 +466,8 @@ __global__ __launch_bounds__(256) void row_lse_kernel(const float* __restrict__ 
   if (lane == 0) { r[i] = m + __logf(s); diag[i] = row[i]; }
 }
 hipError_t launch_row_lse(const float* F, int B, int ld, float* r, float* diag, hipStream_t s) {
-  row_lse_kernel<<<(B + 3) / 4, 256, 0, s>>>(F, B, ld, r, diag);
+  CRL_TIMED("row_lse_kernel", 0.0, 4.0 * B * B, s,
+            row_lse_kernel<<<(B + 3) / 4, 256, 0, s>>>(F, B, ld, r, diag));
   return hipGetLastError();
 }
 
@@ -473,7 +490,8 @@ hipError_t launch_col_lse_partial(const float* F, int B, int ld, int rchunks, fl
                                   hipStream_t s) {
   int rows_per = (B + rchunks - 1) / rchunks;
   dim3 grid((B + 255) / 256, rchunks);
-  col_lse_partial_kernel<<<grid, 256, 0, s>>>(F, B, ld, rows_per, pm, ps);
+  CRL_TIMED("col_lse_partial_kernel", 0.0, 4.0 * B * B, s,
+            col_lse_partial_kernel<<<grid, 256, 0, s>>>(F, B, ld, rows_per, pm, ps));
   return hipGetLastError();
 }
 
@@ -493,7 +511,8 @@ __global__ void lse_merge_kernel(const float* __restrict__ pm, const float* __re
 }
 hipError_t launch_lse_merge(const float* pm, const float* ps, int nparts, int B, float* out,
                             hipStream_t s) {
-  lse_merge_kernel<<<(B + 255) / 256, 256, 0, s>>>(pm, ps, nparts, B, out);
+  CRL_TIMED("lse_merge_kernel", 0.0, 4.0 * B * (2.0 * nparts + 1.0), s,
+            lse_merge_kernel<<<(B + 255) / 256, 256, 0, s>>>(pm, ps, nparts, B, out));
   return hipGetLastError();
 }
 
@@ -545,7 +564,8 @@ __global__ __launch_bounds__(1024) void loss_kernel(const float* __restrict__ r,
 }
 hipError_t launch_loss(const float* r, const float* c, const float* diag, int B, int symmetric,
                        float beta, float* loss_out, hipStream_t s) {
-  loss_kernel<<<1, 1024, 0, s>>>(r, c, diag, B, symmetric, beta, loss_out);
+  CRL_TIMED("loss_kernel", 0.0, 12.0 * B, s,
+            loss_kernel<<<1, 1024, 0, s>>>(r, c, diag, B, symmetric, beta, loss_out));
   return hipGetLastError();
 }
 
@@ -584,7 +604,8 @@ __global__ __launch_bounds__(256) void grad_matrix_kernel(float* __restrict__ F,
 }
 hipError_t launch_grad_matrix(float* F, int B, int ld, const float* r, const float* c, int symmetric,
                               float beta, int l2, float* rowsum, hipStream_t s) {
-  grad_matrix_kernel<<<(B + 3) / 4, 256, 0, s>>>(F, B, ld, r, c, symmetric, beta, l2, rowsum);
+  CRL_TIMED("grad_matrix_kernel", 0.0, 8.0 * B * B, s,
+            grad_matrix_kernel<<<(B + 3) / 4, 256, 0, s>>>(F, B, ld, r, c, symmetric, beta, l2, rowsum));
   return hipGetLastError();
 }
 
@@ -598,7 +619,8 @@ __global__ void l2_fix_kernel(float* __restrict__ dX, const float* __restrict__ 
 hipError_t launch_l2_fix(float* dX, const float* X, const float* rs, int B, int D,
                          hipStream_t s) {
   int64_t n = (int64_t)B * D;
-  l2_fix_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(dX, X, rs, B, D);
+  CRL_TIMED("l2_fix_kernel", 2.0 * n, 12.0 * n, s,
+            l2_fix_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(dX, X, rs, B, D));
   return hipGetLastError();
 }
 
