@@ -157,6 +157,8 @@ int64_t splitk_need(crl_ctx* x) {
   for (int l = 0; l <= x->L; ++l)
     consider(x->lay[0][l].fan_in, x->lay[0][l].fan_out, x->lay[1][l].fan_in,
              x->lay[1][l].fan_out, x->B);
+  // forward output layer: [B x H] . [H x D]
+  consider(x->B, x->D, x->B, x->D, x->H);
   if (!x->fused) {
     // dphi = G psi and dpsi = G^T phi run as single problems with FP32 tiles
     GemmParams P{};
@@ -201,7 +203,7 @@ void plan_workspace(crl_ctx* x) {
     x->dZ[e][0] = take(B * H * es);
     x->dZ[e][1] = take(B * H * es);
     x->lnpart[e] = x->ln ? take((int64_t)x->ln_nparts * 3 * H * 4) : -1;
-    x->cpart[e] = take(((B + 63) / 64) * std::max(H, D) * 4);
+    x->cpart[e] = take(((B + 127) / 128) * std::max(H, D) * 4);
   }
   x->splitk_len = splitk_need(x);
   x->splitk = take(2 * x->splitk_len * 4);
@@ -220,7 +222,7 @@ void plan_workspace(crl_ctx* x) {
     x->cps = take((int64_t)x->rchunks * B * 4);
     x->rowsumH = take(B * 4);
     x->colsumH = take(B * 4);
-    x->cpartB = take(((B + 63) / 64) * B * 4);
+    x->cpartB = take(((B + 127) / 128) * x->ldF * 4);
   } else {
     const int S = fused_splits(x->B);
     const int nrb = (x->B + 63) / 64;
@@ -425,7 +427,11 @@ CRL_API int crl_critic_fwd(crl_ctx* x, const float* params, const uint16_t* para
       else { d.C = W(ws, x->Z[e][l]); d.epi = EPI_BIAS; }
       d.ldc = lo.fan_out;
     }
+    if (last) P.partial = WF(ws, x->splitk);  // few output tiles: split K
     plan_split_k(P, x->bf16, 512);
+    if (P.splits > 1)
+      P.partial_len = (int64_t)P.splits * std::max((int64_t)P.d[0].M * P.d[0].N,
+                                                   (int64_t)P.d[1].M * P.d[1].N);
     CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_MC, x->bf16 && !last, s), "encoder GEMM");
     if (!last && x->ln) {
       LnArgs a{};

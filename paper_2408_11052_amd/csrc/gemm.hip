@@ -3,7 +3,8 @@
 
 namespace crl {
 
-// Sum of split-K partials: C[m][n] (+)= sum_s partial[s][m][n] (FP32 out).
+// Sum of split-K partials: C[m][n] (+)= sum_s partial[s][m][n] (+ bias[n]),
+// FP32 out; the only epilogues used with split-K are none and bias.
 __global__ void splitk_reduce_kernel(GemmParams P) {
   const int g = blockIdx.y;
   const GemmDesc& D = P.d[g];
@@ -16,6 +17,7 @@ __global__ void splitk_reduce_kernel(GemmParams P) {
     for (int k = 0; k < P.splits; ++k) s += src[k * MN + i];
     int64_t row = i / D.N, col = i % D.N;
     int64_t o = row * D.ldc + col;
+    if (D.epi == EPI_BIAS) s += D.bias[col];
     if (D.accumulate) s += C[o];
     C[o] = s;
   }

@@ -12,7 +12,8 @@
 //
 // Tile: 128 x 128 per workgroup of 256 threads (4 waves, 2 x 2), 64 x 64 per
 // wave as 4 x 4 MFMA 16x16 blocks.  K step: 128 bytes of each row per stage
-// (64 BF16 or 32 FP32), double-buffered in LDS with one barrier per stage.
+// (64 BF16 or 32 FP32), double-buffered in LDS with one barrier per stage;
+// global loads run two steps ahead through two register sets.
 //   BF16: v_mfma_f32_16x16x32_bf16, FP32 accumulation.
 //   FP32: v_mfma_f32_16x16x4_f32.
 #pragma once
@@ -82,7 +83,8 @@ __device__ inline uint4 load_vec_guarded(const T* base, int64_t off, int valid) 
 }
 
 // KC operand tile: rows [r0, r0+128), k [k0, k0+BK).  4 vectors per thread.
-template <typename T>
+// FAST: the whole tile is in range (no guards, straight-line vector loads).
+template <typename T, bool FAST>
 __device__ inline void load_kc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
                                int r0, int R, int k0, int kend, int tid) {
   constexpr int VEC = GemmCfg<T>::VEC;
@@ -91,14 +93,18 @@ __device__ inline void load_kc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
     int v = tid + i * kGemmThreads;
     int row = v >> 3, c = v & 7;
     int gr = r0 + row, gk = k0 + c * VEC;
-    int valid = (gr < R) ? min(VEC, kend - gk) : 0;
-    reg[i] = load_vec_guarded<T>(X, (int64_t)gr * ld + gk, valid);
+    if (FAST) {
+      reg[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gr * ld + gk);
+    } else {
+      int valid = (gr < R) ? min(VEC, kend - gk) : 0;
+      reg[i] = load_vec_guarded<T>(X, (int64_t)gr * ld + gk, valid);
+    }
   }
 }
 
 // MC operand tile: k-rows [k0, k0+BK), row/col index [r0, r0+128).
 // Thread (q, mv) loads k-rows 4q..4q+3 at columns mv*VEC..+VEC.
-template <typename T>
+template <typename T, bool FAST>
 __device__ inline void load_mc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
                                int r0, int R, int k0, int kend, int tid) {
   constexpr int BK = GemmCfg<T>::BK, VEC = GemmCfg<T>::VEC;
@@ -108,8 +114,12 @@ __device__ inline void load_mc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     int gk = k0 + 4 * q + j;
-    int valid = (gk < kend) ? min(VEC, R - gm) : 0;
-    reg[j] = load_vec_guarded<T>(X, (int64_t)gk * ld + gm, valid);
+    if (FAST) {
+      reg[j] = *reinterpret_cast<const uint4*>(X + (int64_t)gk * ld + gm);
+    } else {
+      int valid = (gk < kend) ? min(VEC, R - gm) : 0;
+      reg[j] = load_vec_guarded<T>(X, (int64_t)gk * ld + gm, valid);
+    }
   }
 }
 
@@ -213,15 +223,45 @@ __device__ inline void mma_stage(floatx4 (&acc)[4][4], const float* __restrict__
   }
 }
 
+// 8 consecutive values as FP32, from/to FP32 or BF16 storage (16-byte aligned)
+__device__ inline void load8_any(const float* p, float (&o)[8]) {
+  *reinterpret_cast<float4*>(o) = *reinterpret_cast<const float4*>(p);
+  *reinterpret_cast<float4*>(o + 4) = *reinterpret_cast<const float4*>(p + 4);
+}
+__device__ inline void load8_any(const bf16_t* p, float (&o)[8]) {
+  uint4 u = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    o[2 * i] = __builtin_bit_cast(float, w[i] << 16);
+    o[2 * i + 1] = __builtin_bit_cast(float, w[i] & 0xffff0000u);
+  }
+}
+__device__ inline void store8_any(float* p, const float (&o)[8]) {
+  *reinterpret_cast<float4*>(p) = *reinterpret_cast<const float4*>(o);
+  *reinterpret_cast<float4*>(p + 4) = *reinterpret_cast<const float4*>(o + 4);
+}
+__device__ inline void store8_any(bf16_t* p, const float (&o)[8]) {
+  uint4 u;
+  u.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
+  u.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
+  u.z = (uint32_t)f2bf(o[4]) | ((uint32_t)f2bf(o[5]) << 16);
+  u.w = (uint32_t)f2bf(o[6]) | ((uint32_t)f2bf(o[7]) << 16);
+  *reinterpret_cast<uint4*>(p) = u;
+}
+
 // ---------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------
 template <typename T, int LA, int LB, typename OutT>
-__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmParams P) {
+__global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void gemm_kernel(GemmParams P) {
   constexpr int BK = GemmCfg<T>::BK;
   constexpr int LD = lds_ld<T>();
   constexpr int STAGE = (kBM + kBN) * LD;
   __shared__ __attribute__((aligned(16))) T smem[2 * STAGE];
+  static_assert(sizeof(T) * 2 * STAGE >= sizeof(float) * kBM * (kBN + 4),
+                "the epilogue tile must fit in the stage buffers");
 
   const int g = blockIdx.z;
   const GemmDesc& D = P.d[g];
@@ -247,79 +287,149 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmParams P) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  uint4 ra[4], rb[4];
-  auto gload = [&](int k0) {
-    if (LA == LAY_KC) load_kc<T>(ra, A, D.lda, m0, D.M, k0, kend, tid);
-    else              load_mc<T>(ra, A, D.lda, m0, D.M, k0, kend, tid);
-    if (LB == LAY_KC) load_kc<T>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
-    else              load_mc<T>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
+  // Tiles entirely inside M x N (and K steps entirely before kend) take the
+  // unguarded path; edge tiles use element guards.  The choice is uniform
+  // over the workgroup.
+  const bool inner = (m0 + kBM <= D.M) && (n0 + kBN <= D.N);
+  auto gload = [&](uint4 (&ra)[4], uint4 (&rb)[4], int k0) {
+    if (inner && k0 + BK <= kend) {
+      if (LA == LAY_KC) load_kc<T, true>(ra, A, D.lda, m0, D.M, k0, kend, tid);
+      else              load_mc<T, true>(ra, A, D.lda, m0, D.M, k0, kend, tid);
+      if (LB == LAY_KC) load_kc<T, true>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
+      else              load_mc<T, true>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
+    } else {
+      if (LA == LAY_KC) load_kc<T, false>(ra, A, D.lda, m0, D.M, k0, kend, tid);
+      else              load_mc<T, false>(ra, A, D.lda, m0, D.M, k0, kend, tid);
+      if (LB == LAY_KC) load_kc<T, false>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
+      else              load_mc<T, false>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
+    }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](const uint4 (&ra)[4], const uint4 (&rb)[4], int buf) {
     T* As = smem + buf * STAGE;
     T* Bs = As + kBM * LD;
     if (LA == LAY_KC) store_kc<T>(As, ra, tid); else store_mc(As, ra, tid);
     if (LB == LAY_KC) store_kc<T>(Bs, rb, tid); else store_mc(Bs, rb, tid);
   };
 
+  // Two register sets: tile t is fetched into set t&1 two steps before it is
+  // consumed, so each global load has a full step of MFMA work to hide behind.
+  // LDS is double-buffered with one barrier per step.
   const int nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
-  if (nk > 0) {
-    gload(kbeg);
-    sstore(0);
+  uint4 ra0[4], rb0[4], ra1[4], rb1[4];
+  auto step = [&](int kt, uint4 (&rac)[4], uint4 (&rbc)[4], uint4 (&ran)[4], uint4 (&rbn)[4]) {
+    // rac/rbc held tile kt (already in LDS); ran/rbn hold tile kt+1
+    if (kt + 2 < nk) gload(rac, rbc, kbeg + (kt + 2) * BK);
+    const T* As = smem + (kt & 1) * STAGE;
+    mma_stage(acc, As, As + kBM * LD, wm, wn, lane);
+    if (kt + 1 < nk) sstore(ran, rbn, (kt + 1) & 1);
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-      const int cur = kt & 1;
-      if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
-      const T* As = smem + cur * STAGE;
-      mma_stage(acc, As, As + kBM * LD, wm, wn, lane);
-      if (kt + 1 < nk) sstore(cur ^ 1);
-      __syncthreads();
+  };
+  if (nk > 0) {
+    gload(ra0, rb0, kbeg);
+    if (nk > 1) gload(ra1, rb1, kbeg + BK);
+    sstore(ra0, rb0, 0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(kt, ra0, rb0, ra1, rb1);
+      if (kt + 1 < nk) step(kt + 1, ra1, rb1, ra0, rb0);
     }
   }
 
-  // epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 block
+  // Epilogue.  Row/column-only operations (scale, bias, ReLU, L2) are applied
+  // in registers; the 128 x 128 FP32 tile is then staged through LDS so that
+  // global memory sees 16-byte row-contiguous stores (and 16-byte reads of
+  // aux / C where the epilogue needs them).
+  // Lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 MFMA block.
   const int r16 = lane & 15, gq = lane >> 4;
-  if (P.splits > 1) {
-    float* out = P.partial + (int64_t)g * P.partial_len + (int64_t)blockIdx.y * D.M * D.N;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int col = n0 + wn * 64 + j * 16 + r16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int row = m0 + wm * 64 + i * 16 + gq * 4 + r;
-          if (row < D.M && col < D.N) out[(int64_t)row * D.N + col] = acc[i][j][r];
-        }
-      }
-    return;
-  }
-  OutT* __restrict__ C = reinterpret_cast<OutT*>(D.C);
-  const OutT* __restrict__ aux = reinterpret_cast<const OutT*>(D.aux);
+  float* Cs = reinterpret_cast<float*>(smem);  // [128][kLdc], fits in the stage buffers
+  constexpr int kLdc = kBN + 4;
+  const bool split = P.splits > 1;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      int col = n0 + wn * 64 + j * 16 + r16;
-      if (col >= D.N) continue;
-      float bcol = (D.epi == EPI_BIAS || D.epi == EPI_BIAS_RELU) ? D.bias[col] : 0.f;
-      float ccol = (D.epi == EPI_L2) ? D.colv[col] : 0.f;
+      const int cl = wn * 64 + j * 16 + r16;
+      const int col = n0 + cl;
+      float bcol = 0.f, ccol = 0.f;
+      if (!split && col < D.N) {
+        if (D.epi == EPI_BIAS || D.epi == EPI_BIAS_RELU) bcol = D.bias[col];
+        if (D.epi == EPI_L2) ccol = D.colv[col];
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int row = m0 + wm * 64 + i * 16 + gq * 4 + r;
-        if (row >= D.M) continue;
-        int64_t o = (int64_t)row * D.ldc + col;
-        float v = acc[i][j][r] * D.alpha;
-        switch (D.epi) {
-          case EPI_BIAS: v += bcol; break;
-          case EPI_BIAS_RELU: v = fmaxf(v + bcol, 0.f); break;
-          case EPI_MASK_POS: v = (Store<OutT>::to_f(aux[o]) > 0.f) ? v : 0.f; break;
-          case EPI_L2: v = -sqrtf(fmaxf(D.rowv[row] + ccol - 2.f * v, 0.f)); break;
-          default: break;
+        const int rl = wm * 64 + i * 16 + gq * 4 + r;
+        float v = acc[i][j][r];
+        if (!split) {
+          v *= D.alpha;
+          if (D.epi == EPI_BIAS) v += bcol;
+          else if (D.epi == EPI_BIAS_RELU) v = fmaxf(v + bcol, 0.f);
+          else if (D.epi == EPI_L2) {
+            const int row = m0 + rl;
+            const float rv = row < D.M ? D.rowv[row] : 0.f;
+            v = -sqrtf(fmaxf(rv + ccol - 2.f * v, 0.f));
+          }
         }
-        if (D.accumulate) v += Store<OutT>::to_f(C[o]);
-        C[o] = Store<OutT>::from_f(v);
+        Cs[rl * kLdc + cl] = v;
       }
     }
+  __syncthreads();
+  // 128 rows x 16 chunks of 8 values; thread t handles chunk (t & 15) of rows
+  // t/16, t/16 + 16, ...
+  const int ch = tid & 15;
+  const int col0 = n0 + ch * 8;
+  if (split) {
+    float* out = P.partial + (int64_t)g * P.partial_len + (int64_t)blockIdx.y * D.M * D.N;
+    const bool vec = (D.N % 4 == 0) && (col0 + 8 <= D.N);
+    for (int rl = tid >> 4; rl < kBM; rl += 16) {
+      const int row = m0 + rl;
+      if (row >= D.M) break;
+      const float* src = Cs + rl * kLdc + ch * 8;
+      float* dst = out + (int64_t)row * D.N + col0;
+      if (vec) {
+        *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(src);
+        *reinterpret_cast<float4*>(dst + 4) = *reinterpret_cast<const float4*>(src + 4);
+      } else {
+        for (int k = 0; k < 8; ++k)
+          if (col0 + k < D.N) dst[k] = src[k];
+      }
+    }
+    return;
+  }
+  OutT* __restrict__ C = reinterpret_cast<OutT*>(D.C);
+  const OutT* __restrict__ aux = reinterpret_cast<const OutT*>(D.aux);
+  const bool vec = (D.N % 8 == 0) && (D.ldc % 8 == 0) && (col0 + 8 <= D.N);
+  for (int rl = tid >> 4; rl < kBM; rl += 16) {
+    const int row = m0 + rl;
+    if (row >= D.M) break;
+    const float* src = Cs + rl * kLdc + ch * 8;
+    const int64_t o = (int64_t)row * D.ldc + col0;
+    if (vec) {
+      float v[8];
+      *reinterpret_cast<float4*>(v) = *reinterpret_cast<const float4*>(src);
+      *reinterpret_cast<float4*>(v + 4) = *reinterpret_cast<const float4*>(src + 4);
+      if (D.epi == EPI_MASK_POS) {
+        float a8[8];
+        load8_any(aux + o, a8);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = a8[k] > 0.f ? v[k] : 0.f;
+      }
+      if (D.accumulate) {
+        float c8[8];
+        load8_any(C + o, c8);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] += c8[k];
+      }
+      store8_any(C + o, v);
+    } else {
+      for (int k = 0; k < 8; ++k) {
+        if (col0 + k >= D.N) break;
+        float v = src[k];
+        if (D.epi == EPI_MASK_POS) v = Store<OutT>::to_f(aux[o + k]) > 0.f ? v : 0.f;
+        if (D.accumulate) v += Store<OutT>::to_f(C[o + k]);
+        C[o + k] = Store<OutT>::from_f(v);
+      }
+    }
+  }
 }
 
 }  // namespace crl

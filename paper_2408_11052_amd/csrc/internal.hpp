@@ -46,7 +46,7 @@ struct LnArgs {
   // backward
   const void* dH[2];
   void* dZ[2];
-  float* part[2];       // [nwaves][3][N] column partials
+  float* part[2];       // [ceil(B/128)][3][N] column partials
 };
 hipError_t launch_ln_swish_fwd(const LnArgs& a, int count, int B, int N, float eps,
                                bool bf16, hipStream_t s);
@@ -66,7 +66,7 @@ hipError_t launch_partial_reduce(const ColReduceArgs& a, int count, int nparts, 
 struct ColSumArgs {
   const void* X[2];
   float* out[2];
-  float* part[2];   // [ceil(B/64)][N]
+  float* part[2];   // [ceil(B/128)][N]
 };
 hipError_t launch_colsum(const ColSumArgs& a, int count, int B, int N, int ld,
                          bool bf16, hipStream_t s);

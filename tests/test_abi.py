@@ -1,0 +1,114 @@
+"""The C-ABI library: it loads, exports every entry point that include/crl.h
+declares, and rejects bad arguments on the host before touching a device.
+No GPU needed."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2408_11052_amd import _lib
+from synthetic import workloads as WL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "crl.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"CRL_API\s+[\w\s\*]+?\b(crl_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_four_hot_path_calls():
+    names = _declared()
+    for n in ("crl_sample_relabel", "crl_critic_fwd", "crl_critic_bwd", "crl_adam_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+    # and the Python binding declares exactly these
+    assert sorted(_lib.SIGNATURES) == _declared()
+
+
+def test_only_crl_symbols_are_exported():
+    out = os.popen(f"nm -D --defined-only {_lib.LIB_PATH}").read().split("\n")
+    syms = [l.split()[-1] for l in out if l.strip() and l.split()[1] in ("T", "W")]
+    assert syms and all(s.startswith("crl_") or s.startswith("_") for s in syms), syms
+
+
+def _create(**kw):
+    from paper_2408_11052_amd.critic import make_config
+    cfg = make_config(WL.SMALL_RELU)
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    ctx = C.c_void_p()
+    rc = _lib.lib().crl_create(C.byref(cfg), C.byref(ctx))
+    return rc, _lib.lib().crl_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("batch", 0, "batch"),
+    ("hidden", 100, "hidden"),
+    ("repr_dim", 12, "repr_dim"),
+    ("goal_lo", 28, "goal slice"),
+    ("energy", 7, "energy"),
+    ("loss", 3, "loss"),
+    ("discount", 1.0, "discount"),
+    ("discount", 0.0, "discount"),
+    ("max_episode_len", 1, "max_episode_len"),
+    ("ln_eps", 0.0, "ln_eps"),
+    ("logsumexp_penalty", -1.0, "logsumexp_penalty"),
+    ("n_hidden", 0, "n_hidden"),
+])
+def test_create_rejects_bad_config_on_host(field, value, msg):
+    rc, err = _create(**{field: value})
+    assert rc == _lib.CRL_EINVAL
+    assert msg in err
+
+
+def test_create_rejects_unsupported_combinations():
+    rc, err = _create(logits=1)  # fused logits with FP32 tiles
+    assert rc == _lib.CRL_EUNSUPPORTED and "BF16" in err
+    rc, err = _create(logits=1, precision=1, repr_dim=48)
+    assert rc == _lib.CRL_EUNSUPPORTED and "repr_dim" in err
+
+
+def test_reserved_fields_must_be_zero():
+    from paper_2408_11052_amd.critic import make_config
+    cfg = make_config(WL.SMALL_RELU)
+    cfg.reserved[3] = 1
+    ctx = C.c_void_p()
+    assert _lib.lib().crl_create(C.byref(cfg), C.byref(ctx)) == _lib.CRL_EINVAL
+
+
+def test_null_arguments_rejected_without_device():
+    L = _lib.lib()
+    assert L.crl_create(None, None) == _lib.CRL_EINVAL
+    assert L.crl_adam_step(None, None, None, None, None, 10, None, 1e-3, 0.9, 0.999, 1e-8,
+                           None) == _lib.CRL_EINVAL
+    assert L.crl_counter_add(None, 1, None) == _lib.CRL_EINVAL
+    assert L.crl_cast_bf16(None, None, 4, None) == _lib.CRL_EINVAL
+    assert L.crl_sample_relabel(None, None, None, 1, 2, 0, None, None, None, None, None,
+                                None) == _lib.CRL_EINVAL
+    n = C.c_int32()
+    assert L.crl_timing_count(C.byref(n)) == _lib.CRL_OK
+
+
+def test_adam_rejects_misaligned_and_bad_hyperparameters():
+    L = _lib.lib()
+    buf = (C.c_float * 64)()
+    base = C.addressof(buf)
+    base16 = (base + 15) // 16 * 16
+    p = C.c_void_p(base16)
+    mis = C.c_void_p(base16 + 4)
+    step = C.c_void_p(base16)
+    assert L.crl_adam_step(mis, p, p, p, None, 4, step, 1e-3, 0.9, 0.999, 1e-8,
+                           None) == _lib.CRL_EINVAL
+    assert L.crl_adam_step(p, p, p, p, None, 4, step, 1e-3, 1.5, 0.999, 1e-8,
+                           None) == _lib.CRL_EINVAL
+    assert L.crl_adam_step(p, p, p, p, None, -1, step, 1e-3, 0.9, 0.999, 1e-8,
+                           None) == _lib.CRL_EINVAL
+    assert "Adam" in L.crl_last_error().decode() or "n must" in L.crl_last_error().decode()
