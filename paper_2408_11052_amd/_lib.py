@@ -53,7 +53,8 @@ SIGNATURES = {
     "crl_sample_relabel": (C.c_int, [P, P, P, I32, I32, U64, P, P, P, P, P, P]),
     "crl_critic_fwd": (C.c_int, [P, P, P, P, P, P, P, P]),
     "crl_critic_bwd": (C.c_int, [P, P, P, P, P, P, P, P]),
-    "crl_adam_step": (C.c_int, [P, P, P, P, P, I64, P, F32, F32, F32, F32, P]),
+    "crl_adam_step": (C.c_int, [P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_double,
+                                C.c_double, P]),
     "crl_counter_add": (C.c_int, [P, I64, P]),
     "crl_cast_bf16": (C.c_int, [P, P, I64, P]),
     "crl_workspace_view": (C.c_int, [P, I32, C.POINTER(I64), C.POINTER(I64)]),

@@ -650,17 +650,26 @@ CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* para
 }
 
 CRL_API int crl_adam_step(float* p, const float* g, float* m, float* v, uint16_t* p_bf16,
-                          int64_t n, const int64_t* step, float lr, float b1, float b2,
-                          float eps, void* stream) {
+                          int64_t n, const int64_t* step, double lr, double b1, double b2,
+                          double eps, void* stream) {
   if (!p || !g || !m || !v || !step) return fail(CRL_EINVAL, "NULL buffer argument");
   if (n < 0) return fail(CRL_EINVAL, "n must be >= 0");
   if (!aligned16(p) || !aligned16(g) || !aligned16(m) || !aligned16(v) ||
       (p_bf16 && (reinterpret_cast<uintptr_t>(p_bf16) & 7u)))
     return fail(CRL_EINVAL, "Adam buffers must be 16-byte aligned (p_bf16 8-byte)");
-  if (!(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps >= 0.f && std::isfinite(lr)))
+  if (!(b1 > 0.0 && b1 < 1.0 && b2 > 0.0 && b2 < 1.0 && eps >= 0.0 && std::isfinite(lr)))
     return fail(CRL_EINVAL, "Adam hyperparameters out of range");
   if (n == 0) return CRL_OK;
-  CRL_HIP(launch_adam(p, g, m, v, reinterpret_cast<bf16_t*>(p_bf16), n, step, lr, b1, b2, eps,
+  AdamCoef c;
+  c.lr = (float)lr;
+  c.b1 = (float)b1;
+  c.b2 = (float)b2;
+  c.omb1 = (float)(1.0 - b1);
+  c.omb2 = (float)(1.0 - b2);
+  c.log_b1 = (float)std::log(b1);
+  c.log_b2 = (float)std::log(b2);
+  c.eps = (float)eps;
+  CRL_HIP(launch_adam(p, g, m, v, reinterpret_cast<bf16_t*>(p_bf16), n, step, c,
                       (hipStream_t)stream), "Adam launch");
   return CRL_OK;
 }

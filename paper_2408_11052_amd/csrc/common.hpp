@@ -9,6 +9,7 @@ namespace crl {
 typedef uint16_t bf16_t;  // BF16 bit pattern
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // 16-byte register vector
 
 constexpr int kWave = 64;
 

@@ -67,25 +67,25 @@ template <> struct GemmCfg<float> { static constexpr int BK = 32, VEC = 4; };
 // ---------------------------------------------------------------------------
 // global -> register staging
 // ---------------------------------------------------------------------------
+template <typename T> struct Vec16 { T e[16 / sizeof(T)]; };
+struct Words4 { uint32_t w[4]; };
+struct Floats4 { float f[4]; };
+
 template <typename T>
-__device__ inline uint4 load_vec_guarded(const T* base, int64_t off, int valid) {
+__device__ __forceinline__ u32x4 load_vec_guarded(const T* base, int64_t off, int valid) {
   // `valid` = number of in-range elements of the VEC-wide vector at base+off
   constexpr int VEC = GemmCfg<T>::VEC;
-  if (valid >= VEC) return *reinterpret_cast<const uint4*>(base + off);
-  uint4 r = {0u, 0u, 0u, 0u};
-  if (valid > 0) {
-    T tmp[VEC];
+  if (valid >= VEC) return *reinterpret_cast<const u32x4*>(base + off);
+  Vec16<T> t;
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) tmp[i] = (i < valid) ? base[off + i] : T(0);
-    __builtin_memcpy(&r, tmp, 16);
-  }
-  return r;
+  for (int i = 0; i < VEC; ++i) t.e[i] = (i < valid) ? base[off + i] : T(0);
+  return __builtin_bit_cast(u32x4, t);
 }
 
 // KC operand tile: rows [r0, r0+128), k [k0, k0+BK).  4 vectors per thread.
 // FAST: the whole tile is in range (no guards, straight-line vector loads).
 template <typename T, bool FAST>
-__device__ inline void load_kc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
+__device__ __forceinline__ void load_kc(u32x4 (&reg)[4], const T* __restrict__ X, int ld,
                                int r0, int R, int k0, int kend, int tid) {
   constexpr int VEC = GemmCfg<T>::VEC;
 #pragma unroll
@@ -94,7 +94,7 @@ __device__ inline void load_kc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
     int row = v >> 3, c = v & 7;
     int gr = r0 + row, gk = k0 + c * VEC;
     if (FAST) {
-      reg[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gr * ld + gk);
+      reg[i] = *reinterpret_cast<const u32x4*>(X + (int64_t)gr * ld + gk);
     } else {
       int valid = (gr < R) ? min(VEC, kend - gk) : 0;
       reg[i] = load_vec_guarded<T>(X, (int64_t)gr * ld + gk, valid);
@@ -105,7 +105,7 @@ __device__ inline void load_kc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
 // MC operand tile: k-rows [k0, k0+BK), row/col index [r0, r0+128).
 // Thread (q, mv) loads k-rows 4q..4q+3 at columns mv*VEC..+VEC.
 template <typename T, bool FAST>
-__device__ inline void load_mc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
+__device__ __forceinline__ void load_mc(u32x4 (&reg)[4], const T* __restrict__ X, int ld,
                                int r0, int R, int k0, int kend, int tid) {
   constexpr int BK = GemmCfg<T>::BK, VEC = GemmCfg<T>::VEC;
   constexpr int QN = BK / 4;
@@ -115,7 +115,7 @@ __device__ inline void load_mc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
   for (int j = 0; j < 4; ++j) {
     int gk = k0 + 4 * q + j;
     if (FAST) {
-      reg[j] = *reinterpret_cast<const uint4*>(X + (int64_t)gk * ld + gm);
+      reg[j] = *reinterpret_cast<const u32x4*>(X + (int64_t)gk * ld + gm);
     } else {
       int valid = (gk < kend) ? min(VEC, R - gm) : 0;
       reg[j] = load_vec_guarded<T>(X, (int64_t)gk * ld + gm, valid);
@@ -127,49 +127,49 @@ __device__ inline void load_mc(uint4 (&reg)[4], const T* __restrict__ X, int ld,
 template <typename T> constexpr int lds_ld() { return (128 + 16) / (int)sizeof(T); }
 
 template <typename T>
-__device__ inline void store_kc(T* __restrict__ S, const uint4 (&reg)[4], int tid) {
+__device__ __forceinline__ void store_kc(T* __restrict__ S, const u32x4 (&reg)[4], int tid) {
   constexpr int VEC = GemmCfg<T>::VEC, LD = lds_ld<T>();
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     int v = tid + i * kGemmThreads;
     int row = v >> 3, c = v & 7;
-    *reinterpret_cast<uint4*>(S + row * LD + c * VEC) = reg[i];
+    *reinterpret_cast<u32x4*>(S + row * LD + c * VEC) = reg[i];
   }
 }
 
-__device__ inline void store_mc(bf16_t* __restrict__ S, const uint4 (&reg)[4], int tid) {
+__device__ __forceinline__ void store_mc(bf16_t* __restrict__ S, const u32x4 (&reg)[4], int tid) {
   constexpr int LD = lds_ld<bf16_t>();
   constexpr int QN = GemmCfg<bf16_t>::BK / 4;  // 16
   int q = tid % QN, mv = tid / QN;
-  const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&reg[0]);
-  const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&reg[1]);
-  const uint32_t* w2 = reinterpret_cast<const uint32_t*>(&reg[2]);
-  const uint32_t* w3 = reinterpret_cast<const uint32_t*>(&reg[3]);
+  const Words4 w0 = __builtin_bit_cast(Words4, reg[0]);
+  const Words4 w1 = __builtin_bit_cast(Words4, reg[1]);
+  const Words4 w2 = __builtin_bit_cast(Words4, reg[2]);
+  const Words4 w3 = __builtin_bit_cast(Words4, reg[3]);
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     // elements 2d (low halves) and 2d+1 (high halves) of each k-row
     uint2 lo, hi;
-    lo.x = (w0[d] & 0xffffu) | (w1[d] << 16);
-    lo.y = (w2[d] & 0xffffu) | (w3[d] << 16);
-    hi.x = (w0[d] >> 16) | (w1[d] & 0xffff0000u);
-    hi.y = (w2[d] >> 16) | (w3[d] & 0xffff0000u);
+    lo.x = (w0.w[d] & 0xffffu) | (w1.w[d] << 16);
+    lo.y = (w2.w[d] & 0xffffu) | (w3.w[d] << 16);
+    hi.x = (w0.w[d] >> 16) | (w1.w[d] & 0xffff0000u);
+    hi.y = (w2.w[d] >> 16) | (w3.w[d] & 0xffff0000u);
     int m = mv * 8 + 2 * d;
     *reinterpret_cast<uint2*>(S + m * LD + 4 * q) = lo;
     *reinterpret_cast<uint2*>(S + (m + 1) * LD + 4 * q) = hi;
   }
 }
 
-__device__ inline void store_mc(float* __restrict__ S, const uint4 (&reg)[4], int tid) {
+__device__ __forceinline__ void store_mc(float* __restrict__ S, const u32x4 (&reg)[4], int tid) {
   constexpr int LD = lds_ld<float>();
   constexpr int QN = GemmCfg<float>::BK / 4;  // 8
   int q = tid % QN, mv = tid / QN;
-  const float* r0 = reinterpret_cast<const float*>(&reg[0]);
-  const float* r1 = reinterpret_cast<const float*>(&reg[1]);
-  const float* r2 = reinterpret_cast<const float*>(&reg[2]);
-  const float* r3 = reinterpret_cast<const float*>(&reg[3]);
+  const Floats4 r0 = __builtin_bit_cast(Floats4, reg[0]);
+  const Floats4 r1 = __builtin_bit_cast(Floats4, reg[1]);
+  const Floats4 r2 = __builtin_bit_cast(Floats4, reg[2]);
+  const Floats4 r3 = __builtin_bit_cast(Floats4, reg[3]);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    float4 v = make_float4(r0[i], r1[i], r2[i], r3[i]);
+    float4 v = make_float4(r0.f[i], r1.f[i], r2.f[i], r3.f[i]);
     *reinterpret_cast<float4*>(S + (mv * 4 + i) * LD + 4 * q) = v;
   }
 }
@@ -177,7 +177,7 @@ __device__ inline void store_mc(float* __restrict__ S, const uint4 (&reg)[4], in
 // ---------------------------------------------------------------------------
 // MFMA inner product over one LDS stage
 // ---------------------------------------------------------------------------
-__device__ inline void mma_stage(floatx4 (&acc)[4][4], const bf16_t* __restrict__ As,
+__device__ __forceinline__ void mma_stage(floatx4 (&acc)[4][4], const bf16_t* __restrict__ As,
                                  const bf16_t* __restrict__ Bs, int wm, int wn, int lane) {
   constexpr int LD = lds_ld<bf16_t>();
   int r16 = lane & 15, g = lane >> 4;
@@ -198,7 +198,7 @@ __device__ inline void mma_stage(floatx4 (&acc)[4][4], const bf16_t* __restrict_
   }
 }
 
-__device__ inline void mma_stage(floatx4 (&acc)[4][4], const float* __restrict__ As,
+__device__ __forceinline__ void mma_stage(floatx4 (&acc)[4][4], const float* __restrict__ As,
                                  const float* __restrict__ Bs, int wm, int wn, int lane) {
   constexpr int LD = lds_ld<float>();
   int r16 = lane & 15, g = lane >> 4;
@@ -229,7 +229,7 @@ __device__ inline void load8_any(const float* p, float (&o)[8]) {
   *reinterpret_cast<float4*>(o + 4) = *reinterpret_cast<const float4*>(p + 4);
 }
 __device__ inline void load8_any(const bf16_t* p, float (&o)[8]) {
-  uint4 u = *reinterpret_cast<const uint4*>(p);
+  u32x4 u = *reinterpret_cast<const u32x4*>(p);
   const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -242,12 +242,67 @@ __device__ inline void store8_any(float* p, const float (&o)[8]) {
   *reinterpret_cast<float4*>(p + 4) = *reinterpret_cast<const float4*>(o + 4);
 }
 __device__ inline void store8_any(bf16_t* p, const float (&o)[8]) {
-  uint4 u;
+  u32x4 u;
   u.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
   u.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
   u.z = (uint32_t)f2bf(o[4]) | ((uint32_t)f2bf(o[5]) << 16);
   u.w = (uint32_t)f2bf(o[6]) | ((uint32_t)f2bf(o[7]) << 16);
-  *reinterpret_cast<uint4*>(p) = u;
+  *reinterpret_cast<u32x4*>(p) = u;
+}
+
+template <bool B> struct BoolTag { static constexpr bool value = B; };
+
+// K loop.  Two register sets: tile t is fetched into set t&1 two steps
+// before it is consumed, so each global load has a full step of MFMA work to
+// hide behind.  LDS is double-buffered with one barrier per step.  All
+// register arrays are indexed with constants so they stay in VGPRs.
+template <typename T, int LA, int LB, bool FAST>
+__device__ __forceinline__ void gemm_mainloop(floatx4 (&acc)[4][4], T* __restrict__ smem,
+                                              const GemmDesc& D, int m0, int n0, int kbeg,
+                                              int kend, int tid, int wm, int wn, int lane) {
+  constexpr int BK = GemmCfg<T>::BK;
+  constexpr int LD = lds_ld<T>();
+  constexpr int STAGE = (kBM + kBN) * LD;
+  const T* __restrict__ A = reinterpret_cast<const T*>(D.A);
+  const T* __restrict__ B = reinterpret_cast<const T*>(D.B);
+  const int nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk == 0) return;
+#define CRL_GLOAD(ra, rb, k0)                                                    \
+  do {                                                                           \
+    if (LA == LAY_KC) load_kc<T, FAST>(ra, A, D.lda, m0, D.M, (k0), kend, tid);  \
+    else              load_mc<T, FAST>(ra, A, D.lda, m0, D.M, (k0), kend, tid);  \
+    if (LB == LAY_KC) load_kc<T, FAST>(rb, B, D.ldb, n0, D.N, (k0), kend, tid);  \
+    else              load_mc<T, FAST>(rb, B, D.ldb, n0, D.N, (k0), kend, tid);  \
+  } while (0)
+#define CRL_SSTORE(ra, rb, buf)                                                  \
+  do {                                                                           \
+    T* As_ = smem + (buf) * STAGE;                                               \
+    T* Bs_ = As_ + kBM * LD;                                                     \
+    if (LA == LAY_KC) store_kc<T>(As_, ra, tid); else store_mc(As_, ra, tid);    \
+    if (LB == LAY_KC) store_kc<T>(Bs_, rb, tid); else store_mc(Bs_, rb, tid);    \
+  } while (0)
+  // rac/rbc held tile kt (already in LDS) and now receive tile kt+2;
+  // ran/rbn hold tile kt+1.
+#define CRL_STEP(kt, rac, rbc, ran, rbn)                                         \
+  do {                                                                           \
+    if ((kt) + 2 < nk) CRL_GLOAD(rac, rbc, kbeg + ((kt) + 2) * BK);             \
+    const T* As_ = smem + ((kt) & 1) * STAGE;                                    \
+    mma_stage(acc, As_, As_ + kBM * LD, wm, wn, lane);                           \
+    if ((kt) + 1 < nk) CRL_SSTORE(ran, rbn, ((kt) + 1) & 1);                     \
+    __syncthreads();                                                             \
+  } while (0)
+  u32x4 ra0[4], rb0[4], ra1[4], rb1[4];
+  CRL_GLOAD(ra0, rb0, kbeg);
+  if (nk > 1) CRL_GLOAD(ra1, rb1, kbeg + BK);
+  CRL_SSTORE(ra0, rb0, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt += 2) {
+    CRL_STEP(kt, ra0, rb0, ra1, rb1);
+    if (kt + 1 < nk) CRL_STEP(kt + 1, ra1, rb1, ra0, rb0);
+  }
+#undef CRL_STEP
+#undef CRL_SSTORE
+#undef CRL_GLOAD
 }
 
 // ---------------------------------------------------------------------------
@@ -287,53 +342,13 @@ void gemm_kernel(GemmParams P) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // Tiles entirely inside M x N (and K steps entirely before kend) take the
-  // unguarded path; edge tiles use element guards.  The choice is uniform
-  // over the workgroup.
-  const bool inner = (m0 + kBM <= D.M) && (n0 + kBN <= D.N);
-  auto gload = [&](uint4 (&ra)[4], uint4 (&rb)[4], int k0) {
-    if (inner && k0 + BK <= kend) {
-      if (LA == LAY_KC) load_kc<T, true>(ra, A, D.lda, m0, D.M, k0, kend, tid);
-      else              load_mc<T, true>(ra, A, D.lda, m0, D.M, k0, kend, tid);
-      if (LB == LAY_KC) load_kc<T, true>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
-      else              load_mc<T, true>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
-    } else {
-      if (LA == LAY_KC) load_kc<T, false>(ra, A, D.lda, m0, D.M, k0, kend, tid);
-      else              load_mc<T, false>(ra, A, D.lda, m0, D.M, k0, kend, tid);
-      if (LB == LAY_KC) load_kc<T, false>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
-      else              load_mc<T, false>(rb, B, D.ldb, n0, D.N, k0, kend, tid);
-    }
-  };
-  auto sstore = [&](const uint4 (&ra)[4], const uint4 (&rb)[4], int buf) {
-    T* As = smem + buf * STAGE;
-    T* Bs = As + kBM * LD;
-    if (LA == LAY_KC) store_kc<T>(As, ra, tid); else store_mc(As, ra, tid);
-    if (LB == LAY_KC) store_kc<T>(Bs, rb, tid); else store_mc(Bs, rb, tid);
-  };
-
-  // Two register sets: tile t is fetched into set t&1 two steps before it is
-  // consumed, so each global load has a full step of MFMA work to hide behind.
-  // LDS is double-buffered with one barrier per step.
-  const int nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
-  uint4 ra0[4], rb0[4], ra1[4], rb1[4];
-  auto step = [&](int kt, uint4 (&rac)[4], uint4 (&rbc)[4], uint4 (&ran)[4], uint4 (&rbn)[4]) {
-    // rac/rbc held tile kt (already in LDS); ran/rbn hold tile kt+1
-    if (kt + 2 < nk) gload(rac, rbc, kbeg + (kt + 2) * BK);
-    const T* As = smem + (kt & 1) * STAGE;
-    mma_stage(acc, As, As + kBM * LD, wm, wn, lane);
-    if (kt + 1 < nk) sstore(ran, rbn, (kt + 1) & 1);
-    __syncthreads();
-  };
-  if (nk > 0) {
-    gload(ra0, rb0, kbeg);
-    if (nk > 1) gload(ra1, rb1, kbeg + BK);
-    sstore(ra0, rb0, 0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; kt += 2) {
-      step(kt, ra0, rb0, ra1, rb1);
-      if (kt + 1 < nk) step(kt + 1, ra1, rb1, ra0, rb0);
-    }
-  }
+  // Workgroups whose tile lies entirely inside M x N, with a K range made of
+  // whole K steps, run the unguarded loop; the others run the guarded one.
+  // The choice is made once per workgroup, so each loop is straight-line code
+  // and the compiler can wait for exactly the loads each LDS store needs.
+  const bool fast = (m0 + kBM <= D.M) && (n0 + kBN <= D.N) && ((kend - kbeg) % BK == 0);
+  if (fast) gemm_mainloop<T, LA, LB, true>(acc, smem, D, m0, n0, kbeg, kend, tid, wm, wn, lane);
+  else      gemm_mainloop<T, LA, LB, false>(acc, smem, D, m0, n0, kbeg, kend, tid, wm, wn, lane);
 
   // Epilogue.  Row/column-only operations (scale, bias, ReLU, L2) are applied
   // in registers; the 128 x 128 FP32 tile is then staged through LDS so that

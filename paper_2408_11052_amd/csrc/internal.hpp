@@ -73,9 +73,12 @@ hipError_t launch_colsum(const ColSumArgs& a, int count, int B, int N, int ld,
 
 hipError_t launch_sqnorm(const float* X, float* out, int B, int D, hipStream_t s);
 hipError_t launch_cast_bf16(const float* src, bf16_t* dst, int64_t n, hipStream_t s);
+// Adam coefficients: 1 - b and log b are formed in double on the host.
+struct AdamCoef {
+  float lr, b1, b2, omb1, omb2, log_b1, log_b2, eps;
+};
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, bf16_t* pb,
-                       int64_t n, const int64_t* step, float lr, float b1, float b2,
-                       float eps, hipStream_t s);
+                       int64_t n, const int64_t* step, const AdamCoef& c, hipStream_t s);
 hipError_t launch_counter_add(int64_t* c, int64_t inc, hipStream_t s);
 hipError_t launch_zero_ranges(float* base, const int64_t* ranges, int nranges,
                               hipStream_t s);

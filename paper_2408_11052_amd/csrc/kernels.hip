@@ -452,17 +452,15 @@ hipError_t launch_cast_bf16(const float* src, bf16_t* dst, int64_t n, hipStream_
   return hipGetLastError();
 }
 
-// Adam on a flat vector; bias corrections 1 - b^t = -expm1(t log b), which
-// keeps full FP32 relative accuracy (no cancellation in 1 - b^t).
+// Adam on a flat vector.  Bias corrections 1 - b^t = -expm1(t log b) keep
+// full FP32 relative accuracy (no cancellation in 1 - b^t).
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v,
                                                    bf16_t* __restrict__ pb, int64_t n,
-                                                   const int64_t* __restrict__ step, float lr,
-                                                   float b1, float b2, float eps) {
+                                                   const int64_t* __restrict__ step, AdamCoef c) {
   const float t = (float)(*step);
-  const float bc1 = -expm1f(t * logf(b1));
-  const float bc2 = -expm1f(t * logf(b2));
-  const float c1 = 1.f / bc1, c2 = 1.f / bc2;
+  const float c1 = 1.f / (-expm1f(t * c.log_b1));
+  const float c2 = 1.f / (-expm1f(t * c.log_b2));
   const int64_t n4 = n >> 2;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -473,9 +471,9 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const 
     float* pa = &pp.x; float* ga = &gg.x; float* ma = &mm.x; float* va = &vv.x;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      ma[k] = b1 * ma[k] + (1.f - b1) * ga[k];
-      va[k] = b2 * va[k] + (1.f - b2) * ga[k] * ga[k];
-      pa[k] -= lr * (ma[k] * c1) / (sqrtf(va[k] * c2) + eps);
+      ma[k] = c.b1 * ma[k] + c.omb1 * ga[k];
+      va[k] = c.b2 * va[k] + c.omb2 * ga[k] * ga[k];
+      pa[k] -= c.lr * (ma[k] * c1) / (sqrtf(va[k] * c2) + c.eps);
     }
     reinterpret_cast<float4*>(p)[i] = pp;
     reinterpret_cast<float4*>(m)[i] = mm;
@@ -489,21 +487,20 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const 
   }
   if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
     int64_t k = n4 * 4 + threadIdx.x;
-    float mk = b1 * m[k] + (1.f - b1) * g[k];
-    float vk = b2 * v[k] + (1.f - b2) * g[k] * g[k];
+    float mk = c.b1 * m[k] + c.omb1 * g[k];
+    float vk = c.b2 * v[k] + c.omb2 * g[k] * g[k];
     m[k] = mk; v[k] = vk;
-    p[k] -= lr * (mk * c1) / (sqrtf(vk * c2) + eps);
+    p[k] -= c.lr * (mk * c1) / (sqrtf(vk * c2) + c.eps);
     if (pb) pb[k] = f2bf(p[k]);
   }
 }
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, bf16_t* pb, int64_t n,
-                       const int64_t* step, float lr, float b1, float b2, float eps,
-                       hipStream_t s) {
+                       const int64_t* step, const AdamCoef& c, hipStream_t s) {
   int64_t blocks = (n / 4 + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 16384) blocks = 16384;
   CRL_TIMED("adam_kernel", 0.0, (28.0 + (pb ? 2.0 : 0.0)) * n, s,
-            adam_kernel<<<(int)blocks, 256, 0, s>>>(p, g, m, v, pb, n, step, lr, b1, b2, eps));
+            adam_kernel<<<(int)blocks, 256, 0, s>>>(p, g, m, v, pb, n, step, c));
   return hipGetLastError();
 }
 
