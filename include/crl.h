@@ -71,7 +71,7 @@ typedef struct crl_config {
   int32_t goal_dim;       /* d_g: goal = obs[goal_lo : goal_lo + d_g] */
   int32_t goal_lo;
   int32_t n_hidden;       /* hidden layers per encoder (>= 1) */
-  int32_t hidden;         /* hidden width (multiple of 8) */
+  int32_t hidden;         /* hidden width (multiple of 8, at most 1024) */
   int32_t repr_dim;       /* D, multiple of 8 (fused logits: 64 or 256) */
   int32_t activation;     /* CRL_ACT_* : ReLU, or LayerNorm then Swish */
   int32_t energy;         /* CRL_ENERGY_*: <phi,psi> or -||phi - psi||_2 */
@@ -166,12 +166,16 @@ CRL_API int crl_critic_bwd(crl_ctx* ctx, const float* params,
  * gradient steps of Algorithm 1:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
  *   p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
- * with t = *step (device int64, t >= 1, read only).  If p_bf16 is not NULL
- * the BF16 copy of the new p is written there too.  p, g, m, v, p_bf16 must
+ * with t = *step (device int64, t >= 1, read only).  The hyperparameters
+ * are given in double; 1 - b1, 1 - b2 and log b1, log b2 are formed on the
+ * host in double and used in FP32 on the device, so (1 - b2) carries no FP32
+ * representation error of b2.  If p_bf16 is not NULL the BF16 copy of the new
+ * p is written there too.  p, g, m, v, p_bf16 must
  * be 16-byte aligned. */
 CRL_API int crl_adam_step(float* p, const float* g, float* m, float* v,
                           uint16_t* p_bf16, int64_t n, const int64_t* step,
-                          float lr, float b1, float b2, float eps, void* stream);
+                          double lr, double b1, double b2, double eps,
+                          void* stream);
 
 /* *counter += inc on the device (stream-ordered; for step counters that a
  * captured graph advances on every replay). */

@@ -80,8 +80,8 @@ int validate(const crl_config* c) {
   if (c->goal_lo < 0 || c->goal_lo + c->goal_dim > c->obs_dim)
     return fail(CRL_EINVAL, "goal slice [goal_lo, goal_lo + goal_dim) outside the observation");
   if (c->n_hidden < 1 || c->n_hidden > 16) return fail(CRL_EINVAL, "n_hidden must be in [1, 16]");
-  if (c->hidden < 8 || c->hidden % 8 || c->hidden > 2048)
-    return fail(CRL_EINVAL, "hidden must be a multiple of 8 in [8, 2048]");
+  if (c->hidden < 8 || c->hidden % 8 || c->hidden > 1024)
+    return fail(CRL_EINVAL, "hidden must be a multiple of 8 in [8, 1024]");
   if (c->repr_dim < 8 || c->repr_dim % 8 || c->repr_dim > 1024)
     return fail(CRL_EINVAL, "repr_dim must be a multiple of 8 in [8, 1024]");
   if (c->activation != CRL_ACT_RELU && c->activation != CRL_ACT_LN_SWISH)

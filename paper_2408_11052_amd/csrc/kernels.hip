@@ -190,56 +190,108 @@ hipError_t launch_ln_swish_fwd(const LnArgs& a, int count, int B, int N, float e
   return hipGetLastError();
 }
 
-// Backward of h = Swish(g * zhat + b), zhat = (z - mu) * rstd, one
-// wavefront per row: dy = dh * Swish'(y), dzhat = g * dy and
-// dz = rstd * (dzhat - mean(dzhat) - zhat * mean(dzhat * zhat)).
+// Backward of h = Swish(g * zhat + b), zhat = (z - mu) * rstd.  Each
+// workgroup owns kLnRows rows (kLnRows / 4 per wavefront, one row at a time):
+//   dy = dh * Swish'(y), dzhat = g * dy,
+//   dz = rstd * (dzhat - mean(dzhat) - zhat * mean(dzhat * zhat)),
+// and it accumulates the column sums dg = sum dy*zhat, db_ln = sum dy,
+// db_linear = sum dz of its rows; the four wavefronts' sums are added in LDS
+// in a fixed order and written as one partial row per workgroup.
+constexpr int kLnRows = 16;
+
 template <typename T, int CH>
-__global__ __launch_bounds__(256) void ln_swish_bwd_rows_kernel(LnArgs a, int B, int N) {
+__global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int N) {
+  extern __shared__ float red[];  // [4 waves][3][N]
   const int e = blockIdx.y;
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= B) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nch = N >> 3;
-  const T* Zr = reinterpret_cast<const T*>(a.Z[e]) + (int64_t)row * N;
-  const T* dHr = reinterpret_cast<const T*>(a.dH[e]) + (int64_t)row * N;
-  T* dZr = reinterpret_cast<T*>(a.dZ[e]) + (int64_t)row * N;
-  const float mu = a.mu[e][row], rstd = a.rstd[e][row];
-  float zh[CH][8], dzh[CH][8];
-  float s1 = 0.f, s2 = 0.f;
+  float gv[CH][8], bv[CH][8], cg[CH][8], cb[CH][8], cz[CH][8];
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     const int ch = lane + 64 * c;
-    if (ch < nch) {
-      float z[8], dh[8], gv[8], bv[8];
-      load8(Zr + ch * 8, z);
-      load8(dHr + ch * 8, dh);
-      load8(a.g[e] + ch * 8, gv);
-      load8(a.b[e] + ch * 8, bv);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float xh = (z[i] - mu) * rstd;
-        const float y = gv[i] * xh + bv[i];
-        const float sg = sigmoidf_(y);
-        const float d = dh[i] * (sg * (1.f + y * (1.f - sg))) * gv[i];
-        zh[c][i] = xh;
-        dzh[c][i] = d;
-        s1 += d;
-        s2 += d * xh;
+    for (int i = 0; i < 8; ++i) { cg[c][i] = cb[c][i] = cz[c][i] = gv[c][i] = bv[c][i] = 0.f; }
+    if (ch < nch) { load8(a.g[e] + ch * 8, gv[c]); load8(a.b[e] + ch * 8, bv[c]); }
+  }
+  const T* Zb = reinterpret_cast<const T*>(a.Z[e]);
+  const T* dHb = reinterpret_cast<const T*>(a.dH[e]);
+  T* dZb = reinterpret_cast<T*>(a.dZ[e]);
+  const int r0 = blockIdx.x * kLnRows + wave * (kLnRows / 4);
+  const int r1 = min(B, r0 + kLnRows / 4);
+  for (int row = r0; row < r1; ++row) {
+    const float mu = a.mu[e][row], rstd = a.rstd[e][row];
+    float zh[CH][8], dzh[CH][8];
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int ch = lane + 64 * c;
+      if (ch < nch) {
+        float z[8], dh[8];
+        load8(Zb + (int64_t)row * N + ch * 8, z);
+        load8(dHb + (int64_t)row * N + ch * 8, dh);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float xh = (z[i] - mu) * rstd;
+          const float y = gv[c][i] * xh + bv[c][i];
+          const float sg = sigmoidf_(y);
+          const float dy = dh[i] * (sg * (1.f + y * (1.f - sg)));
+          cg[c][i] += dy * xh;
+          cb[c][i] += dy;
+          const float d = dy * gv[c][i];
+          zh[c][i] = xh;
+          dzh[c][i] = d;
+          s1 += d;
+          s2 += d * xh;
+        }
+      }
+    }
+    const float m1 = wave_sum(s1) / (float)N;
+    const float m2 = wave_sum(s2) / (float)N;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int ch = lane + 64 * c;
+      if (ch < nch) {
+        float o[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          o[i] = rstd * (dzh[c][i] - m1 - zh[c][i] * m2);
+          cz[c][i] += o[i];
+        }
+        store8(dZb + (int64_t)row * N + ch * 8, o);
       }
     }
   }
-  const float m1 = wave_sum(s1) / (float)N;
-  const float m2 = wave_sum(s2) / (float)N;
+  float* mine = red + (int64_t)wave * 3 * N;
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     const int ch = lane + 64 * c;
     if (ch < nch) {
-      float o[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) o[i] = rstd * (dzh[c][i] - m1 - zh[c][i] * m2);
-      store8(dZr + ch * 8, o);
+      store8(mine + ch * 8, cg[c]);
+      store8(mine + N + ch * 8, cb[c]);
+      store8(mine + 2 * N + ch * 8, cz[c]);
     }
   }
+  __syncthreads();
+  float* part = a.part[e] + (int64_t)blockIdx.x * 3 * N;
+  for (int k = threadIdx.x; k < 3 * N; k += 256)
+    part[k] = (red[k] + red[3 * N + k]) + (red[6 * N + k] + red[9 * N + k]);
+}
+
+int ln_bwd_partials(int B, int) { return (B + kLnRows - 1) / kLnRows; }
+
+hipError_t launch_ln_swish_bwd(const LnArgs& a, int count, int B, int N, bool bf16, int,
+                               hipStream_t s) {
+  const int ch = (N / 8 + 63) / 64;
+  const int nparts = ln_bwd_partials(B, 0);
+  dim3 grid(nparts, count), block(256);
+  const size_t lds = (size_t)4 * 3 * N * sizeof(float);
+  const double bytes = (double)count * ((double)B * N * 3.0 * (bf16 ? 2 : 4) + 12.0 * nparts * N);
+#define LNB(T, C) CRL_TIMED("ln_swish_bwd_kernel", 0.0, bytes, s, \
+                            ln_swish_bwd_kernel<T, C><<<grid, block, lds, s>>>(a, B, N))
+  if (bf16) { if (ch <= 1) LNB(bf16_t, 1); else if (ch <= 2) LNB(bf16_t, 2); else LNB(bf16_t, 4); }
+  else      { if (ch <= 1) LNB(float, 1);  else if (ch <= 2) LNB(float, 2);  else LNB(float, 4); }
+#undef LNB
+  return hipGetLastError();
 }
 
 // 4-element chunks for the column kernels
@@ -255,113 +307,37 @@ __device__ inline void load4(const bf16_t* p, float (&o)[4]) {
   o[3] = __builtin_bit_cast(float, u.y & 0xffff0000u);
 }
 
-constexpr int kColRows = 128;  // rows per chunk of the column kernels
-
-// Column partial sums over one chunk of rows of the LayerNorm parameters'
-// gradients: dg = sum dy*zhat, db_ln = sum dy, db_linear = sum dz.
-// Block = 64 lanes x 4 columns (256 columns) x 4 wavefronts splitting the rows.
-template <typename T>
-__global__ __launch_bounds__(256) void ln_swish_bwd_cols_kernel(LnArgs a, int B, int N) {
-  __shared__ float red[3][4][256];
-  const int e = blockIdx.z;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int n0 = blockIdx.x * 256 + lane * 4;
-  const int r0 = blockIdx.y * kColRows, r1 = min(B, r0 + kColRows);
-  float sg_[4] = {0, 0, 0, 0}, sb_[4] = {0, 0, 0, 0}, sz_[4] = {0, 0, 0, 0};
-  if (n0 < N) {
-    float gv[4], bv[4];
-    load4(a.g[e] + n0, gv);
-    load4(a.b[e] + n0, bv);
-    const T* Zb = reinterpret_cast<const T*>(a.Z[e]);
-    const T* dHb = reinterpret_cast<const T*>(a.dH[e]);
-    const T* dZb = reinterpret_cast<const T*>(a.dZ[e]);
-    for (int row = r0 + wave; row < r1; row += 4) {
-      const float mu = a.mu[e][row], rstd = a.rstd[e][row];
-      float z[4], dh[4], dz[4];
-      load4(Zb + (int64_t)row * N + n0, z);
-      load4(dHb + (int64_t)row * N + n0, dh);
-      load4(dZb + (int64_t)row * N + n0, dz);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float xh = (z[i] - mu) * rstd;
-        const float y = gv[i] * xh + bv[i];
-        const float sg = sigmoidf_(y);
-        const float dy = dh[i] * (sg * (1.f + y * (1.f - sg)));
-        sg_[i] += dy * xh;
-        sb_[i] += dy;
-        sz_[i] += dz[i];
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    red[0][wave][lane * 4 + i] = sg_[i];
-    red[1][wave][lane * 4 + i] = sb_[i];
-    red[2][wave][lane * 4 + i] = sz_[i];
-  }
-  __syncthreads();
-  const int t = threadIdx.x;
-  const int n = blockIdx.x * 256 + t;
-  if (n < N) {
-    float* part = a.part[e] + (int64_t)blockIdx.y * 3 * N;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      part[(int64_t)k * N + n] = (red[k][0][t] + red[k][1][t]) + (red[k][2][t] + red[k][3][t]);
-  }
-}
-
-int ln_bwd_partials(int B, int) { return (B + kColRows - 1) / kColRows; }
-
-hipError_t launch_ln_swish_bwd(const LnArgs& a, int count, int B, int N, bool bf16, int,
-                               hipStream_t s) {
-  const int ch = (N / 8 + 63) / 64;
-  const double es = bf16 ? 2.0 : 4.0;
-  {
-    dim3 grid((B + 3) / 4, count), block(256);
-    const double bytes = (double)count * B * N * 3.0 * es;
-#define LNB(T, C) CRL_TIMED("ln_swish_bwd_rows_kernel", 0.0, bytes, s, \
-                            ln_swish_bwd_rows_kernel<T, C><<<grid, block, 0, s>>>(a, B, N))
-    if (bf16) { if (ch <= 1) LNB(bf16_t, 1); else if (ch <= 2) LNB(bf16_t, 2); else LNB(bf16_t, 4); }
-    else      { if (ch <= 1) LNB(float, 1);  else if (ch <= 2) LNB(float, 2);  else LNB(float, 4); }
-#undef LNB
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  const int nparts = ln_bwd_partials(B, 0);
-  dim3 grid((N + 255) / 256, nparts, count), block(256);
-  const double bytes = (double)count * ((double)B * N * 3.0 * es + 12.0 * nparts * N);
-  if (bf16) CRL_TIMED("ln_swish_bwd_cols_kernel", 0.0, bytes, s,
-                      ln_swish_bwd_cols_kernel<bf16_t><<<grid, block, 0, s>>>(a, B, N));
-  else      CRL_TIMED("ln_swish_bwd_cols_kernel", 0.0, bytes, s,
-                      ln_swish_bwd_cols_kernel<float><<<grid, block, 0, s>>>(a, B, N));
-  return hipGetLastError();
-}
+constexpr int kColRows = 128;  // rows per chunk of the column-sum kernel
 
 // out[k][n] = sum over w of part[w][k][n]: 64 outputs per block, the parts
-// split over 4 wavefronts (w = grp, grp + 4, ...) and combined in LDS in a
+// split over 16 wavefronts (w = grp, grp + 16, ...) and combined in LDS in a
 // fixed order.
-__global__ __launch_bounds__(256) void partial_reduce_kernel(ColReduceArgs a, int nparts,
-                                                             int nk, int N) {
-  __shared__ float red[4][64];
+__global__ __launch_bounds__(1024) void partial_reduce_kernel(ColReduceArgs a, int nparts,
+                                                              int nk, int N) {
+  __shared__ float red[16][64];
   const int e = blockIdx.y;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
   float s = 0.f;
   if (i < nk * N) {
     const float* p = a.part[e] + i;
-    for (int w = grp; w < nparts; w += 4) s += p[(int64_t)w * nk * N];
+    for (int w = grp; w < nparts; w += 16) s += p[(int64_t)w * nk * N];
   }
   red[grp][lane] = s;
   __syncthreads();
+  for (int h = 8; h >= 1; h >>= 1) {
+    if (grp < h) red[grp][lane] += red[grp + h][lane];
+    __syncthreads();
+  }
   if (grp == 0 && i < nk * N) {
     const int k = i / N, n = i % N;
-    a.out[e][k][n] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    a.out[e][k][n] = red[0][lane];
   }
 }
 
 hipError_t launch_partial_reduce(const ColReduceArgs& a, int count, int nparts, int nk,
                                  int N, hipStream_t s) {
-  dim3 grid((nk * N + 63) / 64, count), block(256);
+  dim3 grid((nk * N + 63) / 64, count), block(1024);
   CRL_TIMED("partial_reduce_kernel", 0.0, 4.0 * count * (nparts + 1.0) * nk * N, s,
             partial_reduce_kernel<<<grid, block, 0, s>>>(a, nparts, nk, N));
   return hipGetLastError();

@@ -52,6 +52,7 @@ def _create(**kw):
 @pytest.mark.parametrize("field,value,msg", [
     ("batch", 0, "batch"),
     ("hidden", 100, "hidden"),
+    ("hidden", 2048, "hidden"),
     ("repr_dim", 12, "repr_dim"),
     ("goal_lo", 28, "goal slice"),
     ("energy", 7, "energy"),
