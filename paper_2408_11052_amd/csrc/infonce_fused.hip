@@ -58,16 +58,54 @@ __global__ void fused_prep_kernel(FusedArgs a, int B, int D) {
   if (lane == 0) nrm[row] = s;
 }
 
-// Stage a 64-row tile of Y [B][D] (BF16) into LDS rows [64][LDY]; rows past B are 0.
-template <int D, int LDY>
-__device__ inline void stage_rows(bf16_t* __restrict__ Ys, const bf16_t* __restrict__ Y, int j0,
-                                  int B, int tid) {
+// A 64-row tile of Y [B][D] (BF16) moves global -> registers -> LDS.  Each
+// of the 256 threads holds D/32 16-byte vectors; rows past B are zero.  The
+// next tile is fetched into registers while the current one is computed on.
+template <int D>
+struct TileRegs { u32x4 v[D / 32]; };
+
+template <int D>
+__device__ __forceinline__ void tile_load(TileRegs<D>& t, const bf16_t* __restrict__ Y, int j0,
+                                          int B, int tid) {
   constexpr int VPR = D / 8;  // 16-byte vectors per row
-  for (int v = tid; v < kFCols * VPR; v += 256) {
-    int r = v / VPR, c = v % VPR;
-    uint4 val = {0u, 0u, 0u, 0u};
-    if (j0 + r < B) val = *reinterpret_cast<const uint4*>(Y + (int64_t)(j0 + r) * D + c * 8);
-    *reinterpret_cast<uint4*>(Ys + r * LDY + c * 8) = val;
+#pragma unroll
+  for (int i = 0; i < D / 32; ++i) {
+    const int v = tid + i * 256;
+    const int r = v / VPR, c = v % VPR;
+    u32x4 val = {0u, 0u, 0u, 0u};
+    if (j0 + r < B) val = *reinterpret_cast<const u32x4*>(Y + (int64_t)(j0 + r) * D + c * 8);
+    t.v[i] = val;
+  }
+}
+
+// rows layout Ys[r][d] (stride LDY)
+template <int D, int LDY>
+__device__ __forceinline__ void tile_store_rows(bf16_t* __restrict__ Ys, const TileRegs<D>& t,
+                                                int tid) {
+  constexpr int VPR = D / 8;
+#pragma unroll
+  for (int i = 0; i < D / 32; ++i) {
+    const int v = tid + i * 256;
+    const int r = v / VPR, c = v % VPR;
+    *reinterpret_cast<u32x4*>(Ys + r * LDY + c * 8) = t.v[i];
+  }
+}
+
+// transposed layout YsT[d][r] (stride LDT)
+template <int D, int LDT>
+__device__ __forceinline__ void tile_store_cols(bf16_t* __restrict__ YsT, const TileRegs<D>& t,
+                                                int tid) {
+  constexpr int VPR = D / 8;
+#pragma unroll
+  for (int i = 0; i < D / 32; ++i) {
+    const int v = tid + i * 256;
+    const int r = v / VPR, c = v % VPR;
+    const u32x4 w = t.v[i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      YsT[(c * 8 + 2 * q) * LDT + r] = (bf16_t)(w[q] & 0xffffu);
+      YsT[(c * 8 + 2 * q + 1) * LDT + r] = (bf16_t)(w[q] >> 16);
+    }
   }
 }
 
@@ -104,9 +142,23 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
     rsum[r] = 0.f;
   }
 
+  // column (max, sum) partials of the previous tile, merged over the 4 waves
+  auto flush_cols = [&](int jp) {
+    if (tid < kFCols && jp + tid < c1) {
+      float cm = cm_s[0][tid], cs = cs_s[0][tid];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) lse_merge(cm, cs, cm_s[w][tid], cs_s[w][tid]);
+      a.col_m[(int64_t)rb * B + jp + tid] = cm;
+      a.col_s[(int64_t)rb * B + jp + tid] = cs;
+    }
+  };
+  TileRegs<D> pf;
+  if (c0 < c1) tile_load<D>(pf, a.psi_b, c0, B, tid);
   for (int j0 = c0; j0 < c1; j0 += kFCols) {
     __syncthreads();
-    stage_rows<D, LDY>(Ys, a.psi_b, j0, B, tid);
+    if (j0 > c0) flush_cols(j0 - kFCols);
+    tile_store_rows<D, LDY>(Ys, pf, tid);
+    if (j0 + kFCols < c1) tile_load<D>(pf, a.psi_b, j0 + kFCols, B, tid);
     __syncthreads();
     floatx4 acc[4];
 #pragma unroll
@@ -147,7 +199,8 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
         for (int jb = 0; jb < 4; ++jb) rsum[r] += __expf(f[jb][r] - rm[r]);
       }
     }
-    // columns: (max, sum) over this wave's 16 rows, then over the 4 waves
+    // columns: (max, sum) over this wave's 16 rows; the 4 waves are merged
+    // by flush_cols after the next barrier
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
       float cm = fmaxf(fmaxf(f[jb][0], f[jb][1]), fmaxf(f[jb][2], f[jb][3]));
@@ -163,14 +216,10 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
       }
       if (g == 0) { cm_s[wave][jb * 16 + r16] = cm; cs_s[wave][jb * 16 + r16] = cs; }
     }
+  }
+  if (c0 < c1) {
     __syncthreads();
-    if (tid < kFCols && j0 + tid < c1) {
-      float cm = cm_s[0][tid], cs = cs_s[0][tid];
-#pragma unroll
-      for (int w = 1; w < 4; ++w) lse_merge(cm, cs, cm_s[w][tid], cs_s[w][tid]);
-      a.col_m[(int64_t)rb * B + j0 + tid] = cm;
-      a.col_s[(int64_t)rb * B + j0 + tid] = cs;
-    }
+    flush_cols(c0 + ((c1 - c0 - 1) / kFCols) * kFCols);
   }
   // merge the row states across the 16 lanes that share each row
 #pragma unroll
@@ -239,18 +288,13 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) acc_dx[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+  TileRegs<D> pf;
+  if (c0 < c1) tile_load<D>(pf, Yb, c0, B, tid);
   for (int j0 = c0; j0 < c1; j0 += kFCols) {
     __syncthreads();
-    stage_rows<D, LDY>(Ys, Yb, j0, B, tid);
-    // transposed copy YsT[d][j]
-    for (int v = tid; v < kFCols * (D / 8); v += 256) {
-      int r = v / (D / 8), c = v % (D / 8);
-      uint4 val = {0u, 0u, 0u, 0u};
-      if (j0 + r < B) val = *reinterpret_cast<const uint4*>(Yb + (int64_t)(j0 + r) * D + c * 8);
-      const bf16_t* e = reinterpret_cast<const bf16_t*>(&val);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) YsT[(c * 8 + i) * LDT + r] = e[i];
-    }
+    tile_store_rows<D, LDY>(Ys, pf, tid);
+    tile_store_cols<D, LDT>(YsT, pf, tid);
+    if (j0 + kFCols < c1) tile_load<D>(pf, Yb, j0 + kFCols, B, tid);
     __syncthreads();
     floatx4 acc[4];
 #pragma unroll
