@@ -47,9 +47,18 @@ def parse():
     ap.add_argument("--fp32-steps", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--full-workload", default="b4096_full_update_actor4x1024")
+    ap.add_argument("--full-steps", type=int, default=1000,
+                    help="consecutive full updates (critic, policy, alpha) timed")
+    ap.add_argument("--full-graph-steps", type=int, default=100)
+    ap.add_argument("--no-full", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="N",
+                    help="only run crl_cast_bf16 over N floats 10 times (reads 4N, writes "
+                         "2N bytes per launch): the known-size kernel that scales the HBM "
+                         "byte counters of a profiler run, then exit")
     return ap.parse_args()
 
 
@@ -126,6 +135,54 @@ def cpu_baseline(w, obs, act, phi, psi, budget_s):
                       f"same workload in {dt:.1f} s"}
 
 
+def csrc_digest() -> str:
+    """sha256 over the library's kernel sources (HBM counters taken for one
+    version of the kernels do not describe another)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2408_11052_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/hbm_traffic_b4096.txt: FETCH_SIZE and WRITE_SIZE per dispatch,
+    scaled by the copy calibration), or None if there is none for this kernel
+    or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_b4096.txt")
+    if not os.path.exists(path):
+        return None
+    src = None
+    rows = {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("csrc_sha256_16 "):
+            src = line.split()[1]
+        elif line.startswith("kernel "):
+            parts = dict(p.split("=", 1) for p in line.split()[1:])
+            rows[parts["name"]] = parts
+    if src != csrc_digest() or kernel not in rows:
+        return None
+    return float(rows[kernel]["hbm_bytes_per_launch"])
+
+
+def copy_calibration(n):
+    import torch
+    from paper_2408_11052_amd import crl_cast_bf16
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty(n, dtype=torch.bfloat16, device="cuda:0")
+    torch.cuda.synchronize()
+    for _ in range(10):
+        crl_cast_bf16(src, dst)
+    torch.cuda.synchronize()
+    log(f"[calibration] crl_cast_bf16 over {n} floats x10: reads {4 * n} B, writes {2 * n} B "
+        f"per launch")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -142,6 +199,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     w = WORKLOADS[args.workload]
     log(f"[bench] workload {w.name}: generating the replay buffer "
         f"({w.num_envs} x {w.episode_len} x {w.obs_dim})")
@@ -191,13 +251,13 @@ def main():
             roofline = {"bound": "mfma", "kernel": name, "achieved": round(ach, 2),
                         "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
                         "flops_per_launch": kfl / la, "us_per_launch": 1e3 * kms / la,
-                        "traffic": None}
+                        "traffic": measured_traffic(name)}
         else:
             ach = kby / la / (kms * 1e-3 / la) / 1e9
             roofline = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1),
                         "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
                         "bytes_per_launch": kby / la, "us_per_launch": 1e3 * kms / la,
-                        "traffic": None}
+                        "traffic": measured_traffic(name)}
     upd.close()
     del upd
     torch.cuda.empty_cache()
@@ -215,6 +275,35 @@ def main():
         log(f"[bench] FP32 plain: {nf / dtf:.1f} steps/s eager, {ng / dtg:.1f} steps/s graph")
         upf.close()
         del upf
+        torch.cuda.empty_cache()
+
+    full = None
+    if not args.no_full:
+        from paper_2408_11052_amd.update import FullUpdate, actor_step_flops
+        from synthetic import actor_params
+        wa = WORKLOADS[args.full_workload]
+        assert (wa.num_envs, wa.episode_len, wa.obs_dim, wa.act_dim) == \
+            (w.num_envs, w.episode_len, w.obs_dim, w.act_dim), "full update needs the same buffer"
+        pa, qa = critic_params_for(wa, seed=1)
+        actor = actor_params(wa.in_sg, wa.actor_hidden, wa.act_dim,
+                             wa.activation == "ln_swish", seed=3)
+        fu = FullUpdate(wa, d_obs, d_act, pa, qa, actor, seed=2)
+        fl = critic_step_flops(wa)["total"] + actor_step_flops(wa)["total"]
+        log(f"[bench] full update {wa.name}: {fu.crit.nparam_actor} policy params; "
+            f"{args.full_steps} steps from graphs of {args.full_graph_steps}")
+        dfu, nfu = time_steps(fu, args.full_steps, 2, args.full_graph_steps)
+        full = {"workload": wa.name, "steps": nfu, "graph_steps": args.full_graph_steps,
+                "steps_per_s": round(nfu / dfu, 2), "ms_per_step": round(1e3 * dfu / nfu, 4),
+                "gflop_per_step": round(fl / 1e9, 3),
+                "tflops": round(fl * nfu / dfu / 1e12, 2),
+                "critic_loss": round(float(fu.loss[0]), 5),
+                "actor_loss": round(float(fu.actor_loss[0]), 5),
+                "log_alpha": round(float(fu.log_alpha[0]), 5)}
+        log(f"[bench] full update: {nfu / dfu:.1f} steps/s, {1e3 * dfu / nfu:.3f} ms/step, "
+            f"{fl * nfu / dfu / 1e12:.1f} TFLOP/s; after {int(fu.n.item())} steps critic "
+            f"{full['critic_loss']}, actor {full['actor_loss']}, log alpha {full['log_alpha']}")
+        fu.close()
+        del fu
         torch.cuda.empty_cache()
 
     cpu = None
@@ -250,6 +339,7 @@ def main():
         "fp32_plain": fp32,
         "speedup_vs_fp32_plain": round(sps / fp32["steps_per_s"], 2) if fp32 else None,
         "peak_hbm_gib": round(peak_mem, 2),
+        "full_update": full,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

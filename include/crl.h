@@ -14,6 +14,9 @@
  *   3. the gradient of that loss w.r.t. every encoder parameter
  *                                                          -> crl_critic_bwd
  *   4. the optimiser step on the flat parameter vector     -> crl_adam_step
+ * and, when the context has a policy, the policy step that follows the critic
+ * step on the same batch (Section 2.2 policy learning; Algorithm 1, policy
+ * update; Section 4 setup, tunable entropy coefficient)   -> crl_actor_step
  *
  * Conventions shared by every call
  *  - Pointers named "device" point to device memory on the current HIP device;
@@ -35,7 +38,9 @@
  * first, then psi's; each layer holds W [fan_in][fan_out], b [fan_out] and,
  * for LayerNorm layers, ln_g [fan_out] and ln_b [fan_out].  Every tensor
  * starts at an element offset that is a multiple of 64; the gaps are padding
- * whose gradient is written as 0.
+ * whose gradient is written as 0.  The policy's layers live in a second flat
+ * vector of the same form (crl_actor_param_count), since they have their own
+ * optimiser state and learning rate.
  */
 #ifndef CRL_H
 #define CRL_H
@@ -82,7 +87,11 @@ typedef struct crl_config {
   float ln_eps;           /* LayerNorm epsilon (added to the variance) */
   double discount;        /* gamma in (0,1) of the relabel offset law */
   int32_t max_episode_len;/* longest episode crl_sample_relabel will see */
-  int32_t reserved[7];    /* must be zero */
+  int32_t actor_n_hidden; /* hidden layers of the policy MLP; 0 = no policy */
+  int32_t actor_hidden;   /* its width (multiple of 8, at most 1024); 0 without */
+  float target_entropy;   /* H of the entropy-coefficient objective (-act_dim
+                             is the usual choice); used with a policy only */
+  int32_t reserved[4];    /* must be zero */
 } crl_config;
 
 typedef struct crl_ctx crl_ctx;
@@ -100,10 +109,17 @@ CRL_API int crl_destroy(crl_ctx* ctx);
 
 /* Number of floats of the flat parameter (and gradient, Adam m, v) vector. */
 CRL_API int crl_param_count(const crl_ctx* ctx, int64_t* n);
-/* Offsets of layer `layer` (0 = first) of encoder 0 (phi) or 1 (psi). */
-CRL_API int crl_layer_layout(const crl_ctx* ctx, int32_t encoder, int32_t layer,
+/* Number of floats of the policy's flat parameter vector (0 without one). */
+CRL_API int crl_actor_param_count(const crl_ctx* ctx, int64_t* n);
+/* Offsets of layer `layer` (0 = first) of net 0 (phi) or 1 (psi), in the
+ * critic vector, or of net 2 (the policy), in the policy vector.  The policy's
+ * output layer has fan_out = 2 act_dim rounded up to a multiple of 8: columns
+ * [0, act_dim) are the mean, [act_dim, 2 act_dim) the scale pre-activation,
+ * the rest padding whose gradient is 0 (zero-initialised, it stays 0). */
+CRL_API int crl_layer_layout(const crl_ctx* ctx, int32_t net, int32_t layer,
                              crl_layer_info* out);
-/* Bytes of the device workspace that crl_critic_fwd / _bwd use (256-aligned). */
+/* Bytes of the device workspace that crl_critic_fwd / _bwd and crl_actor_step
+ * use (256-aligned). */
 CRL_API int crl_workspace_size(const crl_ctx* ctx, int64_t* bytes);
 /* Row strides (elements) of the encoder inputs x_sa [B][ld_sa], x_g [B][ld_g],
  * x_sg [B][ld_sg], and their element size: 4 (FP32) or 2 (BF16).  Columns
@@ -162,6 +178,43 @@ CRL_API int crl_critic_bwd(crl_ctx* ctx, const float* params,
                            const void* x_g, void* ws, float* grads,
                            void* stream);
 
+/* Policy step (Section 2.2, the policy objective; Algorithm 1 takes it after
+ * the critic update, on the same batch; Section 4 setup, SAC-style tunable
+ * entropy coefficient).  With the critic frozen at `params`:
+ *   o = pi_MLP(x_sg) = [mu | rho | pad],  sigma = softplus(rho) + 1e-3,
+ *   u = mu + sigma eps,  a' = tanh(u),
+ *   log pi = sum_k [log N(u_k; mu_k, sigma_k) - log(1 - tanh^2 u_k)]
+ *            (the second term evaluated as 2 (log 2 - u - softplus(-2u))),
+ *   f_b = energy(phi(s_b, a'_b), psi(g_b))   (the diagonal of the critic),
+ *   L_pi = mean_b [alpha log pi_b - f_b],  alpha = exp(*log_alpha),
+ *   L_alpha = -log alpha * (mean_b log pi_b + target_entropy).
+ * eps is standard normal from Box-Muller on the Philox4x64-10 stream 1: for
+ * sample b the block with counter (b, n, 1, j), key (seed, 0), gives words
+ * w0..w3; each word w becomes the uniform (2 floor(w / 2^41) + 1) / 2^24,
+ * (w0, w1) and (w2, w3) make the Box-Muller pairs sqrt(-2 ln u1) cos(2 pi u2),
+ * sqrt(-2 ln u1) sin(2 pi u2), and coordinates 4j .. 4j+3 take them in order.
+ *   params, params_bf16   critic vector (after its Adam step) and BF16 copy
+ *   actor_params, actor_params_bf16   policy vector and BF16 copy (BF16 copy
+ *                         required when precision is BF16)
+ *   log_alpha     device FP32 [1], read
+ *   x_sa, x_g, x_sg   the batch as crl_sample_relabel wrote it (x_sg needed);
+ *                 the state columns of x_sa are reused for phi(s, a')
+ *   seed, step    Philox key word 0 and device batch counter n (read)
+ *   ws            the workspace; this call overwrites the critic's saved
+ *                 activations, so it must come after crl_critic_bwd
+ *   actor_grads   device FP32 out, crl_actor_param_count floats, written (not
+ *                 accumulated): dL_pi / d(policy parameters), padding 0
+ *   alpha_grad    device FP32 [1] out: dL_alpha / dlog alpha
+ *   loss_out      device FP32 [4] out: {L_pi, mean log pi, L_alpha, mean f}
+ * EINVAL when the context was created without a policy. */
+CRL_API int crl_actor_step(crl_ctx* ctx, const float* params,
+                           const uint16_t* params_bf16, const float* actor_params,
+                           const uint16_t* actor_params_bf16,
+                           const float* log_alpha, const void* x_sa,
+                           const void* x_g, const void* x_sg, uint64_t seed,
+                           const int64_t* step, void* ws, float* actor_grads,
+                           float* alpha_grad, float* loss_out, void* stream);
+
 /* Step 4: Adam (Kingma & Ba) on n floats, the optimiser read into the
  * gradient steps of Algorithm 1:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
@@ -195,8 +248,15 @@ enum {
   CRL_WS_DIAG = 4,    /* [B] F_ii */
   CRL_WS_DPHI = 5,    /* [B][D] dL/dphi (after crl_critic_bwd) */
   CRL_WS_DPSI = 6,    /* [B][D] dL/dpsi */
-  CRL_WS_LOGITS = 7   /* [B][ldF] F, ldF = B rounded up to a multiple of 8
+  CRL_WS_LOGITS = 7,  /* [B][ldF] F, ldF = B rounded up to a multiple of 8
                          (materialised logits only) */
+  /* after crl_actor_step (contexts with a policy only): */
+  CRL_WS_POLICY_OUT = 8,    /* [B][P] policy MLP output [mu | rho | pad] */
+  CRL_WS_NOISE = 9,         /* [B][act_dim] eps */
+  CRL_WS_LOG_PI = 10,       /* [B] log pi */
+  CRL_WS_POLICY_ENERGY = 11,/* [B] f_b */
+  CRL_WS_DACTION = 12       /* [B][ldd] d(-mean f)/da', ldd = act_dim rounded
+                               up to a multiple of 8 */
 };
 CRL_API int crl_workspace_view(const crl_ctx* ctx, int32_t which,
                                int64_t* offset, int64_t* bytes);

@@ -54,8 +54,9 @@ class FullUpdate:
                         w.critic_lr)
         eps = A.box_muller_noise(self.seed, n, w.batch_size, w.act_dim)
         obs_t = x_sa[:, :w.obs_dim]
+        la_used = self.log_alpha
         act_out = A.actor_loss_and_grads(self.actor, self.phi, self.psi, x_sg, x_g, obs_t, eps,
-                                         self.log_alpha, w)
+                                         la_used, w)
         for l, L in enumerate(self.actor):
             for k in L:
                 L[k], self.ma[l][k], self.va[l][k] = AD.adam_step(
@@ -66,4 +67,5 @@ class FullUpdate:
                                 w.alpha_lr)
         self.log_alpha, self.m_alpha, self.v_alpha = float(la[0]), float(m[0]), float(v[0])
         return {"critic": crit["total"], "actor": act_out["loss"],
-                "mean_log_pi": act_out["mean_log_pi"], "log_alpha": self.log_alpha}
+                "mean_log_pi": act_out["mean_log_pi"], "mean_f": float(np.mean(act_out["f"])),
+                "alpha": math.exp(la_used), "log_alpha": self.log_alpha}

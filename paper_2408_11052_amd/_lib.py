@@ -18,7 +18,8 @@ LOSS = {"fwd_infonce": 0, "symmetric_infonce": 1}
 PREC = {"fp32": 0, "bf16": 1}
 LOGITS = {"materialised": 0, "fused": 1}
 WS = {"phi": 0, "psi": 1, "row_lse": 2, "col_lse": 3, "diag": 4, "dphi": 5,
-      "dpsi": 6, "logits": 7}
+      "dpsi": 6, "logits": 7, "policy_out": 8, "noise": 9, "log_pi": 10,
+      "policy_energy": 11, "daction": 12}
 
 
 class crl_config(C.Structure):
@@ -29,7 +30,9 @@ class crl_config(C.Structure):
         ("energy", C.c_int32), ("loss", C.c_int32), ("precision", C.c_int32),
         ("logits", C.c_int32), ("logsumexp_penalty", C.c_float),
         ("ln_eps", C.c_float), ("discount", C.c_double),
-        ("max_episode_len", C.c_int32), ("reserved", C.c_int32 * 7),
+        ("max_episode_len", C.c_int32), ("actor_n_hidden", C.c_int32),
+        ("actor_hidden", C.c_int32), ("target_entropy", C.c_float),
+        ("reserved", C.c_int32 * 4),
     ]
 
 
@@ -46,6 +49,7 @@ SIGNATURES = {
     "crl_create": (C.c_int, [C.POINTER(crl_config), C.POINTER(P)]),
     "crl_destroy": (C.c_int, [P]),
     "crl_param_count": (C.c_int, [P, C.POINTER(I64)]),
+    "crl_actor_param_count": (C.c_int, [P, C.POINTER(I64)]),
     "crl_layer_layout": (C.c_int, [P, I32, I32, C.POINTER(crl_layer_info)]),
     "crl_workspace_size": (C.c_int, [P, C.POINTER(I64)]),
     "crl_input_layout": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
@@ -53,6 +57,7 @@ SIGNATURES = {
     "crl_sample_relabel": (C.c_int, [P, P, P, I32, I32, U64, P, P, P, P, P, P]),
     "crl_critic_fwd": (C.c_int, [P, P, P, P, P, P, P, P]),
     "crl_critic_bwd": (C.c_int, [P, P, P, P, P, P, P, P]),
+    "crl_actor_step": (C.c_int, [P, P, P, P, P, P, P, P, P, U64, P, P, P, P, P, P]),
     "crl_adam_step": (C.c_int, [P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_double,
                                 C.c_double, P]),
     "crl_counter_add": (C.c_int, [P, I64, P]),

@@ -51,6 +51,13 @@ def make_config(w, max_episode_len: int | None = None) -> crl_config:
     c.ln_eps = w.ln_eps
     c.discount = w.discounting
     c.max_episode_len = max_episode_len or w.episode_len
+    ahid = tuple(getattr(w, "actor_hidden", ()) or ())
+    if ahid:
+        if len(set(ahid)) != 1:
+            raise ValueError("all policy hidden layers must have the same width")
+        c.actor_n_hidden = len(ahid)
+        c.actor_hidden = ahid[0]
+        c.target_entropy = -float(w.act_dim)
     return c
 
 
@@ -72,13 +79,19 @@ class Critic:
         check(lib().crl_input_layout(self.ctx, C.byref(a), C.byref(b), C.byref(c), C.byref(e)))
         self.ld_sa, self.ld_g, self.ld_sg, self.elem_bytes = a.value, b.value, c.value, e.value
         self.layers: List[List[crl_layer_info]] = []
-        for enc in range(2):
+        for net, depth in ((0, self.cfg.n_hidden), (1, self.cfg.n_hidden),
+                           (2, self.cfg.actor_n_hidden)):
+            if net == 2 and depth == 0:
+                break
             row = []
-            for l in range(self.cfg.n_hidden + 1):
+            for l in range(depth + 1):
                 info = crl_layer_info()
-                check(lib().crl_layer_layout(self.ctx, enc, l, C.byref(info)))
+                check(lib().crl_layer_layout(self.ctx, net, l, C.byref(info)))
                 row.append(info)
             self.layers.append(row)
+        check(lib().crl_actor_param_count(self.ctx, C.byref(n)))
+        self.nparam_actor = n.value
+        self.has_actor = self.nparam_actor > 0
 
     def close(self):
         if self.ctx:
@@ -96,38 +109,56 @@ class Critic:
     def act_dtype(self):
         return torch.bfloat16 if self.elem_bytes == 2 else torch.float32
 
+    @staticmethod
+    def _pack_into(flat, infos, layers):
+        for info, L in zip(infos, layers):
+            W = np.asarray(L["W"], np.float32)
+            # the policy's output layer may be narrower than its padded width
+            assert W.shape[0] == info.fan_in and W.shape[1] <= info.fan_out, (W.shape, info.fan_out)
+            full = np.zeros((info.fan_in, info.fan_out), np.float32)
+            full[:, :W.shape[1]] = W
+            flat[info.w:info.w + full.size] = full.reshape(-1)
+            flat[info.b:info.b + W.shape[1]] = L["b"]
+            if info.ln_g >= 0:
+                flat[info.ln_g:info.ln_g + info.fan_out] = L["ln_g"]
+                flat[info.ln_b:info.ln_b + info.fan_out] = L["ln_b"]
+
+    @staticmethod
+    def _unpack_from(flat, infos, out_cols=None):
+        layers = []
+        for i, info in enumerate(infos):
+            cols = out_cols if (out_cols is not None and i == len(infos) - 1) else info.fan_out
+            L: Dict[str, np.ndarray] = {
+                "W": flat[info.w:info.w + info.fan_in * info.fan_out].reshape(
+                    info.fan_in, info.fan_out)[:, :cols],
+                "b": flat[info.b:info.b + cols]}
+            if info.ln_g >= 0:
+                L["ln_g"] = flat[info.ln_g:info.ln_g + info.fan_out]
+                L["ln_b"] = flat[info.ln_b:info.ln_b + info.fan_out]
+            layers.append(L)
+        return layers
+
     def pack(self, phi_layers, psi_layers) -> np.ndarray:
-        """Flat FP32 parameter vector (zero padding) from per-layer arrays."""
+        """Flat FP32 critic vector (zero padding) from per-layer arrays."""
         flat = np.zeros(self.nparam, np.float32)
-        for enc, layers in enumerate((phi_layers, psi_layers)):
-            for l, L in enumerate(layers):
-                info = self.layers[enc][l]
-                W = np.asarray(L["W"], np.float32)
-                assert W.shape == (info.fan_in, info.fan_out), (W.shape, info.fan_in, info.fan_out)
-                flat[info.w:info.w + W.size] = W.reshape(-1)
-                flat[info.b:info.b + info.fan_out] = L["b"]
-                if info.ln_g >= 0:
-                    flat[info.ln_g:info.ln_g + info.fan_out] = L["ln_g"]
-                    flat[info.ln_b:info.ln_b + info.fan_out] = L["ln_b"]
+        self._pack_into(flat, self.layers[0], phi_layers)
+        self._pack_into(flat, self.layers[1], psi_layers)
         return flat
 
     def unpack(self, flat) -> Tuple[list, list]:
-        """Per-layer dicts (numpy FP32) from a flat vector (params or grads)."""
+        """Per-layer dicts (numpy FP32) from a flat critic vector (params or grads)."""
         flat = np.asarray(flat)
-        out = []
-        for enc in range(2):
-            layers = []
-            for info in self.layers[enc]:
-                L: Dict[str, np.ndarray] = {
-                    "W": flat[info.w:info.w + info.fan_in * info.fan_out].reshape(
-                        info.fan_in, info.fan_out),
-                    "b": flat[info.b:info.b + info.fan_out]}
-                if info.ln_g >= 0:
-                    L["ln_g"] = flat[info.ln_g:info.ln_g + info.fan_out]
-                    L["ln_b"] = flat[info.ln_b:info.ln_b + info.fan_out]
-                layers.append(L)
-            out.append(layers)
-        return out[0], out[1]
+        return self._unpack_from(flat, self.layers[0]), self._unpack_from(flat, self.layers[1])
+
+    def pack_actor(self, layers) -> np.ndarray:
+        """Flat FP32 policy vector; the output layer's padding columns are 0."""
+        flat = np.zeros(self.nparam_actor, np.float32)
+        self._pack_into(flat, self.layers[2], layers)
+        return flat
+
+    def unpack_actor(self, flat) -> list:
+        """Per-layer dicts of the policy, output layer cut to 2 act_dim columns."""
+        return self._unpack_from(np.asarray(flat), self.layers[2], 2 * self.cfg.act_dim)
 
     def inputs(self, device="cuda"):
         """Empty x_sa, x_g, x_sg in the storage type and strides of this ctx."""
@@ -150,6 +181,13 @@ class Critic:
         if name == "logits":
             ld = (B + 7) // 8 * 8
             return v.view(B, ld)[:, :B]
+        A = self.cfg.act_dim
+        if name == "policy_out":
+            return v.view(B, -1)
+        if name == "noise":
+            return v.view(B, A)
+        if name == "daction":
+            return v.view(B, -1)[:, :A]
         return v
 
     # ------------------------------------------------------------ entry points
@@ -167,6 +205,16 @@ class Critic:
     def crl_critic_bwd(self, params, params_bf16, x_sa, x_g, ws, grads, stream=None):
         check(lib().crl_critic_bwd(self.ctx, _ptr(params), _ptr(params_bf16), _ptr(x_sa),
                                    _ptr(x_g), _ptr(ws), _ptr(grads), _stream(stream)))
+
+
+    def crl_actor_step(self, params, params_bf16, actor_params, actor_params_bf16, log_alpha,
+                       x_sa, x_g, x_sg, seed: int, step, ws, actor_grads, alpha_grad,
+                       loss_out, stream=None):
+        check(lib().crl_actor_step(self.ctx, _ptr(params), _ptr(params_bf16),
+                                   _ptr(actor_params), _ptr(actor_params_bf16),
+                                   _ptr(log_alpha), _ptr(x_sa), _ptr(x_g), _ptr(x_sg), seed,
+                                   _ptr(step), _ptr(ws), _ptr(actor_grads), _ptr(alpha_grad),
+                                   _ptr(loss_out), _stream(stream)))
 
 
 def crl_adam_step(p, g, m, v, p_bf16, step, lr: float, b1: float = 0.9, b2: float = 0.999,

@@ -31,6 +31,11 @@ int hip_fail(hipError_t e, const char* what) {
     hipError_t _e = (expr);                       \
     if (_e != hipSuccess) return hip_fail(_e, what); \
   } while (0)
+#define CRL_TRY(expr)          \
+  do {                         \
+    int _rc = (expr);          \
+    if (_rc != CRL_OK) return _rc; \
+  } while (0)
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -39,31 +44,48 @@ struct LayerOff {
   int fan_in, fan_out;
 };
 
+// Static shape of one MLP: phi (0), psi (1) or the policy (2).
+struct Net {
+  std::vector<LayerOff> lay;  // offsets in the flat vector the net lives in
+  int fan_in0;                // input features
+  int ld_in;                  // row stride of its input
+  int H, L;                   // hidden width and hidden layers
+  int out_dim;                // output width (repr dim, or the padded policy head)
+};
+
+// Workspace byte offsets of one MLP's activations and gradients.
+struct Slots {
+  std::vector<int64_t> Z, Hh, mu, rstd;  // per hidden layer
+  int64_t out, dout, dout_t;             // [B][out_dim] FP32, FP32, storage type
+  int64_t dH, dZ[2];                     // [B][H] storage type
+  int64_t lnpart, cpart;                 // column partials
+};
+
 }  // namespace
 
 struct crl_ctx {
   crl_config cfg;
   int device;
-  bool bf16, ln, l2, sym, fused;
-  int B, H, D, L;            // batch, hidden width, repr dim, hidden layers
-  int fan_in0[2];            // d_s + d_a, d_g
-  int ld_in[2];              // ld_sa, ld_g
+  bool bf16, ln, l2, sym, fused, actor;
+  int B, H, D, L;            // batch, critic hidden width, repr dim, hidden layers
+  int A, P;                  // action dim, padded policy-output width (actor only)
   int ld_sg;
   int esz;                   // bytes per activation element
-  std::vector<LayerOff> lay[2];
-  int64_t nparam;
-  std::vector<int64_t> gaps; // (offset, len) pairs of padding
+  Net net[3];
+  Slots sl[3];
+  int64_t nparam, nparam_actor;
+  std::vector<int64_t> gaps[2];  // (offset, len) pairs of padding: critic, actor vector
   // device tables
   uint64_t* d_thr;
-  int64_t* d_gaps;
-  int n_gaps;
+  int64_t* d_gaps[2];
+  int n_gaps[2];
   // workspace plan (byte offsets)
   int64_t ws_bytes;
-  std::vector<int64_t> Z[2], Hh[2], mu[2], rstd[2];
-  int64_t out[2], dout[2], dout_t[2], dH[2], dZ[2][2], lnpart[2], cpart[2];
-  int64_t splitk, splitk_len;  // floats per problem
+  int64_t splitk, splitk_floats;
   int64_t r, c, diag, nphi, npsi, logits, cpm, cps, rowsumH, colsumH, cpartB;
   int64_t phi_b, psi_b, row_m, row_s, col_m, col_s, dx_part, rs_part;
+  int64_t xsa2, noise, logpi, fpol, dact;  // actor step
+  int ldd;                                 // row stride of dact
   int ln_rows_per_wave, ln_nparts, rchunks;
   int ldF;                     // row stride of the materialised logits
 };
@@ -72,7 +94,7 @@ namespace {
 
 int validate(const crl_config* c) {
   if (!c) return fail(CRL_EINVAL, "config is NULL");
-  for (int i = 0; i < 7; ++i)
+  for (int i = 0; i < 4; ++i)
     if (c->reserved[i] != 0) return fail(CRL_EINVAL, "reserved config fields must be zero");
   if (c->batch < 1 || c->batch > 65536) return fail(CRL_EINVAL, "batch must be in [1, 65536]");
   if (c->obs_dim < 1 || c->act_dim < 0 || c->goal_dim < 1)
@@ -107,106 +129,138 @@ int validate(const crl_config* c) {
   if (!(c->ln_eps > 0.f) || !std::isfinite(c->ln_eps)) return fail(CRL_EINVAL, "ln_eps must be > 0");
   if (!(c->discount > 0.0 && c->discount < 1.0)) return fail(CRL_EINVAL, "discount must lie in (0, 1)");
   if (c->max_episode_len < 2) return fail(CRL_EINVAL, "max_episode_len must be >= 2");
+  if (c->actor_n_hidden < 0 || c->actor_n_hidden > 16)
+    return fail(CRL_EINVAL, "actor_n_hidden must be in [0, 16]");
+  if (c->actor_n_hidden == 0) {
+    if (c->actor_hidden != 0) return fail(CRL_EINVAL, "actor_hidden must be 0 without an actor");
+  } else {
+    if (c->actor_hidden < 8 || c->actor_hidden % 8 || c->actor_hidden > 1024)
+      return fail(CRL_EINVAL, "actor_hidden must be a multiple of 8 in [8, 1024]");
+    if (c->act_dim < 1 || c->act_dim > 256)
+      return fail(CRL_EINVAL, "the actor needs act_dim in [1, 256]");
+    if (!std::isfinite(c->target_entropy)) return fail(CRL_EINVAL, "target_entropy must be finite");
+  }
   return CRL_OK;
 }
 
-void plan_params(crl_ctx* x) {
+// Lays out the nets `first..last` one after another in one flat vector; each
+// tensor starts on a 64-element boundary and the gaps are recorded.
+int64_t plan_params(crl_ctx* x, int first, int last, std::vector<int64_t>& gaps) {
   int64_t off = 0;
   auto take = [&](int64_t n) {
     int64_t o = align_up(off, 64);
-    if (o > off) { x->gaps.push_back(off); x->gaps.push_back(o - off); }
+    if (o > off) { gaps.push_back(off); gaps.push_back(o - off); }
     off = o + n;
     return o;
   };
-  for (int e = 0; e < 2; ++e) {
-    x->lay[e].clear();
-    int in = x->fan_in0[e];
-    for (int l = 0; l <= x->L; ++l) {
-      const bool last = l == x->L;
-      const int out = last ? x->D : x->H;
+  gaps.clear();
+  for (int e = first; e <= last; ++e) {
+    Net& N = x->net[e];
+    N.lay.clear();
+    int in = N.fan_in0;
+    for (int l = 0; l <= N.L; ++l) {
+      const bool top = l == N.L;
+      const int out = top ? N.out_dim : N.H;
       LayerOff lo;
       lo.fan_in = in;
       lo.fan_out = out;
       lo.w = take((int64_t)in * out);
       lo.b = take(out);
       lo.g = lo.be = -1;
-      if (!last && x->ln) { lo.g = take(out); lo.be = take(out); }
-      x->lay[e].push_back(lo);
+      if (!top && x->ln) { lo.g = take(out); lo.be = take(out); }
+      N.lay.push_back(lo);
       in = out;
     }
   }
   int64_t end = align_up(off, 64);
-  if (end > off) { x->gaps.push_back(off); x->gaps.push_back(end - off); }
-  x->nparam = end;
-  x->n_gaps = (int)(x->gaps.size() / 2);
+  if (end > off) { gaps.push_back(off); gaps.push_back(end - off); }
+  return end;
 }
 
-// split-K planning for the dW products (and the materialised dphi/dpsi)
+// Floats of split-K partials that the largest split GEMM launch needs.
 int64_t splitk_need(crl_ctx* x) {
   int64_t need = 0;
-  auto consider = [&](int M0, int N0, int M1, int N1, int K) {
+  auto consider = [&](int count, const int (*mnk)[3], bool bf16) {
     GemmParams P{};
-    P.count = 2;
-    P.d[0].M = M0; P.d[0].N = N0; P.d[0].K = K;
-    P.d[1].M = M1; P.d[1].N = N1; P.d[1].K = K;
+    P.count = count;
+    int64_t mn = 0;
+    for (int g = 0; g < count; ++g) {
+      P.d[g].M = mnk[g][0]; P.d[g].N = mnk[g][1]; P.d[g].K = mnk[g][2];
+      mn = std::max(mn, (int64_t)mnk[g][0] * mnk[g][1]);
+    }
     P.partial = reinterpret_cast<float*>(1);
-    plan_split_k(P, x->bf16, 512);
-    int64_t len = (int64_t)P.splits * (std::max((int64_t)M0 * N0, (int64_t)M1 * N1));
-    if (P.splits > 1 && len > need) need = len;
+    plan_split_k(P, bf16, 512);
+    if (P.splits > 1) need = std::max(need, (int64_t)count * P.splits * mn);
   };
-  for (int l = 0; l <= x->L; ++l)
-    consider(x->lay[0][l].fan_in, x->lay[0][l].fan_out, x->lay[1][l].fan_in,
-             x->lay[1][l].fan_out, x->B);
-  // forward output layer: [B x H] . [H x D]
-  consider(x->B, x->D, x->B, x->D, x->H);
-  if (!x->fused) {
-    // dphi = G psi and dpsi = G^T phi run as single problems with FP32 tiles
-    GemmParams P{};
-    P.count = 1;
-    P.d[0].M = x->B; P.d[0].N = x->D; P.d[0].K = x->B;
-    P.partial = reinterpret_cast<float*>(1);
-    plan_split_k(P, false, 512);
-    int64_t len = (int64_t)P.splits * x->B * x->D;
-    if (P.splits > 1 && len > need) need = len;
+  const Net* n = x->net;
+  // critic: dW of every layer, and the forward output layer
+  for (int l = 0; l <= x->L; ++l) {
+    const int d[2][3] = {{n[0].lay[l].fan_in, n[0].lay[l].fan_out, x->B},
+                         {n[1].lay[l].fan_in, n[1].lay[l].fan_out, x->B}};
+    consider(2, d, x->bf16);
+  }
+  {
+    const int d[2][3] = {{x->B, x->D, x->H}, {x->B, x->D, x->H}};
+    consider(2, d, x->bf16);
+  }
+  if (!x->fused) {  // dphi = G psi and dpsi = G^T phi, single FP32 problems
+    const int d[1][3] = {{x->B, x->D, x->B}};
+    consider(1, d, false);
+  }
+  if (x->actor) {
+    for (int l = 0; l <= n[2].L; ++l) {
+      const int d[1][3] = {{n[2].lay[l].fan_in, n[2].lay[l].fan_out, x->B}};
+      consider(1, d, x->bf16);
+    }
+    const int fo[1][3] = {{x->B, x->P, n[2].H}};
+    consider(1, fo, x->bf16);
+    const int da[1][3] = {{x->B, x->A, x->H}};  // action columns of phi's input gradient
+    consider(1, da, x->bf16);
   }
   return need;
 }
 
+void plan_slots(crl_ctx* x, int e, int64_t (*take)(crl_ctx*, int64_t&, int64_t), int64_t& off) {
+  const Net& N = x->net[e];
+  Slots& S = x->sl[e];
+  const int64_t B = x->B, H = N.H, O = N.out_dim, es = x->esz;
+  S.Z.assign(N.L, -1);
+  S.Hh.assign(N.L, -1);
+  S.mu.assign(N.L, -1);
+  S.rstd.assign(N.L, -1);
+  for (int l = 0; l < N.L; ++l) {
+    if (x->ln) {
+      S.Z[l] = take(x, off, B * H * es);
+      S.mu[l] = take(x, off, B * 4);
+      S.rstd[l] = take(x, off, B * 4);
+    }
+    S.Hh[l] = take(x, off, B * H * es);
+  }
+  S.out = take(x, off, B * O * 4);
+  S.dout = take(x, off, B * O * 4);
+  S.dout_t = x->bf16 ? take(x, off, B * O * es) : S.dout;  // FP32: the same buffer
+  S.dH = take(x, off, B * H * es);
+  S.dZ[0] = take(x, off, B * H * es);
+  S.dZ[1] = take(x, off, B * H * es);
+  S.lnpart = x->ln ? take(x, off, (int64_t)x->ln_nparts * 3 * H * 4) : -1;
+  S.cpart = take(x, off, ((B + 127) / 128) * std::max(H, O) * 4);
+}
+
+int64_t take_bytes(crl_ctx*, int64_t& off, int64_t bytes) {
+  int64_t o = align_up(off, 256);
+  off = o + (bytes > 0 ? bytes : 1);
+  return o;
+}
+
 void plan_workspace(crl_ctx* x) {
   int64_t off = 0;
-  auto take = [&](int64_t bytes) {
-    int64_t o = align_up(off, 256);
-    off = o + (bytes > 0 ? bytes : 1);
-    return o;
-  };
-  const int64_t B = x->B, H = x->H, D = x->D;
-  const int64_t es = x->esz;
+  auto take = [&](int64_t bytes) { return take_bytes(x, off, bytes); };
+  const int64_t B = x->B, D = x->D;
   x->ln_rows_per_wave = 16;
   x->ln_nparts = ln_bwd_partials(x->B, x->ln_rows_per_wave);
-  for (int e = 0; e < 2; ++e) {
-    x->Z[e].assign(x->L, -1);
-    x->Hh[e].assign(x->L, -1);
-    x->mu[e].assign(x->L, -1);
-    x->rstd[e].assign(x->L, -1);
-    for (int l = 0; l < x->L; ++l) {
-      if (x->ln) {
-        x->Z[e][l] = take(B * H * es);
-        x->mu[e][l] = take(B * 4);
-        x->rstd[e][l] = take(B * 4);
-      }
-      x->Hh[e][l] = take(B * H * es);
-    }
-    x->out[e] = take(B * D * 4);
-    x->dout[e] = take(B * D * 4);
-    x->dout_t[e] = x->bf16 ? take(B * D * es) : x->dout[e];  // FP32: the same buffer
-    x->dH[e] = take(B * H * es);
-    x->dZ[e][0] = take(B * H * es);
-    x->dZ[e][1] = take(B * H * es);
-    x->lnpart[e] = x->ln ? take((int64_t)x->ln_nparts * 3 * H * 4) : -1;
-    x->cpart[e] = take(((B + 127) / 128) * std::max(H, D) * 4);
-  }
-  x->splitk_len = splitk_need(x);
-  x->splitk = take(2 * x->splitk_len * 4);
+  for (int e = 0; e < (x->actor ? 3 : 2); ++e) plan_slots(x, e, take_bytes, off);
+  x->splitk_floats = splitk_need(x);
+  x->splitk = take(x->splitk_floats * 4);
   x->r = take(B * 4);
   x->c = take(B * 4);
   x->diag = take(B * 4);
@@ -235,6 +289,16 @@ void plan_workspace(crl_ctx* x) {
     x->dx_part = take((int64_t)S * B * D * 4);
     x->rs_part = take((int64_t)S * B * 4);
   }
+  x->xsa2 = x->noise = x->logpi = x->fpol = x->dact = -1;
+  x->ldd = 0;
+  if (x->actor) {
+    x->ldd = (int)align_up(x->A, 8);
+    x->xsa2 = take(B * x->net[0].ld_in * x->esz);
+    x->noise = take(B * x->A * 4);
+    x->logpi = take(B * 4);
+    x->fpol = take(B * 4);
+    x->dact = take(B * x->ldd * 4);
+  }
   x->ws_bytes = align_up(off, 256);
 }
 
@@ -252,6 +316,217 @@ int check_device(const crl_ctx* x) {
   return CRL_OK;
 }
 
+// One MLP taking part in a forward or backward pass.
+struct NetCall {
+  int net;                 // 0 phi, 1 psi, 2 policy
+  const void* x;           // layer-0 input [B][ld] (storage type)
+  int ld;
+  const float* p;          // FP32 flat vector the net lives in
+  const bf16_t* pb;        // its BF16 shadow (BF16 precision)
+  float* g;                // gradient vector, or nullptr: no parameter gradients
+  float* dx;               // optional FP32 gradient of input columns [dx_c0, dx_c0 + dx_n)
+  int dx_c0, dx_n, ldd;
+};
+
+const void* weights(const crl_ctx* x, const NetCall& c, int64_t off) {
+  return x->bf16 ? (const void*)(c.pb + off) : (const void*)(c.p + off);
+}
+
+// Forward of `count` MLPs with the same depth and width, layer by layer in
+// grouped launches: GEMM (bias, and ReLU, in the epilogue), then LayerNorm +
+// Swish.  Outputs and the activations the backward needs stay in ws.
+int mlp_forward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t s) {
+  const Net& N0 = x->net[nc[0].net];
+  const int B = x->B;
+  for (int l = 0; l <= N0.L; ++l) {
+    const bool top = l == N0.L;
+    GemmParams P{};
+    P.count = count;
+    for (int e = 0; e < count; ++e) {
+      const Net& N = x->net[nc[e].net];
+      const Slots& S = x->sl[nc[e].net];
+      const LayerOff& lo = N.lay[l];
+      GemmDesc& d = P.d[e];
+      d.A = l == 0 ? nc[e].x : (const void*)W(ws, S.Hh[l - 1]);
+      d.lda = l == 0 ? nc[e].ld : N.H;
+      d.B = weights(x, nc[e], lo.w);
+      d.ldb = lo.fan_out;
+      d.M = B; d.N = lo.fan_out; d.K = lo.fan_in;
+      d.bias = nc[e].p + lo.b;
+      d.alpha = 1.f;
+      if (top) { d.C = W(ws, S.out); d.epi = EPI_BIAS; }
+      else if (!x->ln) { d.C = W(ws, S.Hh[l]); d.epi = EPI_BIAS_RELU; }
+      else { d.C = W(ws, S.Z[l]); d.epi = EPI_BIAS; }
+      d.ldc = lo.fan_out;
+    }
+    if (top) P.partial = WF(ws, x->splitk);  // few output tiles: split K
+    plan_split_k(P, x->bf16, 512);
+    if (P.splits > 1)
+      P.partial_len = (int64_t)P.splits * std::max((int64_t)P.d[0].M * P.d[0].N,
+                                                   (int64_t)P.d[count - 1].M * P.d[count - 1].N);
+    CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_MC, x->bf16 && !top, s), "encoder GEMM");
+    if (!top && x->ln) {
+      LnArgs a{};
+      for (int e = 0; e < count; ++e) {
+        const Slots& S = x->sl[nc[e].net];
+        const LayerOff& lo = x->net[nc[e].net].lay[l];
+        a.Z[e] = W(ws, S.Z[l]);
+        a.H[e] = W(ws, S.Hh[l]);
+        a.mu[e] = WF(ws, S.mu[l]);
+        a.rstd[e] = WF(ws, S.rstd[l]);
+        a.g[e] = nc[e].p + lo.g;
+        a.b[e] = nc[e].p + lo.be;
+      }
+      CRL_HIP(launch_ln_swish_fwd(a, count, B, N0.H, x->cfg.ln_eps, x->bf16, s), "LayerNorm forward");
+    }
+  }
+  return CRL_OK;
+}
+
+// Backward of `count` MLPs from the output gradients in their dout / dout_t
+// slots, last layer first.  With a gradient vector: dW, bias and LayerNorm
+// parameter gradients of every layer.  A net with dx set (count must be 1)
+// also gets the gradient of the chosen input columns.
+int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t s) {
+  const Net& N0 = x->net[nc[0].net];
+  const int B = x->B, H = N0.H, L = N0.L;
+  const bool grads = nc[0].g != nullptr;
+  float* splitk = WF(ws, x->splitk);
+  int cur = 0;
+  for (int l = L; l >= 0; --l) {
+    const bool top = l == L;
+    const void* dZ[2];
+    for (int e = 0; e < count; ++e) {
+      const Slots& S = x->sl[nc[e].net];
+      dZ[e] = top ? (const void*)W(ws, S.dout_t) : (const void*)W(ws, S.dZ[cur]);
+    }
+    if (grads) {
+      {  // dW = in^T . dZ  (contraction over the batch)
+        GemmParams P{};
+        P.count = count;
+        int64_t mn = 0;
+        for (int e = 0; e < count; ++e) {
+          const Net& N = x->net[nc[e].net];
+          const Slots& S = x->sl[nc[e].net];
+          const LayerOff& lo = N.lay[l];
+          GemmDesc& d = P.d[e];
+          d.A = l == 0 ? nc[e].x : (const void*)W(ws, S.Hh[l - 1]);
+          d.lda = l == 0 ? nc[e].ld : N.H;
+          d.B = dZ[e]; d.ldb = lo.fan_out;
+          d.C = nc[e].g + lo.w; d.ldc = lo.fan_out;
+          d.M = lo.fan_in; d.N = lo.fan_out; d.K = B;
+          d.alpha = 1.f;
+          d.epi = EPI_NONE;
+          mn = std::max(mn, (int64_t)d.M * d.N);
+        }
+        P.partial = splitk;
+        plan_split_k(P, x->bf16, 512);
+        P.partial_len = (int64_t)P.splits * mn;
+        CRL_HIP(launch_gemm(P, x->bf16, LAY_MC, LAY_MC, false, s), "dW GEMM");
+      }
+      // bias gradients of this layer (LayerNorm layers get theirs with dZ)
+      if (top || !x->ln) {
+        ColSumArgs ca{};
+        for (int e = 0; e < count; ++e) {
+          const Slots& S = x->sl[nc[e].net];
+          ca.X[e] = top ? (const void*)WF(ws, S.dout) : dZ[e];
+          ca.out[e] = nc[e].g + x->net[nc[e].net].lay[l].b;
+          ca.part[e] = WF(ws, S.cpart);
+        }
+        const int Nc = top ? N0.out_dim : H;
+        CRL_HIP(launch_colsum(ca, count, B, Nc, Nc, top ? false : x->bf16, s), "bias gradient");
+      }
+    }
+    if (l == 0) {
+      if (nc[0].dx) {  // dx[:, j] = dZ . W[c0 + j, :]^T for the requested input columns
+        const LayerOff& lo = N0.lay[0];
+        GemmParams P{};
+        P.count = 1;
+        GemmDesc& d = P.d[0];
+        d.A = dZ[0]; d.lda = lo.fan_out;
+        d.B = weights(x, nc[0], lo.w + (int64_t)nc[0].dx_c0 * lo.fan_out);
+        d.ldb = lo.fan_out;
+        d.M = B; d.N = nc[0].dx_n; d.K = lo.fan_out;
+        d.C = nc[0].dx; d.ldc = nc[0].ldd;
+        d.alpha = 1.f;
+        d.epi = EPI_NONE;
+        P.partial = splitk;
+        plan_split_k(P, x->bf16, 512);
+        P.partial_len = (int64_t)P.splits * d.M * d.N;
+        CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_KC, false, s), "input gradient GEMM");
+      }
+      break;
+    }
+    // dZ of layer l-1: dH = dZ . W^T, then through ReLU or Swish(LayerNorm)
+    const int nxt = top ? 0 : (cur ^ 1);
+    {
+      GemmParams P{};
+      P.count = count;
+      for (int e = 0; e < count; ++e) {
+        const Slots& S = x->sl[nc[e].net];
+        const LayerOff& lo = x->net[nc[e].net].lay[l];
+        GemmDesc& d = P.d[e];
+        d.A = dZ[e]; d.lda = lo.fan_out;
+        d.B = weights(x, nc[e], lo.w);
+        d.ldb = lo.fan_out;
+        d.M = B; d.N = lo.fan_in; d.K = lo.fan_out;
+        d.alpha = 1.f;
+        d.ldc = lo.fan_in;
+        if (x->ln) { d.C = W(ws, S.dH); d.epi = EPI_NONE; }
+        else { d.C = W(ws, S.dZ[nxt]); d.epi = EPI_MASK_POS; d.aux = W(ws, S.Hh[l - 1]); }
+      }
+      plan_split_k(P, x->bf16, 512);
+      CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_KC, x->bf16, s), "dX GEMM");
+    }
+    if (x->ln) {
+      LnArgs a{};
+      ColReduceArgs ra{};
+      for (int e = 0; e < count; ++e) {
+        const Slots& S = x->sl[nc[e].net];
+        const LayerOff& lp = x->net[nc[e].net].lay[l - 1];
+        a.Z[e] = W(ws, S.Z[l - 1]);
+        a.mu[e] = WF(ws, S.mu[l - 1]);
+        a.rstd[e] = WF(ws, S.rstd[l - 1]);
+        a.g[e] = nc[e].p + lp.g;
+        a.b[e] = nc[e].p + lp.be;
+        a.dH[e] = W(ws, S.dH);
+        a.dZ[e] = W(ws, S.dZ[nxt]);
+        a.part[e] = WF(ws, S.lnpart);
+        if (grads) {
+          ra.part[e] = a.part[e];
+          ra.out[e][0] = nc[e].g + lp.g;
+          ra.out[e][1] = nc[e].g + lp.be;
+          ra.out[e][2] = nc[e].g + lp.b;
+        }
+      }
+      CRL_HIP(launch_ln_swish_bwd(a, count, B, H, x->bf16, x->ln_rows_per_wave, s), "LayerNorm backward");
+      if (grads)
+        CRL_HIP(launch_partial_reduce(ra, count, x->ln_nparts, 3, H, s), "LayerNorm parameter gradients");
+    }
+    cur = nxt;
+  }
+  return CRL_OK;
+}
+
+int upload(void** dst, const void* src, size_t bytes) {
+  *dst = nullptr;
+  if (bytes == 0) return CRL_OK;
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (*dst) (void)hipFree(*dst);
+    *dst = nullptr;
+    return hip_fail(e, "crl_create device tables");
+  }
+  return CRL_OK;
+}
+
+void free_tables(crl_ctx* x) {
+  if (x->d_thr) (void)hipFree(x->d_thr);
+  for (int i = 0; i < 2; ++i)
+    if (x->d_gaps[i]) (void)hipFree(x->d_gaps[i]);
+}
+
 }  // namespace
 
 extern "C" {
@@ -265,23 +540,34 @@ CRL_API int crl_create(const crl_config* cfg, crl_ctx** out) {
   if (rc) return rc;
   crl_ctx* x = new crl_ctx();
   x->cfg = *cfg;
-  CRL_HIP(hipGetDevice(&x->device), "hipGetDevice");
+  hipError_t he = hipGetDevice(&x->device);
+  if (he != hipSuccess) { delete x; return hip_fail(he, "hipGetDevice"); }
   x->bf16 = cfg->precision == CRL_PREC_BF16;
   x->ln = cfg->activation == CRL_ACT_LN_SWISH;
   x->l2 = cfg->energy == CRL_ENERGY_L2;
   x->sym = cfg->loss == CRL_LOSS_SYM;
   x->fused = cfg->logits == CRL_LOGITS_FUSED;
+  x->actor = cfg->actor_n_hidden > 0;
   x->B = cfg->batch;
   x->H = cfg->hidden;
   x->D = cfg->repr_dim;
   x->L = cfg->n_hidden;
-  x->fan_in0[0] = cfg->obs_dim + cfg->act_dim;
-  x->fan_in0[1] = cfg->goal_dim;
-  x->ld_in[0] = (int)align_up(x->fan_in0[0], 8);
-  x->ld_in[1] = (int)align_up(x->fan_in0[1], 8);
-  x->ld_sg = (int)align_up(cfg->obs_dim + cfg->goal_dim, 8);
+  x->A = cfg->act_dim;
+  x->P = (int)align_up(2 * cfg->act_dim, 8);
   x->esz = x->bf16 ? 2 : 4;
-  plan_params(x);
+  x->ld_sg = (int)align_up(cfg->obs_dim + cfg->goal_dim, 8);
+  const int fan_in0[3] = {cfg->obs_dim + cfg->act_dim, cfg->goal_dim, cfg->obs_dim + cfg->goal_dim};
+  for (int e = 0; e < 3; ++e) {
+    Net& N = x->net[e];
+    N.fan_in0 = fan_in0[e];
+    N.ld_in = (int)align_up(fan_in0[e], 8);
+    N.H = e < 2 ? x->H : cfg->actor_hidden;
+    N.L = e < 2 ? x->L : cfg->actor_n_hidden;
+    N.out_dim = e < 2 ? x->D : x->P;
+  }
+  x->nparam = plan_params(x, 0, 1, x->gaps[0]);
+  x->nparam_actor = x->actor ? plan_params(x, 2, 2, x->gaps[1]) : 0;
+  for (int i = 0; i < 2; ++i) x->n_gaps[i] = (int)(x->gaps[i].size() / 2);
   plan_workspace(x);
   // geometric-offset thresholds thr[1..T-2] (stored from index 0)
   const int nthr = std::max(1, cfg->max_episode_len - 2);
@@ -293,19 +579,15 @@ CRL_API int crl_create(const crl_config* cfg, crl_ctx** out) {
     t = (uint64_t)(((unsigned __int128)t * G) >> 64);
   }
   x->d_thr = nullptr;
-  x->d_gaps = nullptr;
-  hipError_t e = hipMalloc(&x->d_thr, nthr * sizeof(uint64_t));
-  if (e == hipSuccess) e = hipMemcpy(x->d_thr, thr.data(), nthr * sizeof(uint64_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess && x->n_gaps > 0) {
-    e = hipMalloc(&x->d_gaps, x->gaps.size() * sizeof(int64_t));
-    if (e == hipSuccess)
-      e = hipMemcpy(x->d_gaps, x->gaps.data(), x->gaps.size() * sizeof(int64_t), hipMemcpyHostToDevice);
-  }
-  if (e != hipSuccess) {
-    if (x->d_thr) (void)hipFree(x->d_thr);
-    if (x->d_gaps) (void)hipFree(x->d_gaps);
+  x->d_gaps[0] = x->d_gaps[1] = nullptr;
+  rc = upload(reinterpret_cast<void**>(&x->d_thr), thr.data(), nthr * sizeof(uint64_t));
+  for (int i = 0; i < 2 && rc == CRL_OK; ++i)
+    rc = upload(reinterpret_cast<void**>(&x->d_gaps[i]), x->gaps[i].data(),
+                x->gaps[i].size() * sizeof(int64_t));
+  if (rc != CRL_OK) {
+    free_tables(x);
     delete x;
-    return hip_fail(e, "crl_create device tables");
+    return rc;
   }
   *out = x;
   return CRL_OK;
@@ -313,8 +595,7 @@ CRL_API int crl_create(const crl_config* cfg, crl_ctx** out) {
 
 CRL_API int crl_destroy(crl_ctx* x) {
   if (!x) return CRL_OK;
-  if (x->d_thr) (void)hipFree(x->d_thr);
-  if (x->d_gaps) (void)hipFree(x->d_gaps);
+  free_tables(x);
   delete x;
   return CRL_OK;
 }
@@ -325,11 +606,19 @@ CRL_API int crl_param_count(const crl_ctx* x, int64_t* n) {
   return CRL_OK;
 }
 
-CRL_API int crl_layer_layout(const crl_ctx* x, int32_t enc, int32_t layer, crl_layer_info* out) {
+CRL_API int crl_actor_param_count(const crl_ctx* x, int64_t* n) {
+  if (!x || !n) return fail(CRL_EINVAL, "NULL argument");
+  *n = x->nparam_actor;
+  return CRL_OK;
+}
+
+CRL_API int crl_layer_layout(const crl_ctx* x, int32_t net, int32_t layer, crl_layer_info* out) {
   if (!x || !out) return fail(CRL_EINVAL, "NULL argument");
-  if (enc < 0 || enc > 1) return fail(CRL_EINVAL, "encoder must be 0 (phi) or 1 (psi)");
-  if (layer < 0 || layer > x->L) return fail(CRL_EINVAL, "layer %d out of range [0, %d]", layer, x->L);
-  const LayerOff& l = x->lay[enc][layer];
+  if (net < 0 || net > 2) return fail(CRL_EINVAL, "net must be 0 (phi), 1 (psi) or 2 (policy)");
+  if (net == 2 && !x->actor) return fail(CRL_EINVAL, "this context has no actor");
+  const Net& N = x->net[net];
+  if (layer < 0 || layer > N.L) return fail(CRL_EINVAL, "layer %d out of range [0, %d]", layer, N.L);
+  const LayerOff& l = N.lay[layer];
   out->w = l.w;
   out->b = l.b;
   out->ln_g = l.g;
@@ -348,8 +637,8 @@ CRL_API int crl_workspace_size(const crl_ctx* x, int64_t* bytes) {
 CRL_API int crl_input_layout(const crl_ctx* x, int32_t* ld_sa, int32_t* ld_g, int32_t* ld_sg,
                              int32_t* elem_bytes) {
   if (!x) return fail(CRL_EINVAL, "NULL context");
-  if (ld_sa) *ld_sa = x->ld_in[0];
-  if (ld_g) *ld_g = x->ld_in[1];
+  if (ld_sa) *ld_sa = x->net[0].ld_in;
+  if (ld_g) *ld_g = x->net[1].ld_in;
   if (ld_sg) *ld_sg = x->ld_sg;
   if (elem_bytes) *elem_bytes = x->esz;
   return CRL_OK;
@@ -358,17 +647,24 @@ CRL_API int crl_input_layout(const crl_ctx* x, int32_t* ld_sa, int32_t* ld_g, in
 CRL_API int crl_workspace_view(const crl_ctx* x, int32_t which, int64_t* offset, int64_t* bytes) {
   if (!x || !offset || !bytes) return fail(CRL_EINVAL, "NULL argument");
   const int64_t B = x->B, D = x->D;
+  if (which >= CRL_WS_POLICY_OUT && which <= CRL_WS_DACTION && !x->actor)
+    return fail(CRL_EINVAL, "this context has no actor");
   switch (which) {
-    case CRL_WS_PHI: *offset = x->out[0]; *bytes = B * D * 4; break;
-    case CRL_WS_PSI: *offset = x->out[1]; *bytes = B * D * 4; break;
+    case CRL_WS_PHI: *offset = x->sl[0].out; *bytes = B * D * 4; break;
+    case CRL_WS_PSI: *offset = x->sl[1].out; *bytes = B * D * 4; break;
     case CRL_WS_ROW_LSE: *offset = x->r; *bytes = B * 4; break;
     case CRL_WS_COL_LSE: *offset = x->c; *bytes = B * 4; break;
     case CRL_WS_DIAG: *offset = x->diag; *bytes = B * 4; break;
-    case CRL_WS_DPHI: *offset = x->dout[0]; *bytes = B * D * 4; break;
-    case CRL_WS_DPSI: *offset = x->dout[1]; *bytes = B * D * 4; break;
+    case CRL_WS_DPHI: *offset = x->sl[0].dout; *bytes = B * D * 4; break;
+    case CRL_WS_DPSI: *offset = x->sl[1].dout; *bytes = B * D * 4; break;
     case CRL_WS_LOGITS:
       if (x->fused) return fail(CRL_EUNSUPPORTED, "fused logits are never materialised");
       *offset = x->logits; *bytes = B * x->ldF * 4; break;
+    case CRL_WS_POLICY_OUT: *offset = x->sl[2].out; *bytes = B * x->P * 4; break;
+    case CRL_WS_NOISE: *offset = x->noise; *bytes = B * x->A * 4; break;
+    case CRL_WS_LOG_PI: *offset = x->logpi; *bytes = B * 4; break;
+    case CRL_WS_POLICY_ENERGY: *offset = x->fpol; *bytes = B * 4; break;
+    case CRL_WS_DACTION: *offset = x->dact; *bytes = B * x->ldd * 4; break;
     default: return fail(CRL_EINVAL, "unknown workspace view %d", which);
   }
   return CRL_OK;
@@ -383,11 +679,10 @@ CRL_API int crl_sample_relabel(crl_ctx* x, const float* obs, const float* act, i
   if (E < 1) return fail(CRL_EINVAL, "num_envs must be >= 1");
   if (T < 2 || T > x->cfg.max_episode_len)
     return fail(CRL_EINVAL, "episode_len %d outside [2, %d]", T, x->cfg.max_episode_len);
-  int rc = check_device(x);
-  if (rc) return rc;
+  CRL_TRY(check_device(x));
   CRL_HIP(launch_relabel(obs, act, E, T, x->cfg.obs_dim, x->cfg.act_dim, x->cfg.goal_dim,
-                         x->cfg.goal_lo, seed, step, x->d_thr, x->B, idx, x_sa, x->ld_in[0],
-                         x_g, x->ld_in[1], x_sg, x->ld_sg, x->bf16, (hipStream_t)stream),
+                         x->cfg.goal_lo, seed, step, x->d_thr, x->B, idx, x_sa, x->net[0].ld_in,
+                         x_g, x->net[1].ld_in, x_sg, x->ld_sg, x->bf16, (hipStream_t)stream),
           "relabel launch");
   return CRL_OK;
 }
@@ -401,55 +696,17 @@ CRL_API int crl_critic_fwd(crl_ctx* x, const float* params, const uint16_t* para
   if (!aligned16(params) || !aligned16(x_sa) || !aligned16(x_g) || !aligned16(ws) ||
       (params_bf16 && !aligned16(params_bf16)))
     return fail(CRL_EINVAL, "buffers must be 16-byte aligned");
-  int rc = check_device(x);
-  if (rc) return rc;
+  CRL_TRY(check_device(x));
   hipStream_t s = (hipStream_t)stream;
-  const int B = x->B, H = x->H, D = x->D, L = x->L;
-  const void* xin[2] = {x_sa, x_g};
+  const int B = x->B, D = x->D;
+  const bf16_t* pb = reinterpret_cast<const bf16_t*>(params_bf16);
 
-  // encoders, both in every launch
-  for (int l = 0; l <= L; ++l) {
-    const bool last = l == L;
-    GemmParams P{};
-    P.count = 2;
-    for (int e = 0; e < 2; ++e) {
-      const LayerOff& lo = x->lay[e][l];
-      GemmDesc& d = P.d[e];
-      d.A = l == 0 ? xin[e] : (const void*)W(ws, x->Hh[e][l - 1]);
-      d.lda = l == 0 ? x->ld_in[e] : H;
-      d.B = x->bf16 ? (const void*)(params_bf16 + lo.w) : (const void*)(params + lo.w);
-      d.ldb = lo.fan_out;
-      d.M = B; d.N = lo.fan_out; d.K = lo.fan_in;
-      d.bias = params + lo.b;
-      d.alpha = 1.f;
-      if (last) { d.C = W(ws, x->out[e]); d.epi = EPI_BIAS; }
-      else if (!x->ln) { d.C = W(ws, x->Hh[e][l]); d.epi = EPI_BIAS_RELU; }
-      else { d.C = W(ws, x->Z[e][l]); d.epi = EPI_BIAS; }
-      d.ldc = lo.fan_out;
-    }
-    if (last) P.partial = WF(ws, x->splitk);  // few output tiles: split K
-    plan_split_k(P, x->bf16, 512);
-    if (P.splits > 1)
-      P.partial_len = (int64_t)P.splits * std::max((int64_t)P.d[0].M * P.d[0].N,
-                                                   (int64_t)P.d[1].M * P.d[1].N);
-    CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_MC, x->bf16 && !last, s), "encoder GEMM");
-    if (!last && x->ln) {
-      LnArgs a{};
-      for (int e = 0; e < 2; ++e) {
-        const LayerOff& lo = x->lay[e][l];
-        a.Z[e] = W(ws, x->Z[e][l]);
-        a.H[e] = W(ws, x->Hh[e][l]);
-        a.mu[e] = WF(ws, x->mu[e][l]);
-        a.rstd[e] = WF(ws, x->rstd[e][l]);
-        a.g[e] = params + lo.g;
-        a.b[e] = params + lo.be;
-      }
-      CRL_HIP(launch_ln_swish_fwd(a, 2, B, H, x->cfg.ln_eps, x->bf16, s), "LayerNorm forward");
-    }
-  }
+  NetCall nc[2] = {{0, x_sa, x->net[0].ld_in, params, pb, nullptr, nullptr, 0, 0, 0},
+                   {1, x_g, x->net[1].ld_in, params, pb, nullptr, nullptr, 0, 0, 0}};
+  CRL_TRY(mlp_forward(x, nc, 2, ws, s));
 
-  float* phi = WF(ws, x->out[0]);
-  float* psi = WF(ws, x->out[1]);
+  float* phi = WF(ws, x->sl[0].out);
+  float* psi = WF(ws, x->sl[1].out);
   float* r = WF(ws, x->r);
   float* c = WF(ws, x->c);
   float* dg = WF(ws, x->diag);
@@ -501,21 +758,20 @@ CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* para
   if (!aligned16(params) || !aligned16(ws) || !aligned16(grads) || !aligned16(x_sa) ||
       !aligned16(x_g) || (params_bf16 && !aligned16(params_bf16)))
     return fail(CRL_EINVAL, "buffers must be 16-byte aligned");
-  int rc = check_device(x);
-  if (rc) return rc;
+  CRL_TRY(check_device(x));
   hipStream_t s = (hipStream_t)stream;
-  const int B = x->B, H = x->H, D = x->D, L = x->L;
+  const int B = x->B, D = x->D;
   const float beta = x->cfg.logsumexp_penalty;
-  const void* xin[2] = {x_sa, x_g};
-  float* phi = WF(ws, x->out[0]);
-  float* psi = WF(ws, x->out[1]);
+  const bf16_t* pb = reinterpret_cast<const bf16_t*>(params_bf16);
+  float* phi = WF(ws, x->sl[0].out);
+  float* psi = WF(ws, x->sl[1].out);
   float* r = WF(ws, x->r);
   float* c = WF(ws, x->c);
-  float* dphi = WF(ws, x->dout[0]);
-  float* dpsi = WF(ws, x->dout[1]);
+  float* dphi = WF(ws, x->sl[0].dout);
+  float* dpsi = WF(ws, x->sl[1].dout);
   float* splitk = WF(ws, x->splitk);
 
-  CRL_HIP(launch_zero_ranges(grads, x->d_gaps, x->n_gaps, s), "zero padding");
+  CRL_HIP(launch_zero_ranges(grads, x->d_gaps[0], x->n_gaps[0], s), "zero padding");
 
   // dL/dphi, dL/dpsi
   if (!x->fused) {
@@ -546,8 +802,8 @@ CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* para
       CRL_HIP(launch_l2_fix(dpsi, psi, WF(ws, x->colsumH), B, D, s), "L2 column term");
     }
     if (x->bf16) {
-      CRL_HIP(launch_cast_bf16(dphi, reinterpret_cast<bf16_t*>(W(ws, x->dout_t[0])), (int64_t)B * D, s), "cast");
-      CRL_HIP(launch_cast_bf16(dpsi, reinterpret_cast<bf16_t*>(W(ws, x->dout_t[1])), (int64_t)B * D, s), "cast");
+      CRL_HIP(launch_cast_bf16(dphi, reinterpret_cast<bf16_t*>(W(ws, x->sl[0].dout_t)), (int64_t)B * D, s), "cast");
+      CRL_HIP(launch_cast_bf16(dpsi, reinterpret_cast<bf16_t*>(W(ws, x->sl[1].dout_t)), (int64_t)B * D, s), "cast");
     }
   } else {
     FusedArgs a{};
@@ -559,93 +815,67 @@ CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* para
     a.dX_part = WF(ws, x->dx_part);
     a.rs_part = WF(ws, x->rs_part);
     a.dphi = dphi; a.dpsi = dpsi;
-    a.dphi_t = W(ws, x->dout_t[0]);
-    a.dpsi_t = W(ws, x->dout_t[1]);
+    a.dphi_t = W(ws, x->sl[0].dout_t);
+    a.dpsi_t = W(ws, x->sl[1].dout_t);
     CRL_HIP(launch_fused_bwd(a, B, D, x->l2, x->sym, beta, x->bf16, s), "fused InfoNCE backward");
   }
 
-  // encoders, last layer first; dZ of hidden layers ping-pongs between two buffers
-  int cur = 0;
-  for (int l = L; l >= 0; --l) {
-    const bool last = l == L;
-    const void* dZ[2];
-    for (int e = 0; e < 2; ++e)
-      dZ[e] = last ? (const void*)W(ws, x->dout_t[e]) : (const void*)W(ws, x->dZ[e][cur]);
-    {  // dW = in^T . dZ  (contraction over the batch)
-      GemmParams P{};
-      P.count = 2;
-      for (int e = 0; e < 2; ++e) {
-        const LayerOff& lo = x->lay[e][l];
-        GemmDesc& d = P.d[e];
-        d.A = l == 0 ? xin[e] : (const void*)W(ws, x->Hh[e][l - 1]);
-        d.lda = l == 0 ? x->ld_in[e] : H;
-        d.B = dZ[e]; d.ldb = lo.fan_out;
-        d.C = grads + lo.w; d.ldc = lo.fan_out;
-        d.M = lo.fan_in; d.N = lo.fan_out; d.K = B;
-        d.alpha = 1.f;
-        d.epi = EPI_NONE;
-      }
-      P.partial = splitk;
-      plan_split_k(P, x->bf16, 512);
-      int64_t mn = std::max((int64_t)P.d[0].M * P.d[0].N, (int64_t)P.d[1].M * P.d[1].N);
-      P.partial_len = (int64_t)P.splits * mn;
-      CRL_HIP(launch_gemm(P, x->bf16, LAY_MC, LAY_MC, false, s), "dW GEMM");
-    }
-    // bias gradients of this layer (LayerNorm layers got theirs with dZ)
-    if (last || !x->ln) {
-      ColSumArgs ca{};
-      for (int e = 0; e < 2; ++e) {
-        ca.X[e] = last ? (const void*)(e == 0 ? dphi : dpsi) : dZ[e];
-        ca.out[e] = grads + x->lay[e][l].b;
-        ca.part[e] = WF(ws, x->cpart[e]);
-      }
-      const int N = last ? D : H;
-      CRL_HIP(launch_colsum(ca, 2, B, N, N, last ? false : x->bf16, s), "bias gradient");
-    }
-    if (l == 0) break;
-    // dZ of layer l-1: dH = dZ . W^T, then through ReLU or Swish(LayerNorm)
-    const int nxt = last ? 0 : (cur ^ 1);
-    {
-      GemmParams P{};
-      P.count = 2;
-      for (int e = 0; e < 2; ++e) {
-        const LayerOff& lo = x->lay[e][l];
-        GemmDesc& d = P.d[e];
-        d.A = dZ[e]; d.lda = lo.fan_out;
-        d.B = x->bf16 ? (const void*)(params_bf16 + lo.w) : (const void*)(params + lo.w);
-        d.ldb = lo.fan_out;
-        d.M = B; d.N = lo.fan_in; d.K = lo.fan_out;
-        d.alpha = 1.f;
-        d.ldc = lo.fan_in;
-        if (x->ln) { d.C = W(ws, x->dH[e]); d.epi = EPI_NONE; }
-        else { d.C = W(ws, x->dZ[e][nxt]); d.epi = EPI_MASK_POS; d.aux = W(ws, x->Hh[e][l - 1]); }
-      }
-      plan_split_k(P, x->bf16, 512);
-      CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_KC, x->bf16, s), "dX GEMM");
-    }
-    if (x->ln) {
-      LnArgs a{};
-      ColReduceArgs ra{};
-      for (int e = 0; e < 2; ++e) {
-        const LayerOff& lp = x->lay[e][l - 1];
-        a.Z[e] = W(ws, x->Z[e][l - 1]);
-        a.mu[e] = WF(ws, x->mu[e][l - 1]);
-        a.rstd[e] = WF(ws, x->rstd[e][l - 1]);
-        a.g[e] = params + lp.g;
-        a.b[e] = params + lp.be;
-        a.dH[e] = W(ws, x->dH[e]);
-        a.dZ[e] = W(ws, x->dZ[e][nxt]);
-        a.part[e] = WF(ws, x->lnpart[e]);
-        ra.part[e] = a.part[e];
-        ra.out[e][0] = grads + lp.g;
-        ra.out[e][1] = grads + lp.be;
-        ra.out[e][2] = grads + lp.b;
-      }
-      CRL_HIP(launch_ln_swish_bwd(a, 2, B, H, x->bf16, x->ln_rows_per_wave, s), "LayerNorm backward");
-      CRL_HIP(launch_partial_reduce(ra, 2, x->ln_nparts, 3, H, s), "LayerNorm parameter gradients");
-    }
-    cur = nxt;
-  }
+  NetCall nc[2] = {{0, x_sa, x->net[0].ld_in, params, pb, grads, nullptr, 0, 0, 0},
+                   {1, x_g, x->net[1].ld_in, params, pb, grads, nullptr, 0, 0, 0}};
+  return mlp_backward(x, nc, 2, ws, s);
+}
+
+CRL_API int crl_actor_step(crl_ctx* x, const float* params, const uint16_t* params_bf16,
+                           const float* actor_params, const uint16_t* actor_params_bf16,
+                           const float* log_alpha, const void* x_sa, const void* x_g,
+                           const void* x_sg, uint64_t seed, const int64_t* step, void* ws,
+                           float* actor_grads, float* alpha_grad, float* loss_out,
+                           void* stream) {
+  if (!x) return fail(CRL_EINVAL, "NULL context");
+  if (!x->actor) return fail(CRL_EINVAL, "this context has no actor (actor_n_hidden = 0)");
+  if (!params || !actor_params || !log_alpha || !x_sa || !x_g || !x_sg || !step || !ws ||
+      !actor_grads || !alpha_grad || !loss_out)
+    return fail(CRL_EINVAL, "NULL buffer argument");
+  if (x->bf16 && (!params_bf16 || !actor_params_bf16))
+    return fail(CRL_EINVAL, "BF16 precision needs params_bf16 and actor_params_bf16");
+  if (!aligned16(params) || !aligned16(actor_params) || !aligned16(x_sa) || !aligned16(x_g) ||
+      !aligned16(x_sg) || !aligned16(ws) || !aligned16(actor_grads) ||
+      (params_bf16 && !aligned16(params_bf16)) ||
+      (actor_params_bf16 && !aligned16(actor_params_bf16)))
+    return fail(CRL_EINVAL, "buffers must be 16-byte aligned");
+  CRL_TRY(check_device(x));
+  hipStream_t s = (hipStream_t)stream;
+  const int B = x->B;
+  const bf16_t* pb = reinterpret_cast<const bf16_t*>(params_bf16);
+  const bf16_t* apb = reinterpret_cast<const bf16_t*>(actor_params_bf16);
+  void* xsa2 = W(ws, x->xsa2);
+  float* eps = WF(ws, x->noise);
+  float* logpi = WF(ws, x->logpi);
+  float* fpol = WF(ws, x->fpol);
+  float* dact = WF(ws, x->dact);
+  const float* pout = WF(ws, x->sl[2].out);
+
+  CRL_HIP(launch_zero_ranges(actor_grads, x->d_gaps[1], x->n_gaps[1], s), "zero padding");
+  // policy MLP on [s, g], then the sampled action and log pi
+  NetCall pol = {2, x_sg, x->ld_sg, actor_params, apb, actor_grads, nullptr, 0, 0, 0};
+  CRL_TRY(mlp_forward(x, &pol, 1, ws, s));
+  CRL_HIP(launch_actor_head_fwd(pout, x->P, x->A, seed, step, x_sa, xsa2, x->net[0].ld_in,
+                                x->cfg.obs_dim, eps, logpi, B, x->bf16, s), "policy head");
+  // frozen critic on (s, a') and g
+  NetCall crit[2] = {{0, xsa2, x->net[0].ld_in, params, pb, nullptr, nullptr, 0, 0, 0},
+                     {1, x_g, x->net[1].ld_in, params, pb, nullptr, nullptr, 0, 0, 0}};
+  CRL_TRY(mlp_forward(x, crit, 2, ws, s));
+  CRL_HIP(launch_actor_energy(WF(ws, x->sl[0].out), WF(ws, x->sl[1].out), x->D, x->l2, fpol,
+                              W(ws, x->sl[0].dout_t), B, x->bf16, s), "policy energy");
+  // d(-mean f)/da' through phi (no parameter gradients)
+  NetCall back = {0, xsa2, x->net[0].ld_in, params, pb, nullptr, dact, x->cfg.obs_dim, x->A, x->ldd};
+  CRL_TRY(mlp_backward(x, &back, 1, ws, s));
+  CRL_HIP(launch_actor_head_bwd(pout, x->P, x->A, eps, dact, x->ldd, log_alpha,
+                                WF(ws, x->sl[2].dout), W(ws, x->sl[2].dout_t), B, x->bf16, s),
+          "policy head backward");
+  CRL_TRY(mlp_backward(x, &pol, 1, ws, s));
+  CRL_HIP(launch_actor_loss(logpi, fpol, B, log_alpha, x->cfg.target_entropy, loss_out,
+                            alpha_grad, s), "actor loss");
   return CRL_OK;
 }
 

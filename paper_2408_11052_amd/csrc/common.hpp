@@ -13,14 +13,17 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // 16-byte register
 
 constexpr int kWave = 64;
 
-// FP32 -> BF16 round to nearest even (NaN kept quiet).
-__host__ __device__ inline bf16_t f2bf(float f) {
-  uint32_t u = __builtin_bit_cast(uint32_t, f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (bf16_t)(u >> 16);
+// FP32 -> BF16, round to nearest even: the hardware conversion
+// (v_cvt_pk_bf16_f32 on gfx950; NaN stays NaN).
+__device__ inline bf16_t f2bf(float f) {
+  return __builtin_bit_cast(bf16_t, (__bf16)f);
 }
-__host__ __device__ inline float bf2f(bf16_t h) {
+// Two values packed low/high into one 32-bit word (one conversion instruction).
+__device__ inline uint32_t pack2bf(float lo, float hi) {
+  return (uint32_t)__builtin_bit_cast(bf16_t, (__bf16)lo) |
+         ((uint32_t)__builtin_bit_cast(bf16_t, (__bf16)hi) << 16);
+}
+__device__ inline float bf2f(bf16_t h) {
   return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
 
@@ -55,6 +58,34 @@ __device__ inline void lse_merge(float& m, float& s, float m2, float s2) {
   else        { s = s + s2 * __expf(m2 - m); }
 }
 
-__device__ inline float sigmoidf_(float y) { return 1.f / (1.f + __expf(-y)); }
+// logistic function with the hardware reciprocal (about 1 ulp)
+__device__ inline float sigmoidf_(float y) { return __builtin_amdgcn_rcpf(1.f + __expf(-y)); }
+
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11): 10 rounds of two 64x64->128 products,
+// key bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ inline void philox4x64_10(uint64_t (&x)[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    uint64_t lo0 = M0 * x[0], hi0 = __umul64hi(M0, x[0]);
+    uint64_t lo1 = M1 * x[2], hi1 = __umul64hi(M1, x[2]);
+    uint64_t y0 = hi1 ^ x[1] ^ k0;
+    uint64_t y2 = hi0 ^ x[3] ^ k1;
+    x[0] = y0; x[1] = lo1; x[2] = y2; x[3] = lo0;
+  }
+}
+
+// Compensated (Kahan) summation step.
+__device__ inline void kahan_add(float& s, float& comp, float x) {
+  float y = x - comp;
+  float t = s + y;
+  comp = (t - s) - y;
+  s = t;
+}
 
 }  // namespace crl

@@ -243,18 +243,18 @@ __device__ inline void store8_any(float* p, const float (&o)[8]) {
 }
 __device__ inline void store8_any(bf16_t* p, const float (&o)[8]) {
   u32x4 u;
-  u.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
-  u.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
-  u.z = (uint32_t)f2bf(o[4]) | ((uint32_t)f2bf(o[5]) << 16);
-  u.w = (uint32_t)f2bf(o[6]) | ((uint32_t)f2bf(o[7]) << 16);
+  u.x = pack2bf(o[0], o[1]);
+  u.y = pack2bf(o[2], o[3]);
+  u.z = pack2bf(o[4], o[5]);
+  u.w = pack2bf(o[6], o[7]);
   *reinterpret_cast<u32x4*>(p) = u;
 }
 
 template <bool B> struct BoolTag { static constexpr bool value = B; };
 
 // K loop.  Two register sets: tile t is fetched into set t&1 two steps
-// before it is consumed, so each global load has a full step of MFMA work to
-// hide behind.  LDS is double-buffered with one barrier per step.  All
+// before it is consumed (one full step of MFMA work between the load and the
+// LDS store that waits for it).  LDS is double-buffered with one barrier per step.  All
 // register arrays are indexed with constants so they stay in VGPRs.
 template <typename T, int LA, int LB, bool FAST>
 __device__ __forceinline__ void gemm_mainloop(floatx4 (&acc)[4][4], T* __restrict__ smem,
@@ -282,24 +282,61 @@ __device__ __forceinline__ void gemm_mainloop(floatx4 (&acc)[4][4], T* __restric
     if (LB == LAY_KC) store_kc<T>(Bs_, rb, tid); else store_mc(Bs_, rb, tid);    \
   } while (0)
   // rac/rbc held tile kt (already in LDS) and now receive tile kt+2;
-  // ran/rbn hold tile kt+1.
+  // ran/rbn hold tile kt+1, which goes to the other LDS buffer.
 #define CRL_STEP(kt, rac, rbc, ran, rbn)                                         \
   do {                                                                           \
-    if ((kt) + 2 < nk) CRL_GLOAD(rac, rbc, kbeg + ((kt) + 2) * BK);             \
+    CRL_GLOAD(rac, rbc, kbeg + ((kt) + 2) * BK);                                 \
     const T* As_ = smem + ((kt) & 1) * STAGE;                                    \
     mma_stage(acc, As_, As_ + kBM * LD, wm, wn, lane);                           \
-    if ((kt) + 1 < nk) CRL_SSTORE(ran, rbn, ((kt) + 1) & 1);                     \
+    CRL_SSTORE(ran, rbn, ((kt) + 1) & 1);                                        \
+    __syncthreads();                                                             \
+  } while (0)
+  // the last two steps fetch nothing; the last one stores nothing
+#define CRL_STEP_NOLOAD(kt, ran, rbn)                                            \
+  do {                                                                           \
+    const T* As_ = smem + ((kt) & 1) * STAGE;                                    \
+    mma_stage(acc, As_, As_ + kBM * LD, wm, wn, lane);                           \
+    CRL_SSTORE(ran, rbn, ((kt) + 1) & 1);                                        \
+    __syncthreads();                                                             \
+  } while (0)
+  // the closing barrier lets the epilogue reuse the stage buffers
+#define CRL_STEP_LAST(kt)                                                        \
+  do {                                                                           \
+    const T* As_ = smem + ((kt) & 1) * STAGE;                                    \
+    mma_stage(acc, As_, As_ + kBM * LD, wm, wn, lane);                           \
     __syncthreads();                                                             \
   } while (0)
   u32x4 ra0[4], rb0[4], ra1[4], rb1[4];
   CRL_GLOAD(ra0, rb0, kbeg);
-  if (nk > 1) CRL_GLOAD(ra1, rb1, kbeg + BK);
+  if (nk == 1) {
+    CRL_SSTORE(ra0, rb0, 0);
+    __syncthreads();
+    CRL_STEP_LAST(0);
+    return;
+  }
+  CRL_GLOAD(ra1, rb1, kbeg + BK);
   CRL_SSTORE(ra0, rb0, 0);
   __syncthreads();
-  for (int kt = 0; kt < nk; kt += 2) {
+  // Steady state in pairs, with every step fetching and storing.  The loop
+  // has a single back edge with the same loads in flight as on entry (tile
+  // kt+1 in set 1), so the compiler's wait before each LDS store covers
+  // only the older register set and never the loads just issued.
+  int kt = 0;
+  for (; kt + 3 < nk; kt += 2) {
     CRL_STEP(kt, ra0, rb0, ra1, rb1);
-    if (kt + 1 < nk) CRL_STEP(kt + 1, ra1, rb1, ra0, rb0);
+    CRL_STEP(kt + 1, ra1, rb1, ra0, rb0);
   }
+  // 2 or 3 steps remain; set 1 holds tile kt+1
+  if (kt + 2 < nk) {
+    CRL_STEP(kt, ra0, rb0, ra1, rb1);        // fetches the last tile kt+2
+    CRL_STEP_NOLOAD(kt + 1, ra0, rb0);
+    CRL_STEP_LAST(kt + 2);
+  } else {
+    CRL_STEP_NOLOAD(kt, ra1, rb1);
+    CRL_STEP_LAST(kt + 1);
+  }
+#undef CRL_STEP_LAST
+#undef CRL_STEP_NOLOAD
 #undef CRL_STEP
 #undef CRL_SSTORE
 #undef CRL_GLOAD

@@ -152,13 +152,16 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
       a.col_s[(int64_t)rb * B + jp + tid] = cs;
     }
   };
+  // the prefetch is unconditional (clamped to the last tile) so the wait
+  // before each LDS store covers exactly the previous fetch
+  const int jlast = c0 + ((c1 - c0 - 1) / kFCols) * kFCols;
   TileRegs<D> pf;
   if (c0 < c1) tile_load<D>(pf, a.psi_b, c0, B, tid);
   for (int j0 = c0; j0 < c1; j0 += kFCols) {
     __syncthreads();
     if (j0 > c0) flush_cols(j0 - kFCols);
     tile_store_rows<D, LDY>(Ys, pf, tid);
-    if (j0 + kFCols < c1) tile_load<D>(pf, a.psi_b, j0 + kFCols, B, tid);
+    tile_load<D>(pf, a.psi_b, min(j0 + kFCols, jlast), B, tid);
     __syncthreads();
     floatx4 acc[4];
 #pragma unroll
@@ -288,13 +291,14 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) acc_dx[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+  const int jlast = c0 + ((c1 - c0 - 1) / kFCols) * kFCols;
   TileRegs<D> pf;
   if (c0 < c1) tile_load<D>(pf, Yb, c0, B, tid);
   for (int j0 = c0; j0 < c1; j0 += kFCols) {
     __syncthreads();
     tile_store_rows<D, LDY>(Ys, pf, tid);
     tile_store_cols<D, LDT>(YsT, pf, tid);
-    if (j0 + kFCols < c1) tile_load<D>(pf, Yb, j0 + kFCols, B, tid);
+    tile_load<D>(pf, Yb, min(j0 + kFCols, jlast), B, tid);
     __syncthreads();
     floatx4 acc[4];
 #pragma unroll
@@ -335,7 +339,7 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
             if (symmetric) gv += pa - dl;
           }
           gv *= inv;
-          if (L2) gv = d > 0.f ? gv / d : 0.f;
+          if (L2) gv = d > 0.f ? gv * __builtin_amdgcn_rcpf(d) : 0.f;
         }
         hsum[r] += gv;
         Gs[wave][(4 * g + r) * LDT + jb * 16 + r16] = f2bf(gv);

@@ -124,4 +124,18 @@ hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, hipStream_
 hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmetric,
                             float beta, bool out_bf16, hipStream_t s);
 
+// actor.hip: the policy step's elementwise/row kernels
+hipError_t launch_actor_head_fwd(const float* out, int ldo, int A, uint64_t seed,
+                                 const int64_t* step, const void* x_sa, void* x_sa2, int ld,
+                                 int d_s, float* eps, float* logpi, int B, bool bf16,
+                                 hipStream_t s);
+hipError_t launch_actor_energy(const float* phi, const float* psi, int D, int l2, float* f,
+                               void* dphi, int B, bool bf16, hipStream_t s);
+hipError_t launch_actor_head_bwd(const float* out, int ldo, int A, const float* eps,
+                                 const float* da, int ldd, const float* log_alpha, float* dout,
+                                 void* dout_t, int B, bool bf16, hipStream_t s);
+hipError_t launch_actor_loss(const float* logpi, const float* f, int B, const float* log_alpha,
+                             float target_entropy, float* loss_out, float* alpha_grad,
+                             hipStream_t s);
+
 }  // namespace crl

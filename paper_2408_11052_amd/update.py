@@ -1,7 +1,9 @@
-"""One contrastive-RL critic update as a sequence of C-ABI calls.
+"""One contrastive-RL update as a sequence of C-ABI calls.
 
 Algorithm 1 (the update loop): sample a batch with hindsight goals, take the
-critic gradient step on the InfoNCE + logsumexp objective.  The batch counter
+critic gradient step on the InfoNCE + logsumexp objective, then (FullUpdate)
+the policy step on the same batch with the updated critic, and the step of
+the entropy coefficient.  The batch counter
 n (the Philox counter word) and the Adam step t live in device memory and are
 advanced by the library on the stream, so the same enqueued sequence can be
 captured once into a HIP graph and replayed for consecutive updates.
@@ -40,15 +42,18 @@ class CriticUpdate:
         self.n = torch.zeros(1, dtype=torch.int64, device=self.dev)  # batch counter
         self.t = torch.zeros(1, dtype=torch.int64, device=self.dev)  # Adam step
 
-    def enqueue(self):
-        """Enqueue one full update on the current stream (no host sync)."""
+    def _critic_step(self, x_sg):
         c = self.crit
         c.crl_sample_relabel(self.obs, self.act, self.seed, self.n, self.idx, self.x_sa,
-                             self.x_g, None)
+                             self.x_g, x_sg)
         c.crl_critic_fwd(self.params, self.pbf, self.x_sa, self.x_g, self.ws, self.loss)
         c.crl_critic_bwd(self.params, self.pbf, self.x_sa, self.x_g, self.ws, self.grads)
         crl_counter_add(self.t, 1)
         crl_adam_step(self.params, self.grads, self.m, self.v, self.pbf, self.t, self.lr)
+
+    def enqueue(self):
+        """Enqueue one critic update on the current stream (no host sync)."""
+        self._critic_step(None)
         crl_counter_add(self.n, 1)
 
     def capture(self, steps: int = 1) -> torch.cuda.CUDAGraph:
@@ -65,6 +70,55 @@ class CriticUpdate:
 
     def close(self):
         self.crit.close()
+
+
+class FullUpdate(CriticUpdate):
+    """Critic update, then the policy and entropy-coefficient steps.
+
+    log alpha and its Adam moments are 4-float vectors so that they meet the
+    16-byte alignment of crl_adam_step; only element 0 is used (the others
+    have zero gradient and stay 0).
+    """
+
+    def __init__(self, w, obs: torch.Tensor, act: torch.Tensor, phi_layers, psi_layers,
+                 actor_layers, seed: int = 2, log_alpha: float = 0.0, device="cuda:0"):
+        super().__init__(w, obs, act, phi_layers, psi_layers, seed=seed, device=device)
+        c = self.crit
+        if not c.has_actor:
+            raise ValueError("the workload has no policy (actor_hidden is empty)")
+        self.policy_lr = float(w.policy_lr)
+        self.alpha_lr = float(w.alpha_lr)
+        self.aparams = torch.from_numpy(c.pack_actor(actor_layers)).to(self.dev)
+        self.apbf = None
+        if w.precision == "bf16":
+            self.apbf = torch.empty(c.nparam_actor, dtype=torch.bfloat16, device=self.dev)
+            crl_cast_bf16(self.aparams, self.apbf)
+        self.agrads = torch.zeros_like(self.aparams)
+        self.am = torch.zeros_like(self.aparams)
+        self.av = torch.zeros_like(self.aparams)
+        self.log_alpha = torch.zeros(4, dtype=torch.float32, device=self.dev)
+        self.log_alpha[0] = float(log_alpha)
+        self.alpha_grad = torch.zeros(4, dtype=torch.float32, device=self.dev)
+        self.m_alpha = torch.zeros(4, dtype=torch.float32, device=self.dev)
+        self.v_alpha = torch.zeros(4, dtype=torch.float32, device=self.dev)
+        self.actor_loss = torch.zeros(4, dtype=torch.float32, device=self.dev)
+
+    def enqueue(self):
+        """Enqueue one full update (critic, policy, alpha) on the current stream."""
+        c = self.crit
+        self._critic_step(self.x_sg)
+        c.crl_actor_step(self.params, self.pbf, self.aparams, self.apbf, self.log_alpha,
+                         self.x_sa, self.x_g, self.x_sg, self.seed, self.n, self.ws,
+                         self.agrads, self.alpha_grad, self.actor_loss)
+        crl_adam_step(self.aparams, self.agrads, self.am, self.av, self.apbf, self.t,
+                      self.policy_lr)
+        crl_adam_step(self.log_alpha, self.alpha_grad, self.m_alpha, self.v_alpha, None,
+                      self.t, self.alpha_lr)
+        crl_counter_add(self.n, 1)
+
+
+def _mlp_macs(dims) -> list:
+    return [dims[i] * dims[i + 1] for i in range(len(dims) - 1)]
 
 
 def critic_step_flops(w) -> dict:
@@ -85,6 +139,25 @@ def critic_step_flops(w) -> dict:
     logits_b = 4 * B * B * D
     return {"enc_fwd": fwd, "enc_bwd": bwd, "logits_fwd": logits_f, "logits_bwd": logits_b,
             "total": fwd + bwd + logits_f + logits_b}
+
+
+def actor_step_flops(w) -> dict:
+    """Algorithmic FLOPs of one policy step (2 per multiply-add).
+
+    Policy MLP forward and backward (dW every layer, dX all but the first);
+    the frozen critic's phi and psi forward on (s, a') and g; the input
+    gradient of phi down to the action columns.
+    """
+    B, D, A = w.batch_size, w.repr_dim, w.act_dim
+    pol = _mlp_macs([w.in_sg, *w.actor_hidden, 2 * A])
+    phi = _mlp_macs([w.in_sa, *w.hidden, D])
+    psi = _mlp_macs([w.goal_dim, *w.hidden, D])
+    pol_f = 2 * B * sum(pol)
+    pol_b = 2 * B * sum(pol) + 2 * B * sum(pol[1:])
+    crit_f = 2 * B * (sum(phi) + sum(psi))
+    phi_dx = 2 * B * sum(phi[1:]) + 2 * B * w.hidden[0] * A
+    return {"policy_fwd": pol_f, "policy_bwd": pol_b, "critic_fwd": crit_f,
+            "phi_input_grad": phi_dx, "total": pol_f + pol_b + crit_f + phi_dx}
 
 
 def adam_bytes(nparam: int, shadow: bool) -> int:

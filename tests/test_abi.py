@@ -19,9 +19,10 @@ def _declared():
     return sorted(set(re.findall(r"CRL_API\s+[\w\s\*]+?\b(crl_\w+)\s*\(", src)))
 
 
-def test_header_declares_the_four_hot_path_calls():
+def test_header_declares_the_hot_path_calls():
     names = _declared()
-    for n in ("crl_sample_relabel", "crl_critic_fwd", "crl_critic_bwd", "crl_adam_step"):
+    for n in ("crl_sample_relabel", "crl_critic_fwd", "crl_critic_bwd", "crl_adam_step",
+              "crl_actor_step"):
         assert n in names
 
 
@@ -70,6 +71,56 @@ def test_create_rejects_bad_config_on_host(field, value, msg):
     assert msg in err
 
 
+@pytest.mark.parametrize("fields,msg", [
+    ({"actor_n_hidden": 2, "actor_hidden": 100}, "actor_hidden"),
+    ({"actor_n_hidden": 2, "actor_hidden": 2048}, "actor_hidden"),
+    ({"actor_n_hidden": 17, "actor_hidden": 64}, "actor_n_hidden"),
+    ({"actor_n_hidden": 0, "actor_hidden": 64}, "actor_hidden"),
+    ({"actor_n_hidden": 2, "actor_hidden": 64, "act_dim": 0}, "act_dim"),
+    ({"actor_n_hidden": 2, "actor_hidden": 64, "target_entropy": float("nan")},
+     "target_entropy"),
+])
+def test_create_rejects_bad_policy_config(fields, msg):
+    rc, err = _create(**fields)
+    assert rc == _lib.CRL_EINVAL
+    assert msg in err
+
+
+def test_policy_config_fields_follow_the_workload():
+    from paper_2408_11052_amd.critic import make_config
+    cfg = make_config(WL.FULL_UPDATE_B4096)
+    assert (cfg.actor_n_hidden, cfg.actor_hidden) == (4, 1024)
+    assert cfg.target_entropy == -WL.FULL_UPDATE_B4096.act_dim
+    cfg = make_config(WL.DOT_B4096_BF16)
+    assert (cfg.actor_n_hidden, cfg.actor_hidden, cfg.target_entropy) == (0, 0, 0.0)
+
+
+def test_ctypes_structs_match_the_c_header(tmp_path):
+    """Size and field offsets of crl_config / crl_layer_info as the C compiler
+    lays them out from include/crl.h, against the ctypes mirror."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in _lib.crl_config._fields_]
+    lines = [f'printf("crl_config %zu\\n", sizeof(crl_config));']
+    lines += [f'printf("crl_config.{f} %zu\\n", offsetof(crl_config, {f}));' for f in fields]
+    lines += ['printf("crl_layer_info %zu\\n", sizeof(crl_layer_info));']
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"crl.h\"\n"
+                   "int main(void) {\n" + "\n".join(lines) + "\nreturn 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    assert int(out["crl_config"]) == C.sizeof(_lib.crl_config)
+    for f in fields:
+        assert int(out[f"crl_config.{f}"]) == getattr(_lib.crl_config, f).offset, f
+    assert int(out["crl_layer_info"]) == C.sizeof(_lib.crl_layer_info)
+
+
 def test_create_rejects_unsupported_combinations():
     rc, err = _create(logits=1)  # fused logits with FP32 tiles
     assert rc == _lib.CRL_EUNSUPPORTED and "BF16" in err
@@ -94,6 +145,10 @@ def test_null_arguments_rejected_without_device():
     assert L.crl_cast_bf16(None, None, 4, None) == _lib.CRL_EINVAL
     assert L.crl_sample_relabel(None, None, None, 1, 2, 0, None, None, None, None, None,
                                 None) == _lib.CRL_EINVAL
+    assert L.crl_actor_step(None, None, None, None, None, None, None, None, None, 0, None,
+                            None, None, None, None, None) == _lib.CRL_EINVAL
+    n64 = C.c_int64()
+    assert L.crl_actor_param_count(None, C.byref(n64)) == _lib.CRL_EINVAL
     n = C.c_int32()
     assert L.crl_timing_count(C.byref(n)) == _lib.CRL_OK
 
