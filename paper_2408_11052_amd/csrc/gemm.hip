@@ -1,5 +1,6 @@
 // Instantiations and host dispatch of the MFMA GEMM.
 #include "internal.hpp"
+#include "gemm_lds.hpp"
 
 namespace crl {
 
@@ -38,6 +39,40 @@ static const char* kernel_name() {
   return names[sizeof(T) == 2][LA][LB][sizeof(OutT) == 2];
 }
 
+template <int LA, int LB, typename OutT, int BN>
+static const char* lds_kernel_name() {
+  static const char* names[2][2][2][2] = {
+      {{{"gemm_lds_kernel<KC,KC,f32,64>", "gemm_lds_kernel<KC,KC,bf16,64>"},
+        {"gemm_lds_kernel<KC,MC,f32,64>", "gemm_lds_kernel<KC,MC,bf16,64>"}},
+       {{"gemm_lds_kernel<MC,KC,f32,64>", "gemm_lds_kernel<MC,KC,bf16,64>"},
+        {"gemm_lds_kernel<MC,MC,f32,64>", "gemm_lds_kernel<MC,MC,bf16,64>"}}},
+      {{{"gemm_lds_kernel<KC,KC,f32>", "gemm_lds_kernel<KC,KC,bf16>"},
+        {"gemm_lds_kernel<KC,MC,f32>", "gemm_lds_kernel<KC,MC,bf16>"}},
+       {{"gemm_lds_kernel<MC,KC,f32>", "gemm_lds_kernel<MC,KC,bf16>"},
+        {"gemm_lds_kernel<MC,MC,f32>", "gemm_lds_kernel<MC,MC,bf16>"}}}};
+  return names[BN == 128][LA][LB][sizeof(OutT) == 2];
+}
+
+// The direct-to-LDS kernel takes a launch whose K ranges are all whole 64-deep
+// steps, with 16-byte rows and N a multiple of 8 (ragged M and N are handled
+// by clamped loads and guarded stores).  Its column tile is 128 wide, as the
+// planned grid; or 64 wide when no problem is wider than 64 (one column tile
+// either way).
+static int lds_path_bn(const GemmParams& P) {
+  int nmax = 0;
+  for (int g = 0; g < P.count; ++g) {
+    const GemmDesc& d = P.d[g];
+    if (d.K % lds::BK || P.k_chunk % lds::BK || d.N % 8) return 0;
+    if (d.lda % 8 || d.ldb % 8 || d.ldc % 8) return 0;
+    if (d.epi == EPI_L2 || d.accumulate) return 0;
+    if ((reinterpret_cast<uintptr_t>(d.A) | reinterpret_cast<uintptr_t>(d.B) |
+         reinterpret_cast<uintptr_t>(d.C)) & 15u)
+      return 0;
+    nmax = d.N > nmax ? d.N : nmax;
+  }
+  return nmax > 64 ? 128 : 64;
+}
+
 template <typename T, int LA, int LB, typename OutT>
 static hipError_t run(GemmParams& P, hipStream_t s) {
   int maxt = 0;
@@ -51,9 +86,21 @@ static hipError_t run(GemmParams& P, hipStream_t s) {
     bytes += (double)sizeof(T) * ((double)d.M * d.K + (double)d.K * d.N) +
              (double)(P.splits > 1 ? 4 : sizeof(OutT)) * d.M * d.N;
   }
-  KTimer t = timing_begin(kernel_name<T, LA, LB, OutT>(), flops, bytes, s);
-  gemm_kernel<T, LA, LB, OutT><<<grid, block, 0, s>>>(P);
-  timing_end(t);
+  int bn = 0;
+  if constexpr (sizeof(T) == 2) bn = lds_path_bn(P);
+  if (bn == 128) {
+    KTimer t = timing_begin(lds_kernel_name<LA, LB, OutT, 128>(), flops, bytes, s);
+    gemm_lds_kernel<LA, LB, OutT, 128><<<grid, lds::NT, 0, s>>>(P);
+    timing_end(t);
+  } else if (bn == 64) {
+    KTimer t = timing_begin(lds_kernel_name<LA, LB, OutT, 64>(), flops, bytes, s);
+    gemm_lds_kernel<LA, LB, OutT, 64><<<grid, lds::NT, 0, s>>>(P);
+    timing_end(t);
+  } else {
+    KTimer t = timing_begin(kernel_name<T, LA, LB, OutT>(), flops, bytes, s);
+    gemm_kernel<T, LA, LB, OutT><<<grid, block, 0, s>>>(P);
+    timing_end(t);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || P.splits <= 1) return e;
   int64_t mn = 0;

@@ -24,11 +24,13 @@ namespace crl {
 constexpr int kFRows = 64;   // rows per workgroup
 constexpr int kFCols = 64;   // columns per tile
 
+// Column splits: enough workgroups for four waves per SIMD (1024 x 4 waves
+// over 1024 SIMDs), at most 16 partials per row to merge.
 int fused_splits(int B) {
   int nrb = (B + kFRows - 1) / kFRows;
-  int S = 512 / nrb;
+  int S = 1024 / nrb;
   if (S < 1) S = 1;
-  if (S > 8) S = 8;
+  if (S > 16) S = 16;
   int cps = (B + S - 1) / S;
   cps = (cps + kFCols - 1) / kFCols * kFCols;
   return (B + cps - 1) / cps;

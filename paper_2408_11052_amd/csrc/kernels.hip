@@ -342,35 +342,40 @@ __device__ inline void load4(const bf16_t* p, float (&o)[4]) {
 
 constexpr int kColRows = 128;  // rows per chunk of the column-sum kernel
 
-// out[k][n] = sum over w of part[w][k][n]: 64 outputs per block, the parts
-// split over 16 wavefronts (w = grp, grp + 16, ...) and combined in LDS in a
-// fixed order.
-__global__ __launch_bounds__(1024) void partial_reduce_kernel(ColReduceArgs a, int nparts,
-                                                              int nk, int N) {
-  __shared__ float red[16][64];
+// out[k][n] = sum over w of part[w][k][n]: 16 outputs per workgroup, the
+// parts split over 16 groups (w = grp, grp + 16, ...; four independent running
+// sums per thread), then a fixed-order tree over the groups in LDS.
+__global__ __launch_bounds__(256) void partial_reduce_kernel(ColReduceArgs a, int nparts,
+                                                             int nk, int N) {
+  __shared__ float red[16][17];
   const int e = blockIdx.y;
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + lane;
-  float s = 0.f;
+  const int col = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int i = blockIdx.x * 16 + col;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
   if (i < nk * N) {
     const float* p = a.part[e] + i;
-    for (int w = grp; w < nparts; w += 16) s += p[(int64_t)w * nk * N];
+    const int64_t st = (int64_t)nk * N;
+    int w = grp;
+    for (; w + 48 < nparts; w += 64) {
+      s0 += p[w * st];
+      s1 += p[(w + 16) * st];
+      s2 += p[(w + 32) * st];
+      s3 += p[(w + 48) * st];
+    }
+    for (; w < nparts; w += 16) s0 += p[w * st];
   }
-  red[grp][lane] = s;
+  red[grp][col] = (s0 + s1) + (s2 + s3);
   __syncthreads();
   for (int h = 8; h >= 1; h >>= 1) {
-    if (grp < h) red[grp][lane] += red[grp + h][lane];
+    if (grp < h) red[grp][col] += red[grp + h][col];
     __syncthreads();
   }
-  if (grp == 0 && i < nk * N) {
-    const int k = i / N, n = i % N;
-    a.out[e][k][n] = red[0][lane];
-  }
+  if (grp == 0 && i < nk * N) a.out[e][i / N][i % N] = red[0][col];
 }
 
 hipError_t launch_partial_reduce(const ColReduceArgs& a, int count, int nparts, int nk,
                                  int N, hipStream_t s) {
-  dim3 grid((nk * N + 63) / 64, count), block(1024);
+  dim3 grid((nk * N + 15) / 16, count), block(256);
   CRL_TIMED("partial_reduce_kernel", 0.0, 4.0 * count * (nparts + 1.0) * nk * N, s,
             partial_reduce_kernel<<<grid, block, 0, s>>>(a, nparts, nk, N));
   return hipGetLastError();
@@ -583,26 +588,33 @@ hipError_t launch_col_lse_partial(const float* F, int B, int ld, int rchunks, fl
 __global__ __launch_bounds__(256) void lse_merge_kernel(const float* __restrict__ pm,
                                                         const float* __restrict__ ps, int nparts,
                                                         int B, float* __restrict__ out) {
-  __shared__ float sm[4][64], ss[4][64];
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int j = blockIdx.x * 64 + lane;
+  // 16 columns per workgroup, the parts split over 16 groups (p = grp,
+  // grp + 16, ...), then a fixed-order tree over the groups in LDS
+  __shared__ float sm[16][17], ss[16][17];
+  const int col = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int j = blockIdx.x * 16 + col;
   float m = -INFINITY, s = 0.f;
   if (j < B)
-    for (int p = grp; p < nparts; p += 4)
+    for (int p = grp; p < nparts; p += 16)
       lse_merge(m, s, pm[(int64_t)p * B + j], ps[(int64_t)p * B + j]);
-  sm[grp][lane] = m;
-  ss[grp][lane] = s;
+  sm[grp][col] = m;
+  ss[grp][col] = s;
   __syncthreads();
-  if (grp == 0 && j < B) {
-#pragma unroll
-    for (int g = 1; g < 4; ++g) lse_merge(m, s, sm[g][lane], ss[g][lane]);
-    out[j] = m + __logf(s);
+  for (int h = 8; h >= 1; h >>= 1) {
+    if (grp < h) {
+      float mm = sm[grp][col], s2 = ss[grp][col];
+      lse_merge(mm, s2, sm[grp + h][col], ss[grp + h][col]);
+      sm[grp][col] = mm;
+      ss[grp][col] = s2;
+    }
+    __syncthreads();
   }
+  if (grp == 0 && j < B) out[j] = sm[0][col] + __logf(ss[0][col]);
 }
 hipError_t launch_lse_merge(const float* pm, const float* ps, int nparts, int B, float* out,
                             hipStream_t s) {
   CRL_TIMED("lse_merge_kernel", 0.0, 4.0 * B * (2.0 * nparts + 1.0), s,
-            lse_merge_kernel<<<(B + 63) / 64, 256, 0, s>>>(pm, ps, nparts, B, out));
+            lse_merge_kernel<<<(B + 15) / 16, 256, 0, s>>>(pm, ps, nparts, B, out));
   return hipGetLastError();
 }
 

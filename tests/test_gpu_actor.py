@@ -81,8 +81,13 @@ CASES = {
     "fp32_dot_ln": SMALL,
     "fp32_l2_relu": SMALL.with_(name="actor_l2_relu", energy_function="l2", activation="relu",
                                 batch_size=133),
+    # 64-deep K steps throughout: the policy's and critic's GEMMs take the
+    # direct-to-LDS kernel, with ragged M (first-layer dW) and N (16-wide head)
     "bf16_dot_ln": SMALL.with_(name="actor_bf16", precision="bf16", logits="fused",
-                               batch_size=264, hidden=(128, 128), actor_hidden=(96, 96, 96)),
+                               batch_size=256, hidden=(128, 128), actor_hidden=(128,) * 3),
+    "bf16_l2_ln_ragged": SMALL.with_(name="actor_bf16_ragged", precision="bf16", logits="fused",
+                                     energy_function="l2", batch_size=264, hidden=(128, 128),
+                                     actor_hidden=(96, 96, 96)),
 }
 
 

@@ -38,6 +38,12 @@ SMALL = [
     WL.SMALL_RELU.with_(name="relu_l2_fwd_bf16_fused_b96", batch_size=96, hidden=(64,),
                         precision="bf16", logits="fused",
                         contrastive_loss_function="fwd_infonce", num_envs=8, episode_len=20),
+    # whole 128 x 128 tiles: the hidden-layer GEMMs (forward, dX, split-K dW)
+    # take the direct-to-LDS kernel, with bias, ReLU and ReLU-mask epilogues
+    WL.DOT_B4096_BF16.with_(name="ln_dot_sym_bf16_fused_b512_tiles", batch_size=512,
+                            hidden=(256,) * 3, num_envs=48, episode_len=50),
+    WL.SMALL_RELU.with_(name="relu_l2_sym_bf16_mat_b384_tiles", batch_size=384,
+                        hidden=(128, 128, 128), precision="bf16", num_envs=32, episode_len=40),
 ]
 
 
