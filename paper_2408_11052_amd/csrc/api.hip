@@ -58,7 +58,20 @@ struct Slots {
   std::vector<int64_t> Z, Hh, mu, rstd;  // per hidden layer
   int64_t out, dout, dout_t;             // [B][out_dim] FP32, FP32, storage type
   int64_t dH, dZ[2];                     // [B][H] storage type
-  int64_t lnpart, cpart;                 // column partials
+  std::vector<int64_t> lnp;              // per hidden layer: LayerNorm column partials
+  std::vector<int64_t> bp;               // per layer: bias column partials, -1 if none
+};
+
+// The nets whose backward runs in the same launches, and the reductions of
+// their gradient partials that follow it.
+struct Group {
+  int nets[2], count;
+  std::vector<int64_t> dwp;              // per layer: dW split-K partials, -1 if unsplit
+  std::vector<RedJob> few, many;         // reduction jobs (few / many parts)
+  RedJob* d_few = nullptr;
+  RedJob* d_many = nullptr;
+  int64_t total4 = 0, nblocks = 0;
+  double few_bytes = 0, many_bytes = 0;
 };
 
 }  // namespace
@@ -73,6 +86,7 @@ struct crl_ctx {
   int esz;                   // bytes per activation element
   Net net[3];
   Slots sl[3];
+  Group grp[2];                  // 0: phi and psi, 1: the policy
   int64_t nparam, nparam_actor;
   std::vector<int64_t> gaps[2];  // (offset, len) pairs of padding: critic, actor vector
   // device tables
@@ -220,6 +234,12 @@ int64_t splitk_need(crl_ctx* x) {
   return need;
 }
 
+int64_t take_bytes(crl_ctx*, int64_t& off, int64_t bytes) {
+  int64_t o = align_up(off, 256);
+  off = o + (bytes > 0 ? bytes : 1);
+  return o;
+}
+
 void plan_slots(crl_ctx* x, int e, int64_t (*take)(crl_ctx*, int64_t&, int64_t), int64_t& off) {
   const Net& N = x->net[e];
   Slots& S = x->sl[e];
@@ -242,14 +262,89 @@ void plan_slots(crl_ctx* x, int e, int64_t (*take)(crl_ctx*, int64_t&, int64_t),
   S.dH = take(x, off, B * H * es);
   S.dZ[0] = take(x, off, B * H * es);
   S.dZ[1] = take(x, off, B * H * es);
-  S.lnpart = x->ln ? take(x, off, (int64_t)x->ln_nparts * 3 * H * 4) : -1;
-  S.cpart = take(x, off, ((B + 127) / 128) * std::max(H, O) * 4);
 }
 
-int64_t take_bytes(crl_ctx*, int64_t& off, int64_t bytes) {
-  int64_t o = align_up(off, 256);
-  off = o + (bytes > 0 ? bytes : 1);
-  return o;
+// dW = in^T . dZ of layer l for the nets of a group: shapes and split plan
+// (the same function plans the workspace and the launch)
+GemmParams dw_params(const crl_ctx* x, const Group& G, int l) {
+  GemmParams P{};
+  P.count = G.count;
+  for (int e = 0; e < G.count; ++e) {
+    const LayerOff& lo = x->net[G.nets[e]].lay[l];
+    P.d[e].M = lo.fan_in;
+    P.d[e].N = lo.fan_out;
+    P.d[e].K = x->B;
+  }
+  P.partial = reinterpret_cast<float*>(1);
+  plan_split_k(P, x->bf16, 512);
+  P.partial = nullptr;
+  return P;
+}
+
+// Partial buffers of a group's backward and the jobs that reduce them into
+// the gradient vector: dW split-K partials, bias column partials (output
+// layer, and ReLU hidden layers), LayerNorm column partials (dg, db_ln, db).
+void plan_group(crl_ctx* x, Group& G, int64_t& off) {
+  const int64_t B = x->B;
+  const int L = x->net[G.nets[0]].L;
+  const int nrb = colsum_chunks(x->B);
+  G.dwp.assign(L + 1, -1);
+  G.few.clear();
+  G.many.clear();
+  auto add = [](std::vector<RedJob>& v, int64_t src, int64_t stride, int64_t dst, int nparts,
+                int n) {
+    RedJob j{};
+    j.src = src; j.stride = stride; j.dst = dst; j.nparts = nparts; j.n = n;
+    v.push_back(j);
+  };
+  for (int e = 0; e < G.count; ++e) {
+    Slots& S = x->sl[G.nets[e]];
+    S.lnp.assign(L, -1);
+    S.bp.assign(L + 1, -1);
+  }
+  for (int l = 0; l <= L; ++l) {
+    const GemmParams P = dw_params(x, G, l);
+    if (P.splits > 1) {
+      int64_t mn = 0;
+      for (int e = 0; e < G.count; ++e) mn = std::max(mn, (int64_t)P.d[e].M * P.d[e].N);
+      G.dwp[l] = take_bytes(x, off, (int64_t)G.count * P.splits * mn * 4);
+      for (int e = 0; e < G.count; ++e)
+        add(G.few, G.dwp[l] + (int64_t)e * P.splits * mn * 4, (int64_t)P.d[e].M * P.d[e].N,
+            x->net[G.nets[e]].lay[l].w, P.splits, P.d[e].M * P.d[e].N);
+    }
+    const bool top = l == L;
+    for (int e = 0; e < G.count; ++e) {
+      const Net& N = x->net[G.nets[e]];
+      Slots& S = x->sl[G.nets[e]];
+      const LayerOff& lo = N.lay[l];
+      if (top || !x->ln) {
+        S.bp[l] = take_bytes(x, off, (int64_t)nrb * lo.fan_out * 4);
+        add(G.many, S.bp[l], lo.fan_out, lo.b, nrb, lo.fan_out);
+      }
+      if (!top && x->ln) {
+        const int H = N.H;
+        S.lnp[l] = take_bytes(x, off, (int64_t)x->ln_nparts * 3 * H * 4);
+        const int64_t dst[3] = {lo.g, lo.be, lo.b};
+        for (int k = 0; k < 3; ++k)
+          add(G.many, S.lnp[l] + (int64_t)k * H * 4, 3 * H, dst[k], x->ln_nparts, H);
+      }
+    }
+  }
+  G.total4 = 0;
+  G.few_bytes = 0;
+  for (RedJob& j : G.few) {
+    j.first = G.total4;
+    G.total4 += j.n / 4;
+    G.few_bytes += 4.0 * j.n * (j.nparts + 1.0);
+  }
+  G.nblocks = 0;
+  G.many_bytes = 0;
+  for (RedJob& j : G.many) {
+    j.first = G.nblocks;
+    G.nblocks += (j.n + 15) / 16;
+    G.many_bytes += 4.0 * j.n * (j.nparts + 1.0);
+  }
+  (void)B;
 }
 
 void plan_workspace(crl_ctx* x) {
@@ -259,6 +354,9 @@ void plan_workspace(crl_ctx* x) {
   x->ln_rows_per_wave = 16;
   x->ln_nparts = ln_bwd_partials(x->B, x->ln_rows_per_wave);
   for (int e = 0; e < (x->actor ? 3 : 2); ++e) plan_slots(x, e, take_bytes, off);
+  x->grp[0].nets[0] = 0; x->grp[0].nets[1] = 1; x->grp[0].count = 2;
+  x->grp[1].nets[0] = 2; x->grp[1].nets[1] = 2; x->grp[1].count = 1;
+  for (int gi = 0; gi < (x->actor ? 2 : 1); ++gi) plan_group(x, x->grp[gi], off);
   x->splitk_floats = splitk_need(x);
   x->splitk = take(x->splitk_floats * 4);
   x->r = take(B * 4);
@@ -391,6 +489,8 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
   const Net& N0 = x->net[nc[0].net];
   const int B = x->B, H = N0.H, L = N0.L;
   const bool grads = nc[0].g != nullptr;
+  const Group& G = x->grp[nc[0].net == 2 ? 1 : 0];
+  if (grads && G.count != count) return fail(CRL_EINVAL, "internal: backward group mismatch");
   float* splitk = WF(ws, x->splitk);
   int cur = 0;
   for (int l = L; l >= 0; --l) {
@@ -401,9 +501,9 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
       dZ[e] = top ? (const void*)W(ws, S.dout_t) : (const void*)W(ws, S.dZ[cur]);
     }
     if (grads) {
-      {  // dW = in^T . dZ  (contraction over the batch)
-        GemmParams P{};
-        P.count = count;
+      {  // dW = in^T . dZ  (contraction over the batch); split-K partials are
+         // reduced once, after the last layer
+        GemmParams P = dw_params(x, G, l);
         int64_t mn = 0;
         for (int e = 0; e < count; ++e) {
           const Net& N = x->net[nc[e].net];
@@ -414,27 +514,28 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
           d.lda = l == 0 ? nc[e].ld : N.H;
           d.B = dZ[e]; d.ldb = lo.fan_out;
           d.C = nc[e].g + lo.w; d.ldc = lo.fan_out;
-          d.M = lo.fan_in; d.N = lo.fan_out; d.K = B;
           d.alpha = 1.f;
           d.epi = EPI_NONE;
           mn = std::max(mn, (int64_t)d.M * d.N);
         }
-        P.partial = splitk;
-        plan_split_k(P, x->bf16, 512);
-        P.partial_len = (int64_t)P.splits * mn;
+        if (P.splits > 1) {
+          P.partial = WF(ws, G.dwp[l]);
+          P.partial_len = (int64_t)P.splits * mn;
+          P.defer_reduce = 1;
+        }
         CRL_HIP(launch_gemm(P, x->bf16, LAY_MC, LAY_MC, false, s), "dW GEMM");
       }
-      // bias gradients of this layer (LayerNorm layers get theirs with dZ)
+      // bias column partials of this layer (LayerNorm layers get theirs with dZ)
       if (top || !x->ln) {
         ColSumArgs ca{};
         for (int e = 0; e < count; ++e) {
           const Slots& S = x->sl[nc[e].net];
           ca.X[e] = top ? (const void*)WF(ws, S.dout) : dZ[e];
-          ca.out[e] = nc[e].g + x->net[nc[e].net].lay[l].b;
-          ca.part[e] = WF(ws, S.cpart);
+          ca.part[e] = WF(ws, S.bp[l]);
         }
         const int Nc = top ? N0.out_dim : H;
-        CRL_HIP(launch_colsum(ca, count, B, Nc, Nc, top ? false : x->bf16, s), "bias gradient");
+        CRL_HIP(launch_colsum_partials(ca, count, B, Nc, Nc, top ? false : x->bf16, s),
+                "bias gradient");
       }
     }
     if (l == 0) {
@@ -478,9 +579,8 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
       plan_split_k(P, x->bf16, 512);
       CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_KC, x->bf16, s), "dX GEMM");
     }
-    if (x->ln) {
+    if (x->ln) {  // column partials of dg, db_ln, db go to the layer's own region
       LnArgs a{};
-      ColReduceArgs ra{};
       for (int e = 0; e < count; ++e) {
         const Slots& S = x->sl[nc[e].net];
         const LayerOff& lp = x->net[nc[e].net].lay[l - 1];
@@ -491,19 +591,18 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
         a.b[e] = nc[e].p + lp.be;
         a.dH[e] = W(ws, S.dH);
         a.dZ[e] = W(ws, S.dZ[nxt]);
-        a.part[e] = WF(ws, S.lnpart);
-        if (grads) {
-          ra.part[e] = a.part[e];
-          ra.out[e][0] = nc[e].g + lp.g;
-          ra.out[e][1] = nc[e].g + lp.be;
-          ra.out[e][2] = nc[e].g + lp.b;
-        }
+        a.part[e] = WF(ws, S.lnp[l - 1]);
       }
       CRL_HIP(launch_ln_swish_bwd(a, count, B, H, x->bf16, x->ln_rows_per_wave, s), "LayerNorm backward");
-      if (grads)
-        CRL_HIP(launch_partial_reduce(ra, count, x->ln_nparts, 3, H, s), "LayerNorm parameter gradients");
     }
     cur = nxt;
+  }
+  if (grads) {
+    const char* wsc = static_cast<const char*>(ws);
+    CRL_HIP(launch_grad_reduce_few(wsc, nc[0].g, G.d_few, (int)G.few.size(), G.total4,
+                                   G.few_bytes, s), "dW split-K reduction");
+    CRL_HIP(launch_grad_reduce_many(wsc, nc[0].g, G.d_many, (int)G.many.size(), G.nblocks,
+                                    G.many_bytes, s), "bias and LayerNorm gradient reduction");
   }
   return CRL_OK;
 }
@@ -523,8 +622,11 @@ int upload(void** dst, const void* src, size_t bytes) {
 
 void free_tables(crl_ctx* x) {
   if (x->d_thr) (void)hipFree(x->d_thr);
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {
     if (x->d_gaps[i]) (void)hipFree(x->d_gaps[i]);
+    if (x->grp[i].d_few) (void)hipFree(x->grp[i].d_few);
+    if (x->grp[i].d_many) (void)hipFree(x->grp[i].d_many);
+  }
 }
 
 }  // namespace
@@ -584,6 +686,12 @@ CRL_API int crl_create(const crl_config* cfg, crl_ctx** out) {
   for (int i = 0; i < 2 && rc == CRL_OK; ++i)
     rc = upload(reinterpret_cast<void**>(&x->d_gaps[i]), x->gaps[i].data(),
                 x->gaps[i].size() * sizeof(int64_t));
+  for (int i = 0; i < 2 && rc == CRL_OK; ++i) {
+    Group& G = x->grp[i];
+    rc = upload(reinterpret_cast<void**>(&G.d_few), G.few.data(), G.few.size() * sizeof(RedJob));
+    if (rc == CRL_OK)
+      rc = upload(reinterpret_cast<void**>(&G.d_many), G.many.data(), G.many.size() * sizeof(RedJob));
+  }
   if (rc != CRL_OK) {
     free_tables(x);
     delete x;

@@ -102,7 +102,7 @@ static hipError_t run(GemmParams& P, hipStream_t s) {
     timing_end(t);
   }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || P.splits <= 1) return e;
+  if (e != hipSuccess || P.splits <= 1 || P.defer_reduce) return e;
   int64_t mn = 0;
   for (int g = 0; g < P.count; ++g) {
     int64_t v = (int64_t)P.d[g].M * P.d[g].N;

@@ -58,7 +58,26 @@ struct GemmParams {
   int k_chunk;         // K range per split (multiple of the K step)
   float* partial;      // splits > 1: partial[g][s][M][N] (FP32, no epilogue)
   int64_t partial_len; // floats per problem in `partial`
+  int defer_reduce;    // splits > 1: leave the partials for a later reduction
 };
+
+// Work item (tile, split, problem) of a workgroup.  Workgroups are dealt to
+// the 8 XCDs round-robin by linear id; the linear id is remapped so that each
+// XCD gets one contiguous eighth of the (problem, split, tile) order -- a run
+// of tiles sharing one K range of one problem, whose operand panels then stay
+// in that XCD's L2.
+struct WorkItem { int tile, split, prob; };
+__device__ __forceinline__ WorkItem gemm_work_item() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy * gridDim.z;
+  int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
+  WorkItem w;
+  w.tile = lin % gx;
+  w.split = (lin / gx) % gy;
+  w.prob = lin / (gx * gy);
+  return w;
+}
 
 template <typename T> struct GemmCfg;
 template <> struct GemmCfg<bf16_t> { static constexpr int BK = 64, VEC = 8; };
@@ -355,17 +374,15 @@ void gemm_kernel(GemmParams P) {
   static_assert(sizeof(T) * 2 * STAGE >= sizeof(float) * kBM * (kBN + 4),
                 "the epilogue tile must fit in the stage buffers");
 
-  const int g = blockIdx.z;
+  const WorkItem wi = gemm_work_item();
+  const int g = wi.prob;
   const GemmDesc& D = P.d[g];
   const int ntile = P.tiles[g];
-  int pid = blockIdx.x;
+  const int pid = wi.tile;
   if (pid >= ntile) return;
-  // XCD-aware order: consecutive workgroup ids go round-robin over the 8
-  // XCDs; give each XCD a contiguous run of tiles so its L2 sees few panels.
-  if ((ntile & 7) == 0 && gridDim.x == (unsigned)ntile) pid = (pid & 7) * (ntile >> 3) + (pid >> 3);
   const int tm = pid / P.tiles_n[g], tn = pid % P.tiles_n[g];
   const int m0 = tm * kBM, n0 = tn * kBN;
-  const int kbeg = blockIdx.y * P.k_chunk;
+  const int kbeg = wi.split * P.k_chunk;
   const int kend = min(D.K, kbeg + P.k_chunk);
 
   const T* __restrict__ A = reinterpret_cast<const T*>(D.A);
@@ -430,7 +447,7 @@ void gemm_kernel(GemmParams P) {
   const int ch = tid & 15;
   const int col0 = n0 + ch * 8;
   if (split) {
-    float* out = P.partial + (int64_t)g * P.partial_len + (int64_t)blockIdx.y * D.M * D.N;
+    float* out = P.partial + (int64_t)g * P.partial_len + (int64_t)wi.split * D.M * D.N;
     const bool vec = (D.N % 4 == 0) && (col0 + 8 <= D.N);
     for (int rl = tid >> 4; rl < kBM; rl += 16) {
       const int row = m0 + rl;

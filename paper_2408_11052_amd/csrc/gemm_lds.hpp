@@ -133,16 +133,15 @@ void gemm_lds_kernel(GemmParams P) {
   constexpr int LDS = 2 * STAGE > EPI ? 2 * STAGE : EPI;
   constexpr int NJ = BN / 32;
   __shared__ __attribute__((aligned(1024))) char smem[LDS];
-  const int gi = blockIdx.z;
+  const WorkItem wi = gemm_work_item();
+  const int gi = wi.prob;
   const GemmDesc& D = P.d[gi];
   const int ntile = P.tiles[gi];
-  int pid = blockIdx.x;
+  const int pid = wi.tile;
   if (pid >= ntile) return;
-  // XCD-aware order, as in gemm_kernel
-  if ((ntile & 7) == 0 && gridDim.x == (unsigned)ntile) pid = (pid & 7) * (ntile >> 3) + (pid >> 3);
   const int tm = pid / P.tiles_n[gi], tn = pid % P.tiles_n[gi];
   const int m0 = tm * BM, n0 = tn * BN;
-  const int kbeg = blockIdx.y * P.k_chunk;
+  const int kbeg = wi.split * P.k_chunk;
   const int nk = (min(D.K, kbeg + P.k_chunk) - kbeg) / BK;  // <= 0: empty split
   const bf16_t* A = reinterpret_cast<const bf16_t*>(D.A);
   const bf16_t* B = reinterpret_cast<const bf16_t*>(D.B);
@@ -205,7 +204,7 @@ void gemm_lds_kernel(GemmParams P) {
   const int rows = min(BM, D.M - m0);
   if (col0 >= D.N) return;
   if (split) {
-    float* out = P.partial + (int64_t)gi * P.partial_len + (int64_t)blockIdx.y * D.M * D.N;
+    float* out = P.partial + (int64_t)gi * P.partial_len + (int64_t)wi.split * D.M * D.N;
     for (int rl = tid / TPR; rl < rows; rl += RSTEP) {
       const float* src = Cs + rl * kLdc + ch * 8;
       float* dst = out + (int64_t)(m0 + rl) * D.N + col0;

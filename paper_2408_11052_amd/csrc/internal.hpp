@@ -70,6 +70,27 @@ struct ColSumArgs {
 };
 hipError_t launch_colsum(const ColSumArgs& a, int count, int B, int N, int ld,
                          bool bf16, hipStream_t s);
+// only the per-chunk partials part[e][ceil(B/128)][N] of launch_colsum
+hipError_t launch_colsum_partials(const ColSumArgs& a, int count, int B, int N, int ld,
+                                  bool bf16, hipStream_t s);
+int colsum_chunks(int B);
+
+// Deferred gradient reductions: g[dst + i] = sum_k part_k[i], part_k at byte
+// offset src + 4 k stride in the workspace, i < n, in the order k = 0, 1, ...
+// (with four interleaved running sums, combined in a fixed order).  `first`
+// is the job's first float4 (few-part jobs) or first 16-output block
+// (many-part jobs) in the launch's index space.
+struct RedJob {
+  int64_t src;
+  int64_t stride;
+  int64_t dst;
+  int64_t first;
+  int32_t nparts, n;
+};
+hipError_t launch_grad_reduce_few(const char* ws, float* g, const RedJob* jobs, int njobs,
+                                  int64_t total4, double bytes, hipStream_t s);
+hipError_t launch_grad_reduce_many(const char* ws, float* g, const RedJob* jobs, int njobs,
+                                   int64_t nblocks, double bytes, hipStream_t s);
 
 hipError_t launch_sqnorm(const float* X, float* out, int B, int D, hipStream_t s);
 hipError_t launch_cast_bf16(const float* src, bf16_t* dst, int64_t n, hipStream_t s);

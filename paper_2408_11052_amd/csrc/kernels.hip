@@ -408,17 +408,25 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(ColSumArgs a, int B
     a.part[e][(int64_t)blockIdx.y * N + n] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
 
-hipError_t launch_colsum(const ColSumArgs& a, int count, int B, int N, int ld, bool bf16,
-                         hipStream_t s) {
+int colsum_chunks(int B) { return (B + kColRows - 1) / kColRows; }
+
+hipError_t launch_colsum_partials(const ColSumArgs& a, int count, int B, int N, int ld,
+                                  bool bf16, hipStream_t s) {
   // N and ld must be multiples of 4 (vector loads of 4 elements)
-  const int nrb = (B + kColRows - 1) / kColRows;
+  const int nrb = colsum_chunks(B);
   dim3 grid((N + 255) / 256, nrb, count), block(256);
   const double cs_bytes = (double)count * B * N * (bf16 ? 2 : 4);
   if (bf16) CRL_TIMED("colsum_partial_kernel", 0.0, cs_bytes, s,
                       colsum_partial_kernel<bf16_t><<<grid, block, 0, s>>>(a, B, N, ld));
   else      CRL_TIMED("colsum_partial_kernel", 0.0, cs_bytes, s,
                       colsum_partial_kernel<float><<<grid, block, 0, s>>>(a, B, N, ld));
-  hipError_t err = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const ColSumArgs& a, int count, int B, int N, int ld, bool bf16,
+                         hipStream_t s) {
+  const int nrb = colsum_chunks(B);
+  hipError_t err = launch_colsum_partials(a, count, B, N, ld, bf16, s);
   if (err != hipSuccess) return err;
   ColReduceArgs r{};
   for (int e = 0; e < count; ++e) { r.part[e] = a.part[e]; r.out[e][0] = a.out[e]; }
@@ -428,6 +436,98 @@ hipError_t launch_colsum(const ColSumArgs& a, int count, int B, int N, int ld, b
 // ---------------------------------------------------------------------------
 // small utilities
 // ---------------------------------------------------------------------------
+// last job whose `first` is <= v (jobs sorted by `first`)
+__device__ inline int find_job(const RedJob* __restrict__ jobs, int njobs, int64_t v) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].first <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// few parts (split-K partials): one float4 of one job per thread
+__global__ __launch_bounds__(256) void grad_reduce_few_kernel(const char* __restrict__ ws,
+                                                              float* __restrict__ g,
+                                                              const RedJob* __restrict__ jobs,
+                                                              int njobs, int64_t total4) {
+  const int64_t v = blockIdx.x * 256ll + threadIdx.x;
+  if (v >= total4) return;
+  const RedJob J = jobs[find_job(jobs, njobs, v)];
+  const int64_t i4 = v - J.first;
+  const float4* p = reinterpret_cast<const float4*>(ws + J.src) + i4;
+  const int64_t st = J.stride / 4;
+  float4 s[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) s[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  int k = 0;
+  for (; k + 3 < J.nparts; k += 4) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 t = p[(k + q) * st];
+      s[q].x += t.x; s[q].y += t.y; s[q].z += t.z; s[q].w += t.w;
+    }
+  }
+  for (; k < J.nparts; ++k) {
+    const float4 t = p[k * st];
+    s[0].x += t.x; s[0].y += t.y; s[0].z += t.z; s[0].w += t.w;
+  }
+  float4 r;
+  r.x = (s[0].x + s[1].x) + (s[2].x + s[3].x);
+  r.y = (s[0].y + s[1].y) + (s[2].y + s[3].y);
+  r.z = (s[0].z + s[1].z) + (s[2].z + s[3].z);
+  r.w = (s[0].w + s[1].w) + (s[2].w + s[3].w);
+  reinterpret_cast<float4*>(g + J.dst)[i4] = r;
+}
+
+// many parts (per-chunk column partials): 16 outputs per workgroup, the parts
+// over 16 groups, then a fixed-order tree in LDS
+__global__ __launch_bounds__(256) void grad_reduce_many_kernel(const char* __restrict__ ws,
+                                                               float* __restrict__ g,
+                                                               const RedJob* __restrict__ jobs,
+                                                               int njobs) {
+  __shared__ float red[16][17];
+  const RedJob J = jobs[find_job(jobs, njobs, blockIdx.x)];
+  const int col = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int64_t i = (blockIdx.x - J.first) * 16 + col;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  if (i < J.n) {
+    const float* p = reinterpret_cast<const float*>(ws + J.src) + i;
+    int k = grp;
+    for (; k + 48 < J.nparts; k += 64) {
+      s0 += p[k * J.stride];
+      s1 += p[(k + 16) * J.stride];
+      s2 += p[(k + 32) * J.stride];
+      s3 += p[(k + 48) * J.stride];
+    }
+    for (; k < J.nparts; k += 16) s0 += p[k * J.stride];
+  }
+  red[grp][col] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  for (int h = 8; h >= 1; h >>= 1) {
+    if (grp < h) red[grp][col] += red[grp + h][col];
+    __syncthreads();
+  }
+  if (grp == 0 && i < J.n) g[J.dst + i] = red[0][col];
+}
+
+hipError_t launch_grad_reduce_few(const char* ws, float* g, const RedJob* jobs, int njobs,
+                                  int64_t total4, double bytes, hipStream_t s) {
+  if (njobs == 0 || total4 == 0) return hipSuccess;
+  CRL_TIMED("grad_reduce_few_kernel", 0.0, bytes, s,
+            grad_reduce_few_kernel<<<(unsigned)((total4 + 255) / 256), 256, 0, s>>>(
+                ws, g, jobs, njobs, total4));
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce_many(const char* ws, float* g, const RedJob* jobs, int njobs,
+                                   int64_t nblocks, double bytes, hipStream_t s) {
+  if (njobs == 0 || nblocks == 0) return hipSuccess;
+  CRL_TIMED("grad_reduce_many_kernel", 0.0, bytes, s,
+            grad_reduce_many_kernel<<<(unsigned)nblocks, 256, 0, s>>>(ws, g, jobs, njobs));
+  return hipGetLastError();
+}
+
 __global__ void sqnorm_kernel(const float* __restrict__ X, float* __restrict__ out, int B, int D) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
