@@ -135,39 +135,39 @@ def cpu_baseline(w, obs, act, phi, psi, budget_s):
                       f"same workload in {dt:.1f} s"}
 
 
-def csrc_digest() -> str:
-    """sha256 over the library's kernel sources (HBM counters taken for one
-    version of the kernels do not describe another)."""
+def source_digest(files) -> str:
+    """sha256 (first 16 hex digits) over library source files, in the given order."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2408_11052_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    for f in files:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/hbm_traffic_b4096.txt: FETCH_SIZE and WRITE_SIZE per dispatch,
-    scaled by the copy calibration), or None if there is none for this kernel
-    or the kernel sources changed since the counters were taken."""
+    scaled by the copy calibration), or None if it holds no line for this
+    kernel or the sources that define the kernel changed since the counters
+    were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_b4096.txt")
     if not os.path.exists(path):
         return None
-    src = None
-    rows = {}
     for line in open(path):
-        line = line.strip()
-        if line.startswith("csrc_sha256_16 "):
-            src = line.split()[1]
-        elif line.startswith("kernel "):
-            parts = dict(p.split("=", 1) for p in line.split()[1:])
-            rows[parts["name"]] = parts
-    if src != csrc_digest() or kernel not in rows:
-        return None
-    return float(rows[kernel]["hbm_bytes_per_launch"])
+        if not line.startswith("kernel "):
+            continue
+        parts = dict(p.split("=", 1) for p in line.split()[1:])
+        if parts.get("name") != kernel:
+            continue
+        try:
+            if source_digest(parts["sources"].split(",")) != parts["sha"]:
+                return None
+        except (KeyError, OSError):
+            return None
+        return float(parts["hbm_bytes_per_launch"])
+    return None
 
 
 def copy_calibration(n):
