@@ -246,7 +246,11 @@ def main():
         top = max(rows, key=lambda r: r[2])
         name, la, kms, kfl, kby = top
         if kfl > 0:
-            peak = PEAK_BF16_TFLOPS if "bf16" in name else PEAK_FP32_TFLOPS
+            # operand precision: the direct-to-LDS GEMM and the fused InfoNCE
+            # kernels always multiply BF16; gemm_kernel names its storage type first
+            bf16_in = (name.startswith("gemm_lds_kernel") or name.startswith("gemm_kernel<bf16")
+                       or name.startswith("infonce"))
+            peak = PEAK_BF16_TFLOPS if bf16_in else PEAK_FP32_TFLOPS
             ach = kfl / la / (kms * 1e-3 / la) / 1e12
             roofline = {"bound": "mfma", "kernel": name, "achieved": round(ach, 2),
                         "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),

@@ -93,30 +93,13 @@ __device__ __forceinline__ void tile_store_rows(bf16_t* __restrict__ Ys, const T
   }
 }
 
-// transposed layout YsT[d][r] (stride LDT)
-template <int D, int LDT>
-__device__ __forceinline__ void tile_store_cols(bf16_t* __restrict__ YsT, const TileRegs<D>& t,
-                                                int tid) {
-  constexpr int VPR = D / 8;
-#pragma unroll
-  for (int i = 0; i < D / 32; ++i) {
-    const int v = tid + i * 256;
-    const int r = v / VPR, c = v % VPR;
-    const u32x4 w = t.v[i];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      YsT[(c * 8 + 2 * q) * LDT + r] = (bf16_t)(w[q] & 0xffffu);
-      YsT[(c * 8 + 2 * q + 1) * LDT + r] = (bf16_t)(w[q] >> 16);
-    }
-  }
-}
-
 template <int KS, int L2>
 __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, int cps) {
   constexpr int D = KS * 32;
   constexpr int LDY = D + 8;
   __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDY];
-  __shared__ float cm_s[4][kFCols], cs_s[4][kFCols];
+  // column (max, sum) of each (wave, 4-row group) for the current tile
+  __shared__ float cm_s[16][kFCols], cs_s[16][kFCols];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
@@ -144,12 +127,13 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
     rsum[r] = 0.f;
   }
 
-  // column (max, sum) partials of the previous tile, merged over the 4 waves
+  // column (max, sum) partials of the previous tile, merged over the 16
+  // (wave, row group) entries in a fixed order
   auto flush_cols = [&](int jp) {
     if (tid < kFCols && jp + tid < c1) {
       float cm = cm_s[0][tid], cs = cs_s[0][tid];
 #pragma unroll
-      for (int w = 1; w < 4; ++w) lse_merge(cm, cs, cm_s[w][tid], cs_s[w][tid]);
+      for (int w = 1; w < 16; ++w) lse_merge(cm, cs, cm_s[w][tid], cs_s[w][tid]);
       a.col_m[(int64_t)rb * B + jp + tid] = cm;
       a.col_s[(int64_t)rb * B + jp + tid] = cs;
     }
@@ -158,12 +142,24 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
   // before each LDS store covers exactly the previous fetch
   const int jlast = c0 + ((c1 - c0 - 1) / kFCols) * kFCols;
   TileRegs<D> pf;
-  if (c0 < c1) tile_load<D>(pf, a.psi_b, c0, B, tid);
+  float nypf[4];
+  auto ny_load = [&](int j0) {
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      const int col = j0 + jb * 16 + r16;
+      nypf[jb] = (L2 && col < c1) ? a.npsi[col] : 0.f;
+    }
+  };
+  if (c0 < c1) { tile_load<D>(pf, a.psi_b, c0, B, tid); ny_load(c0); }
   for (int j0 = c0; j0 < c1; j0 += kFCols) {
     __syncthreads();
     if (j0 > c0) flush_cols(j0 - kFCols);
     tile_store_rows<D, LDY>(Ys, pf, tid);
+    float nyv[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) nyv[jb] = nypf[jb];
     tile_load<D>(pf, a.psi_b, min(j0 + kFCols, jlast), B, tid);
+    ny_load(min(j0 + kFCols, jlast));
     __syncthreads();
     floatx4 acc[4];
 #pragma unroll
@@ -181,7 +177,7 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
     for (int jb = 0; jb < 4; ++jb) {
       const int col = j0 + jb * 16 + r16;
       const bool cv = col < c1;
-      const float ny = (L2 && cv) ? a.npsi[col] : 0.f;
+      const float ny = nyv[jb];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         float v = acc[jb][r];
@@ -204,8 +200,8 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
         for (int jb = 0; jb < 4; ++jb) rsum[r] += __expf(f[jb][r] - rm[r]);
       }
     }
-    // columns: (max, sum) over this wave's 16 rows; the 4 waves are merged
-    // by flush_cols after the next barrier
+    // columns: (max, sum) over this lane's 4 rows, one entry per (wave, row
+    // group); flush_cols merges the 16 entries after the next barrier
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
       float cm = fmaxf(fmaxf(f[jb][0], f[jb][1]), fmaxf(f[jb][2], f[jb][3]));
@@ -214,12 +210,8 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
 #pragma unroll
         for (int r = 0; r < 4; ++r) cs += __expf(f[jb][r] - cm);
       }
-#pragma unroll
-      for (int o = 16; o <= 32; o <<= 1) {
-        float m2 = __shfl_xor(cm, o, 64), s2 = __shfl_xor(cs, o, 64);
-        lse_merge(cm, cs, m2, s2);
-      }
-      if (g == 0) { cm_s[wave][jb * 16 + r16] = cm; cs_s[wave][jb * 16 + r16] = cs; }
+      cm_s[wave * 4 + g][jb * 16 + r16] = cm;
+      cs_s[wave * 4 + g][jb * 16 + r16] = cs;
     }
   }
   if (c0 < c1) {
@@ -245,6 +237,11 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
 
 // TRANS = 0: rows are phi, streamed operand psi -> partials of dphi.
 // TRANS = 1: rows are psi, streamed operand phi -> partials of dpsi.
+// Per 64-column tile: F (MFMA), G (or H) into the wave's own LDS strip, then
+// dX += G . Y with the Y operand read from the row-major tile by the 16-bit
+// transpose read (no transposed copy of the tile is kept).  The tile's
+// column values (the other side's LSE, its penalty factor, |y|^2) are
+// fetched together with the tile, one tile ahead.
 template <int KS, int L2, int TRANS>
 __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, int cps,
                                                           float beta, int symmetric) {
@@ -252,14 +249,18 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
   constexpr int LDY = D + 8;
   constexpr int LDT = kFCols + 8;
   constexpr int NB = D / 16;  // 16-wide output blocks of dX
+  typedef short v4s __attribute__((ext_vector_type(4)));
+  typedef short v8s __attribute__((ext_vector_type(8)));
   __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDY];
-  __shared__ __attribute__((aligned(16))) bf16_t YsT[D * LDT];
   __shared__ __attribute__((aligned(16))) bf16_t Gs[4][16 * LDT];
 
   const bf16_t* Xb = TRANS ? a.psi_b : a.phi_b;
   const bf16_t* Yb = TRANS ? a.phi_b : a.psi_b;
   const float* nX = TRANS ? a.npsi : a.nphi;
   const float* nY = TRANS ? a.nphi : a.npsi;
+  // TRANS=0: rows own r_i (and the penalty), columns own c_j; TRANS=1: swapped
+  const float* lseX = TRANS ? a.c : a.r;
+  const float* lseY = TRANS ? a.r : a.c;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
@@ -284,8 +285,7 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
     const int row = row_base + 4 * g + r;
     rvalid[r] = row < B;
     nx[r] = (L2 && rvalid[r]) ? nX[row] : 0.f;
-    // TRANS=0: the row owns r_i (and the penalty); TRANS=1: the row owns c_j
-    lse_a[r] = rvalid[r] ? (TRANS ? a.c[row] : a.r[row]) : 0.f;
+    lse_a[r] = rvalid[r] ? lseX[row] : 0.f;
     pen_a[r] = rvalid[r] ? (TRANS ? 0.f : 2.f * beta * a.r[row]) : 0.f;
     hsum[r] = 0.f;
   }
@@ -293,14 +293,29 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) acc_dx[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+  // per-lane column values of a tile (columns j0 + jb*16 + r16)
+  struct ColVals { float lse[4], pen[4], ny[4]; };
+  auto col_load = [&](ColVals& cvv, int j0) {
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      const int col = j0 + jb * 16 + r16;
+      const bool cv = col < c1;
+      cvv.lse[jb] = cv ? lseY[col] : 0.f;
+      cvv.pen[jb] = (cv && TRANS) ? 2.f * beta * a.r[col] : 0.f;
+      cvv.ny[jb] = (L2 && cv) ? nY[col] : 0.f;
+    }
+  };
+
   const int jlast = c0 + ((c1 - c0 - 1) / kFCols) * kFCols;
   TileRegs<D> pf;
-  if (c0 < c1) tile_load<D>(pf, Yb, c0, B, tid);
+  ColVals cpf;
+  if (c0 < c1) { tile_load<D>(pf, Yb, c0, B, tid); col_load(cpf, c0); }
   for (int j0 = c0; j0 < c1; j0 += kFCols) {
     __syncthreads();
     tile_store_rows<D, LDY>(Ys, pf, tid);
-    tile_store_cols<D, LDT>(YsT, pf, tid);
+    const ColVals cvals = cpf;
     tile_load<D>(pf, Yb, min(j0 + kFCols, jlast), B, tid);
+    col_load(cpf, min(j0 + kFCols, jlast));
     __syncthreads();
     floatx4 acc[4];
 #pragma unroll
@@ -312,32 +327,28 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
         acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b, acc[jb], 0, 0, 0);
       }
     }
-    // G (or H = G/d for L2) for this tile, written to the wave's LDS strip
+    // G (or H = G/d for L2) for this tile, into the wave's own LDS strip
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
       const int col = j0 + jb * 16 + r16;
       const bool cv = col < c1;
-      const float ny = (L2 && cv) ? nY[col] : 0.f;
-      // TRANS=0: the column owns c_j; TRANS=1: the column owns r_i (+ penalty)
-      const float lse_b = cv ? (TRANS ? a.r[col] : a.c[col]) : 0.f;
-      const float pen_b = (cv && TRANS) ? 2.f * beta * a.r[col] : 0.f;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row_base + 4 * g + r;
         float v = acc[jb][r];
         float d = 0.f;
-        if (L2) { d = sqrtf(fmaxf(nx[r] + ny - 2.f * v, 0.f)); v = -d; }
+        if (L2) { d = sqrtf(fmaxf(nx[r] + cvals.ny[jb] - 2.f * v, 0.f)); v = -d; }
         float gv = 0.f;
         if (cv && rvalid[r]) {
           const float dl = (row == col) ? 1.f : 0.f;
           // rows-side and columns-side softmax terms
           const float pa = __expf(v - lse_a[r]);
-          const float pb = __expf(v - lse_b);
+          const float pb = __expf(v - cvals.lse[jb]);
           if (TRANS == 0) {
             gv = pa * (1.f + pen_a[r]) - dl;
             if (symmetric) gv += pb - dl;
           } else {
-            gv = pb * (1.f + pen_b) - dl;
+            gv = pb * (1.f + cvals.pen[jb]) - dl;
             if (symmetric) gv += pa - dl;
           }
           gv *= inv;
@@ -347,15 +358,27 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
         Gs[wave][(4 * g + r) * LDT + jb * 16 + r16] = f2bf(gv);
       }
     }
-    __syncthreads();
-    // dX[16 rows][D] += G[16][64] . Y[64][D]
+    // only this wave reads its strip back: a wave-local LDS wait suffices
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    // dX[16 rows][D] += G[16][64] . Y[64][D]; lane (g, j) needs Y[8g + 0..7][d]
+    // of column d = nb*16 + j: two transpose reads of 4 rows each
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
       bf16x8 ga = *reinterpret_cast<const bf16x8*>(&Gs[wave][r16 * LDT + kk * 32 + g * 8]);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        bf16x8 yb = *reinterpret_cast<const bf16x8*>(YsT + (nb * 16 + r16) * LDT + kk * 32 + g * 8);
-        acc_dx[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, yb, acc_dx[nb], 0, 0, 0);
+        v4s h[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int jrow = kk * 32 + 8 * g + 4 * t + (r16 >> 2);
+          const int dcol = nb * 16 + 4 * (r16 & 3);
+          h[t] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+              (__attribute__((address_space(3))) v4s*)(Ys + jrow * LDY + dcol));
+        }
+        v8s yv = {h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+        acc_dx[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, __builtin_bit_cast(bf16x8, yv),
+                                                             acc_dx[nb], 0, 0, 0);
       }
     }
   }
