@@ -1,16 +1,22 @@
-"""Benchmark of the contrastive-RL critic update on one MI355X.
+"""Benchmark of the contrastive-RL update on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-A step is one whole update: relabel + gather from the GPU-resident replay
-buffer, phi/psi encoders, critic matrix + InfoNCE + logsumexp penalty,
+A step is one whole critic update: relabel + gather from the GPU-resident
+replay buffer, phi/psi encoders, critic matrix + InfoNCE + logsumexp penalty,
 backward through everything, Adam.  The default workload is the B=4096,
 4x1024 LayerNorm+Swish, dot-energy, symmetric-InfoNCE update with BF16 MFMA
 tiles and the fused (never materialised) logits; its K steps are replayed
-from one captured HIP graph.  Beside it the same update is timed on the plain
-FP32 path (FP32 MFMA tiles, materialised B x B logits, eager launches), the
-per-kernel times are taken with HIP events in an instrumented eager pass, and
-the FP64 oracle is timed on the host cores on a bounded sample.
+from captured HIP graphs.  Beside it:
+  - the same update on the plain FP32 path (FP32 MFMA tiles, materialised
+    B x B logits), eager and from a graph;
+  - per-kernel times from HIP events in an instrumented eager pass;
+  - the full update (the same critic step, then the 4x1024 tanh-Gaussian
+    policy step and the entropy-coefficient step), 1000 consecutive steps
+    from captured graphs;
+  - the B=16384, D=256 L2-energy update (fused: its B x B logits are never
+    stored) with its peak HBM use;
+  - the FP64 oracle on the host cores, on a bounded sample.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -52,6 +58,11 @@ def parse():
                     help="consecutive full updates (critic, policy, alpha) timed")
     ap.add_argument("--full-graph-steps", type=int, default=100)
     ap.add_argument("--no-full", action="store_true")
+    ap.add_argument("--large-workload", default="b16384_lnswish2x1024_d256_l2_sym")
+    ap.add_argument("--large-steps", type=int, default=100,
+                    help="updates timed on the large-batch fused workload (never materialises "
+                         "the B x B logits)")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -310,6 +321,38 @@ def main():
         del fu
         torch.cuda.empty_cache()
 
+    large = None
+    if not args.no_large:
+        wl = WORKLOADS[args.large_workload]
+        log(f"[bench] large-batch workload {wl.name}: buffer {wl.num_envs} x {wl.episode_len} x "
+            f"{wl.obs_dim}")
+        lobs, lact = buffer_for(wl, seed=0)
+        lp, lq = critic_params_for(wl, seed=1)
+        ld_obs = torch.from_numpy(lobs).to(dev)
+        ld_act = torch.from_numpy(lact).to(dev)
+        del lobs, lact
+        torch.cuda.reset_peak_memory_stats()
+        lu = CriticUpdate(wl, ld_obs, ld_act, lp, lq, seed=2)
+        lfl = critic_step_flops(wl)["total"]
+        dtl, nl = time_steps(lu, args.large_steps, 5, 10)
+        peak_l = torch.cuda.max_memory_allocated() / 2**30
+        # the B x B FP32 logits this workload never stores
+        dense = wl.batch_size * wl.batch_size * 4 / 2**30
+        large = {"workload": wl.name, "batch": wl.batch_size, "steps": nl,
+                 "steps_per_s": round(nl / dtl, 2), "ms_per_step": round(1e3 * dtl / nl, 4),
+                 "gflop_per_step": round(lfl / 1e9, 3),
+                 "tflops": round(lfl * nl / dtl / 1e12, 2),
+                 "tflops_frac_bf16_peak": round(lfl * nl / dtl / 1e12 / PEAK_BF16_TFLOPS, 4),
+                 "peak_hbm_gib": round(peak_l, 2), "workspace_gib": round(lu.crit.ws_bytes / 2**30, 3),
+                 "dense_logits_gib_not_stored": round(dense, 2),
+                 "loss": round(float(lu.loss[0]), 5)}
+        log(f"[bench] large batch: {nl / dtl:.1f} steps/s, {1e3 * dtl / nl:.3f} ms/step, "
+            f"{lfl * nl / dtl / 1e12:.1f} TFLOP/s; peak HBM {peak_l:.2f} GiB (buffer included), "
+            f"workspace {lu.crit.ws_bytes / 2**30:.2f} GiB; B x B logits would be {dense:.2f} GiB")
+        lu.close()
+        del lu, ld_obs, ld_act
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu:
         log(f"[bench] FP64 oracle on the host cores (~{args.cpu_seconds:.0f} s)")
@@ -344,6 +387,7 @@ def main():
         "speedup_vs_fp32_plain": round(sps / fp32["steps_per_s"], 2) if fp32 else None,
         "peak_hbm_gib": round(peak_mem, 2),
         "full_update": full,
+        "large_batch": large,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
