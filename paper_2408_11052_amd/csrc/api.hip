@@ -450,6 +450,10 @@ int mlp_forward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t 
       d.B = weights(x, nc[e], lo.w);
       d.ldb = lo.fan_out;
       d.M = B; d.N = lo.fan_out; d.K = lo.fan_in;
+      if (l == 0 && x->bf16) {  // zero input columns up to the padded stride
+        d.K = (int)align_up(lo.fan_in, 64);
+        d.kb = lo.fan_in;
+      }
       d.bias = nc[e].p + lo.b;
       d.alpha = 1.f;
       if (top) { d.C = W(ws, S.out); d.epi = EPI_BIAS; }
@@ -657,16 +661,18 @@ CRL_API int crl_create(const crl_config* cfg, crl_ctx** out) {
   x->A = cfg->act_dim;
   x->P = (int)align_up(2 * cfg->act_dim, 8);
   x->esz = x->bf16 ? 2 : 4;
-  x->ld_sg = (int)align_up(cfg->obs_dim + cfg->goal_dim, 8);
   const int fan_in0[3] = {cfg->obs_dim + cfg->act_dim, cfg->goal_dim, cfg->obs_dim + cfg->goal_dim};
   for (int e = 0; e < 3; ++e) {
     Net& N = x->net[e];
     N.fan_in0 = fan_in0[e];
-    N.ld_in = (int)align_up(fan_in0[e], 8);
+    // BF16 inputs are padded with zero columns to whole 64-deep K steps, so
+    // the first layer runs on the direct-to-LDS GEMM too
+    N.ld_in = (int)align_up(fan_in0[e], x->bf16 ? 64 : 8);
     N.H = e < 2 ? x->H : cfg->actor_hidden;
     N.L = e < 2 ? x->L : cfg->actor_n_hidden;
     N.out_dim = e < 2 ? x->D : x->P;
   }
+  x->ld_sg = x->net[2].ld_in;
   x->nparam = plan_params(x, 0, 1, x->gaps[0]);
   x->nparam_actor = x->actor ? plan_params(x, 2, 2, x->gaps[1]) : 0;
   for (int i = 0; i < 2; ++i) x->n_gaps[i] = (int)(x->gaps[i].size() / 2);

@@ -79,22 +79,29 @@ static hipError_t run(GemmParams& P, hipStream_t s) {
   for (int g = 0; g < P.count; ++g) maxt = P.tiles[g] > maxt ? P.tiles[g] : maxt;
   if (maxt == 0) return hipSuccess;
   dim3 grid(maxt, P.splits, P.count), block(kGemmThreads);
-  double flops = 0.0, bytes = 0.0;
-  for (int g = 0; g < P.count; ++g) {
-    const GemmDesc& d = P.d[g];
-    flops += 2.0 * d.M * d.N * d.K;
-    bytes += (double)sizeof(T) * ((double)d.M * d.K + (double)d.K * d.N) +
-             (double)(P.splits > 1 ? 4 : sizeof(OutT)) * d.M * d.N;
-  }
   int bn = 0;
   if constexpr (sizeof(T) == 2) bn = lds_path_bn(P);
+  if (bn == 0)  // the register-staged kernel handles any K: drop zero-padded K
+    for (int g = 0; g < P.count; ++g)
+      if (P.d[g].kb > 0) {
+        P.d[g].K = P.d[g].kb;
+        P.d[g].kb = 0;
+      }
+  double flops = 0.0, bytes = 0.0;  // algorithmic: the unpadded K
+  for (int g = 0; g < P.count; ++g) {
+    const GemmDesc& d = P.d[g];
+    const double k = d.kb > 0 ? d.kb : d.K;
+    flops += 2.0 * d.M * d.N * k;
+    bytes += (double)sizeof(T) * ((double)d.M * k + k * d.N) +
+             (double)(P.splits > 1 ? 4 : sizeof(OutT)) * d.M * d.N;
+  }
   if (bn == 128) {
     KTimer t = timing_begin(lds_kernel_name<LA, LB, OutT, 128>(), flops, bytes, s);
-    gemm_lds_kernel<LA, LB, OutT, 128><<<grid, lds::NT, 0, s>>>(P);
+    gemm_lds_kernel<LA, LB, OutT, 128><<<grid, lds::threads<128>(), 0, s>>>(P);
     timing_end(t);
   } else if (bn == 64) {
     KTimer t = timing_begin(lds_kernel_name<LA, LB, OutT, 64>(), flops, bytes, s);
-    gemm_lds_kernel<LA, LB, OutT, 64><<<grid, lds::NT, 0, s>>>(P);
+    gemm_lds_kernel<LA, LB, OutT, 64><<<grid, lds::threads<64>(), 0, s>>>(P);
     timing_end(t);
   } else {
     KTimer t = timing_begin(kernel_name<T, LA, LB, OutT>(), flops, bytes, s);

@@ -44,6 +44,9 @@ struct GemmDesc {
   int epi;
   float alpha;
   int accumulate;     // C += result (read-modify-write of C)
+  int kb;             // rows k < kb of an MC-layout B exist (0: all K).  The
+                      // direct-to-LDS kernel re-reads row kb-1 for k >= kb;
+                      // the caller guarantees A is zero in those columns
 };
 
 constexpr int kGemmMaxGroup = 2;

@@ -5,7 +5,9 @@
 // their 16-byte chunks; tiles contiguous along M or N (MC) are read with the
 // 16-bit transpose read ds_read_b64_tr_b16, which turns four rows of 4 x 16-bit
 // chunks into the per-lane K runs the MFMA wants.  Tiles are 128 x BN with BN
-// 128 or 64.  M and N may be ragged (loads past the edge are clamped into the
+// 128 or 64, computed by BN/16 waves of 64 x 32 each (eight or four waves: more
+// resident waves hide more of the load and barrier latency than larger
+// per-wave blocks save in LDS reads).  M and N may be ragged (loads past the edge are clamped into the
 // operand and the results they feed are not stored); every K range must be a
 // whole number of 64-deep steps, otherwise gemm_kernel takes the launch.
 #pragma once
@@ -14,7 +16,10 @@
 namespace crl {
 namespace lds {
 
-constexpr int BM = 128, BK = 64, NT = 256;
+constexpr int BM = 128, BK = 64;
+// waves and threads of a 128 x BN tile: a 2 x (BN/32) grid of 64 x 32 blocks
+template <int BN> constexpr int waves() { return BN / 16; }
+template <int BN> constexpr int threads() { return 64 * waves<BN>(); }
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) v4s lds_v4s;
@@ -38,18 +43,21 @@ template <> __device__ __forceinline__ int mc_swz<64>(int kr) {
   return 2 * (((kr >> 1) & 1) + 2 * ((kr >> 3) & 1));
 }
 
-// One wave instruction fills one 1 KB block of the tile; the 4 waves take
-// blocks wave, wave+4, ...  W = extent of the tile along M or N; R = extent of
-// the operand along it.  A KC row past R re-reads row R-1, an MC chunk past
-// the row stride re-reads the last chunk: in bounds, and only ever feeding
-// outputs that are not stored.
-template <int LAY, int W>
+// One wave instruction fills one 1 KB block of the tile; the NW waves take
+// blocks wave, wave+NW, ...  W = extent of the tile along M or N; R = extent of
+// the operand along it; KR = k-rows of an MC operand that exist.  A KC row
+// past R re-reads row R-1, an MC chunk past the row stride re-reads the last
+// chunk (in bounds, and only ever feeding outputs that are not stored); an MC
+// k-row past KR re-reads row KR-1, which meets zero columns of the other
+// operand.
+template <int LAY, int W, int NW>
 __device__ __forceinline__ void issue_tile(const bf16_t* __restrict__ X, int ld, int r0, int R,
-                                           int k0, char* tile, int wave, int lane) {
+                                           int KR, int k0, char* tile, int wave, int lane) {
   constexpr int NBLK = tile_bytes<W>() / 1024;
+  static_assert(NBLK % NW == 0, "whole blocks per wave");
 #pragma unroll
-  for (int i = 0; i < NBLK / 4; ++i) {
-    const int blk = wave + 4 * i;
+  for (int i = 0; i < NBLK / NW; ++i) {
+    const int blk = wave + NW * i;
     const bf16_t* src;
     if (LAY == LAY_KC) {  // 8 rows of 128 B per block
       const int r = blk * 8 + (lane >> 3);
@@ -59,7 +67,7 @@ __device__ __forceinline__ void issue_tile(const bf16_t* __restrict__ X, int ld,
       constexpr int LPR = W / 8;  // lanes (chunks) per k-row
       const int kr = blk * (64 / LPR) + lane / LPR;
       const int c = (lane % LPR) ^ mc_swz<W>(kr);
-      src = X + (int64_t)(k0 + kr) * ld + min(r0 + 8 * c, ld - 8);
+      src = X + (int64_t)min(k0 + kr, KR - 1) * ld + min(r0 + 8 * c, ld - 8);
     }
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(tile + blk * 1024),
                                      16, 0, 0);
@@ -89,11 +97,11 @@ __device__ __forceinline__ bf16x8 frag_mc(const char* tile, int mb, int hh, int 
 }
 
 // one 64-deep stage: wave (wm, wn) owns rows wm*64 + 0..63, columns
-// wn*BN/2 + 0..BN/2-1 of the tile
+// wn*32 + 0..31 of the tile
 template <int LA, int LB, int BN>
-__device__ __forceinline__ void compute_tile(floatx4 (&acc)[4][BN / 32], const char* At,
+__device__ __forceinline__ void compute_tile(floatx4 (&acc)[4][2], const char* At,
                                              const char* Bt, int wm, int wn, int lane) {
-  constexpr int NJ = BN / 32;
+  constexpr int NJ = 2;
   const int g = lane >> 4, j = lane & 15;
 #pragma unroll
   for (int hh = 0; hh < 2; ++hh) {
@@ -104,8 +112,8 @@ __device__ __forceinline__ void compute_tile(floatx4 (&acc)[4][BN / 32], const c
                           : frag_mc<BM>(At, wm * 64 + i * 16, hh, g, j);
 #pragma unroll
     for (int i = 0; i < NJ; ++i)
-      b[i] = LB == LAY_KC ? frag_kc(Bt, wn * (BN / 2) + i * 16 + j, hh, g)
-                          : frag_mc<BN>(Bt, wn * (BN / 2) + i * 16, hh, g, j);
+      b[i] = LB == LAY_KC ? frag_kc(Bt, wn * 32 + i * 16 + j, hh, g)
+                          : frag_mc<BN>(Bt, wn * 32 + i * 16, hh, g, j);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -122,16 +130,19 @@ template <int N> __device__ __forceinline__ void wait_vm() {
 
 }  // namespace lds
 
+// two workgroups per CU: 2 * waves<BN>() waves over the 4 SIMDs
 template <int LA, int LB, typename OutT, int BN>
-__global__ __launch_bounds__(lds::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ __launch_bounds__(lds::threads<BN>())
+__attribute__((amdgpu_waves_per_eu(lds::waves<BN>() / 2, lds::waves<BN>() / 2)))
 void gemm_lds_kernel(GemmParams P) {
   using namespace lds;
+  constexpr int NW = waves<BN>(), NT = threads<BN>();
   constexpr int TA = tile_bytes<BM>(), TB = tile_bytes<BN>();
   constexpr int STAGE = TA + TB;
   constexpr int kLdc = BN + 4;
   constexpr int EPI = (int)sizeof(float) * BM * kLdc;
   constexpr int LDS = 2 * STAGE > EPI ? 2 * STAGE : EPI;
-  constexpr int NJ = BN / 32;
+  constexpr int NJ = 2;
   __shared__ __attribute__((aligned(1024))) char smem[LDS];
   const WorkItem wi = gemm_work_item();
   const int gi = wi.prob;
@@ -145,8 +156,9 @@ void gemm_lds_kernel(GemmParams P) {
   const int nk = (min(D.K, kbeg + P.k_chunk) - kbeg) / BK;  // <= 0: empty split
   const bf16_t* A = reinterpret_cast<const bf16_t*>(D.A);
   const bf16_t* B = reinterpret_cast<const bf16_t*>(D.B);
+  const int kb = D.kb > 0 ? D.kb : D.K;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / (NW / 2), wn = wave % (NW / 2);
   floatx4 acc[4][NJ];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -155,8 +167,8 @@ void gemm_lds_kernel(GemmParams P) {
 
   auto issue = [&](int t) {
     char* st = smem + (t & 1) * STAGE;
-    issue_tile<LA, BM>(A, D.lda, m0, D.M, kbeg + t * BK, st, wave, lane);
-    issue_tile<LB, BN>(B, D.ldb, n0, D.N, kbeg + t * BK, st + TA, wave, lane);
+    issue_tile<LA, BM, NW>(A, D.lda, m0, D.M, D.K, kbeg + t * BK, st, wave, lane);
+    issue_tile<LB, BN, NW>(B, D.ldb, n0, D.N, kb, kbeg + t * BK, st + TA, wave, lane);
   };
   if (nk > 0) issue(0);
   for (int kt = 0; kt < nk; ++kt) {
@@ -175,23 +187,23 @@ void gemm_lds_kernel(GemmParams P) {
   const int r16 = lane & 15, gq = lane >> 4;
   float* Cs = reinterpret_cast<float*>(smem);
   const bool split = P.splits > 1;
+  const bool has_bias = !split && (D.epi == EPI_BIAS || D.epi == EPI_BIAS_RELU);
+  float bcol[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)  // clamped column: past-the-edge values are not stored
+    bcol[j] = has_bias ? D.bias[min(n0 + wn * 32 + j * 16 + r16, D.N - 1)] : 0.f;
+  const float alpha = split ? 1.f : D.alpha;
+  const bool relu = !split && D.epi == EPI_BIAS_RELU;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int cl = wn * (BN / 2) + j * 16 + r16;
-      float bcol = 0.f;
-      if (!split && (D.epi == EPI_BIAS || D.epi == EPI_BIAS_RELU) && n0 + cl < D.N)
-        bcol = D.bias[n0 + cl];
+      const int cl = wn * 32 + j * 16 + r16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rl = wm * 64 + i * 16 + gq * 4 + r;
-        float v = acc[i][j][r];
-        if (!split) {
-          v *= D.alpha;
-          if (D.epi == EPI_BIAS) v += bcol;
-          else if (D.epi == EPI_BIAS_RELU) v = fmaxf(v + bcol, 0.f);
-        }
+        float v = acc[i][j][r] * alpha + bcol[j];
+        if (relu) v = fmaxf(v, 0.f);
         Cs[rl * kLdc + cl] = v;
       }
     }
