@@ -67,6 +67,7 @@ struct Slots {
 struct Group {
   int nets[2], count;
   std::vector<int64_t> dwp;              // per layer: dW split-K partials, -1 if unsplit
+  std::vector<int> dwbn;                 // per layer: column tile of the LDS kernel (0: dense partials)
   std::vector<RedJob> few, many;         // reduction jobs (few / many parts)
   RedJob* d_few = nullptr;
   RedJob* d_many = nullptr;
@@ -91,8 +92,6 @@ struct crl_ctx {
   std::vector<int64_t> gaps[2];  // (offset, len) pairs of padding: critic, actor vector
   // device tables
   uint64_t* d_thr;
-  int64_t* d_gaps[2];
-  int n_gaps[2];
   // workspace plan (byte offsets)
   int64_t ws_bytes;
   int64_t splitk, splitk_floats;
@@ -270,10 +269,13 @@ GemmParams dw_params(const crl_ctx* x, const Group& G, int l) {
   GemmParams P{};
   P.count = G.count;
   for (int e = 0; e < G.count; ++e) {
-    const LayerOff& lo = x->net[G.nets[e]].lay[l];
+    const Net& N = x->net[G.nets[e]];
+    const LayerOff& lo = N.lay[l];
     P.d[e].M = lo.fan_in;
     P.d[e].N = lo.fan_out;
     P.d[e].K = x->B;
+    P.d[e].lda = l == 0 ? N.ld_in : N.H;
+    P.d[e].ldb = P.d[e].ldc = lo.fan_out;
   }
   P.partial = reinterpret_cast<float*>(1);
   plan_split_k(P, x->bf16, 512);
@@ -284,11 +286,13 @@ GemmParams dw_params(const crl_ctx* x, const Group& G, int l) {
 // Partial buffers of a group's backward and the jobs that reduce them into
 // the gradient vector: dW split-K partials, bias column partials (output
 // layer, and ReLU hidden layers), LayerNorm column partials (dg, db_ln, db).
-void plan_group(crl_ctx* x, Group& G, int64_t& off) {
+void plan_group(crl_ctx* x, int gi, int64_t& off) {
+  Group& G = x->grp[gi];
   const int64_t B = x->B;
   const int L = x->net[G.nets[0]].L;
   const int nrb = colsum_chunks(x->B);
   G.dwp.assign(L + 1, -1);
+  G.dwbn.assign(L + 1, 0);
   G.few.clear();
   G.many.clear();
   auto add = [](std::vector<RedJob>& v, int64_t src, int64_t stride, int64_t dst, int nparts,
@@ -305,12 +309,23 @@ void plan_group(crl_ctx* x, Group& G, int64_t& off) {
   for (int l = 0; l <= L; ++l) {
     const GemmParams P = dw_params(x, G, l);
     if (P.splits > 1) {
-      int64_t mn = 0;
-      for (int e = 0; e < G.count; ++e) mn = std::max(mn, (int64_t)P.d[e].M * P.d[e].N);
-      G.dwp[l] = take_bytes(x, off, (int64_t)G.count * P.splits * mn * 4);
-      for (int e = 0; e < G.count; ++e)
-        add(G.few, G.dwp[l] + (int64_t)e * P.splits * mn * 4, (int64_t)P.d[e].M * P.d[e].N,
-            x->net[G.nets[e]].lay[l].w, P.splits, P.d[e].M * P.d[e].N);
+      // partial layout of the kernel that will run: fragment order on the
+      // direct-to-LDS kernel, dense otherwise
+      const int bn = gemm_lds_bn(P, x->bf16);
+      int64_t ps = 0;
+      for (int e = 0; e < G.count; ++e) ps = std::max(ps, frag_partial_floats(P, e, bn));
+      G.dwbn[l] = bn;
+      G.dwp[l] = take_bytes(x, off, (int64_t)G.count * P.splits * ps * 4);
+      for (int e = 0; e < G.count; ++e) {
+        RedJob j{};
+        j.src = G.dwp[l] + (int64_t)e * P.splits * ps * 4;
+        j.stride = frag_partial_floats(P, e, bn);
+        j.dst = x->net[G.nets[e]].lay[l].w;
+        j.nparts = P.splits;
+        j.n = (int32_t)j.stride;
+        j.M = P.d[e].M; j.N = P.d[e].N; j.tiles_n = P.tiles_n[e]; j.bn = bn;
+        G.few.push_back(j);
+      }
     }
     const bool top = l == L;
     for (int e = 0; e < G.count; ++e) {
@@ -318,8 +333,12 @@ void plan_group(crl_ctx* x, Group& G, int64_t& off) {
       Slots& S = x->sl[G.nets[e]];
       const LayerOff& lo = N.lay[l];
       if (top || !x->ln) {
-        S.bp[l] = take_bytes(x, off, (int64_t)nrb * lo.fan_out * 4);
-        add(G.many, S.bp[l], lo.fan_out, lo.b, nrb, lo.fan_out);
+        // the critic's output-layer partials come from the fused InfoNCE
+        // backward reduction (blocks of 256 / D rows), the others from the
+        // column sums
+        const int np = (top && gi == 0 && x->fused) ? fused_bias_chunks(x->B, lo.fan_out) : nrb;
+        S.bp[l] = take_bytes(x, off, (int64_t)np * lo.fan_out * 4);
+        add(G.many, S.bp[l], lo.fan_out, lo.b, np, lo.fan_out);
       }
       if (!top && x->ln) {
         const int H = N.H;
@@ -330,12 +349,15 @@ void plan_group(crl_ctx* x, Group& G, int64_t& off) {
       }
     }
   }
+  // the padding between the vector's tensors: written as zeros
+  const std::vector<int64_t>& gaps = x->gaps[gi];
+  for (size_t k = 0; k + 1 < gaps.size(); k += 2) add(G.many, 0, 0, gaps[k], 0, (int)gaps[k + 1]);
   G.total4 = 0;
   G.few_bytes = 0;
   for (RedJob& j : G.few) {
     j.first = G.total4;
     G.total4 += j.n / 4;
-    G.few_bytes += 4.0 * j.n * (j.nparts + 1.0);
+    G.few_bytes += 4.0 * j.M * j.N * (j.nparts + 1.0);
   }
   G.nblocks = 0;
   G.many_bytes = 0;
@@ -356,7 +378,7 @@ void plan_workspace(crl_ctx* x) {
   for (int e = 0; e < (x->actor ? 3 : 2); ++e) plan_slots(x, e, take_bytes, off);
   x->grp[0].nets[0] = 0; x->grp[0].nets[1] = 1; x->grp[0].count = 2;
   x->grp[1].nets[0] = 2; x->grp[1].nets[1] = 2; x->grp[1].count = 1;
-  for (int gi = 0; gi < (x->actor ? 2 : 1); ++gi) plan_group(x, x->grp[gi], off);
+  for (int gi = 0; gi < (x->actor ? 2 : 1); ++gi) plan_group(x, gi, off);
   x->splitk_floats = splitk_need(x);
   x->splitk = take(x->splitk_floats * 4);
   x->r = take(B * 4);
@@ -384,8 +406,8 @@ void plan_workspace(crl_ctx* x) {
     x->row_s = take((int64_t)S * B * 4);
     x->col_m = take((int64_t)nrb * B * 4);
     x->col_s = take((int64_t)nrb * B * 4);
-    x->dx_part = take((int64_t)S * B * D * 4);
-    x->rs_part = take((int64_t)S * B * 4);
+    x->dx_part = take((int64_t)2 * S * B * D * 4);
+    x->rs_part = take((int64_t)2 * S * B * 4);
   }
   x->xsa2 = x->noise = x->logpi = x->fpol = x->dact = -1;
   x->ldd = 0;
@@ -433,7 +455,10 @@ const void* weights(const crl_ctx* x, const NetCall& c, int64_t off) {
 // Forward of `count` MLPs with the same depth and width, layer by layer in
 // grouped launches: GEMM (bias, and ReLU, in the epilogue), then LayerNorm +
 // Swish.  Outputs and the activations the backward needs stay in ws.
-int mlp_forward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t s) {
+// top_deferred: the output layer's split-K partials are left unreduced and
+// its launch parameters returned (splits == 1 there: nothing deferred).
+int mlp_forward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t s,
+                GemmParams* top_deferred = nullptr) {
   const Net& N0 = x->net[nc[0].net];
   const int B = x->B;
   for (int l = 0; l <= N0.L; ++l) {
@@ -466,6 +491,10 @@ int mlp_forward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t 
     if (P.splits > 1)
       P.partial_len = (int64_t)P.splits * std::max((int64_t)P.d[0].M * P.d[0].N,
                                                    (int64_t)P.d[count - 1].M * P.d[count - 1].N);
+    if (top && top_deferred) {
+      P.defer_reduce = P.splits > 1;
+      *top_deferred = P;
+    }
     CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_MC, x->bf16 && !top, s), "encoder GEMM");
     if (!top && x->ln) {
       LnArgs a{};
@@ -489,7 +518,8 @@ int mlp_forward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t 
 // slots, last layer first.  With a gradient vector: dW, bias and LayerNorm
 // parameter gradients of every layer.  A net with dx set (count must be 1)
 // also gets the gradient of the chosen input columns.
-int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t s) {
+int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t s,
+                 bool top_bias_ready = false) {
   const Net& N0 = x->net[nc[0].net];
   const int B = x->B, H = N0.H, L = N0.L;
   const bool grads = nc[0].g != nullptr;
@@ -508,7 +538,6 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
       {  // dW = in^T . dZ  (contraction over the batch); split-K partials are
          // reduced once, after the last layer
         GemmParams P = dw_params(x, G, l);
-        int64_t mn = 0;
         for (int e = 0; e < count; ++e) {
           const Net& N = x->net[nc[e].net];
           const Slots& S = x->sl[nc[e].net];
@@ -520,17 +549,22 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
           d.C = nc[e].g + lo.w; d.ldc = lo.fan_out;
           d.alpha = 1.f;
           d.epi = EPI_NONE;
-          mn = std::max(mn, (int64_t)d.M * d.N);
         }
         if (P.splits > 1) {
+          const int bn = gemm_lds_bn(P, x->bf16);
+          if (bn != G.dwbn[l]) return fail(CRL_EINVAL, "internal: dW partial layout mismatch");
+          int64_t ps = 0;
+          for (int e = 0; e < count; ++e) ps = std::max(ps, frag_partial_floats(P, e, bn));
           P.partial = WF(ws, G.dwp[l]);
-          P.partial_len = (int64_t)P.splits * mn;
+          P.partial_len = (int64_t)P.splits * ps;
           P.defer_reduce = 1;
+          P.frag = 1;
         }
         CRL_HIP(launch_gemm(P, x->bf16, LAY_MC, LAY_MC, false, s), "dW GEMM");
       }
-      // bias column partials of this layer (LayerNorm layers get theirs with dZ)
-      if (top || !x->ln) {
+      // bias column partials of this layer (LayerNorm layers get theirs with dZ;
+      // top_bias_ready: the output layer's were written with dout)
+      if ((top && !top_bias_ready) || (!top && !x->ln)) {
         ColSumArgs ca{};
         for (int e = 0; e < count; ++e) {
           const Slots& S = x->sl[nc[e].net];
@@ -603,10 +637,9 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
   }
   if (grads) {
     const char* wsc = static_cast<const char*>(ws);
-    CRL_HIP(launch_grad_reduce_few(wsc, nc[0].g, G.d_few, (int)G.few.size(), G.total4,
-                                   G.few_bytes, s), "dW split-K reduction");
-    CRL_HIP(launch_grad_reduce_many(wsc, nc[0].g, G.d_many, (int)G.many.size(), G.nblocks,
-                                    G.many_bytes, s), "bias and LayerNorm gradient reduction");
+    CRL_HIP(launch_grad_reduce(wsc, nc[0].g, G.d_few, (int)G.few.size(), G.total4, G.d_many,
+                               (int)G.many.size(), G.nblocks, G.few_bytes + G.many_bytes, s),
+            "gradient reductions");
   }
   return CRL_OK;
 }
@@ -627,7 +660,6 @@ int upload(void** dst, const void* src, size_t bytes) {
 void free_tables(crl_ctx* x) {
   if (x->d_thr) (void)hipFree(x->d_thr);
   for (int i = 0; i < 2; ++i) {
-    if (x->d_gaps[i]) (void)hipFree(x->d_gaps[i]);
     if (x->grp[i].d_few) (void)hipFree(x->grp[i].d_few);
     if (x->grp[i].d_many) (void)hipFree(x->grp[i].d_many);
   }
@@ -675,7 +707,6 @@ CRL_API int crl_create(const crl_config* cfg, crl_ctx** out) {
   x->ld_sg = x->net[2].ld_in;
   x->nparam = plan_params(x, 0, 1, x->gaps[0]);
   x->nparam_actor = x->actor ? plan_params(x, 2, 2, x->gaps[1]) : 0;
-  for (int i = 0; i < 2; ++i) x->n_gaps[i] = (int)(x->gaps[i].size() / 2);
   plan_workspace(x);
   // geometric-offset thresholds thr[1..T-2] (stored from index 0)
   const int nthr = std::max(1, cfg->max_episode_len - 2);
@@ -687,11 +718,7 @@ CRL_API int crl_create(const crl_config* cfg, crl_ctx** out) {
     t = (uint64_t)(((unsigned __int128)t * G) >> 64);
   }
   x->d_thr = nullptr;
-  x->d_gaps[0] = x->d_gaps[1] = nullptr;
   rc = upload(reinterpret_cast<void**>(&x->d_thr), thr.data(), nthr * sizeof(uint64_t));
-  for (int i = 0; i < 2 && rc == CRL_OK; ++i)
-    rc = upload(reinterpret_cast<void**>(&x->d_gaps[i]), x->gaps[i].data(),
-                x->gaps[i].size() * sizeof(int64_t));
   for (int i = 0; i < 2 && rc == CRL_OK; ++i) {
     Group& G = x->grp[i];
     rc = upload(reinterpret_cast<void**>(&G.d_few), G.few.data(), G.few.size() * sizeof(RedJob));
@@ -817,7 +844,10 @@ CRL_API int crl_critic_fwd(crl_ctx* x, const float* params, const uint16_t* para
 
   NetCall nc[2] = {{0, x_sa, x->net[0].ld_in, params, pb, nullptr, nullptr, 0, 0, 0},
                    {1, x_g, x->net[1].ld_in, params, pb, nullptr, nullptr, 0, 0, 0}};
-  CRL_TRY(mlp_forward(x, nc, 2, ws, s));
+  // fused logits: the output layer's split-K sum is taken by the kernel that
+  // makes the BF16 copies and norms
+  GemmParams top{};
+  CRL_TRY(mlp_forward(x, nc, 2, ws, s, x->fused ? &top : nullptr));
 
   float* phi = WF(ws, x->sl[0].out);
   float* psi = WF(ws, x->sl[1].out);
@@ -857,7 +887,8 @@ CRL_API int crl_critic_fwd(crl_ctx* x, const float* params, const uint16_t* para
     a.row_m = WF(ws, x->row_m); a.row_s = WF(ws, x->row_s);
     a.col_m = WF(ws, x->col_m); a.col_s = WF(ws, x->col_s);
     a.r = r; a.c = c; a.diag = dg;
-    CRL_HIP(launch_fused_fwd(a, B, D, x->l2, s), "fused InfoNCE forward");
+    CRL_HIP(launch_fused_fwd(a, B, D, x->l2, top.splits > 1 ? &top : nullptr, s),
+            "fused InfoNCE forward");
   }
   CRL_HIP(launch_loss(r, c, dg, B, x->sym, x->cfg.logsumexp_penalty, loss_out, s), "loss");
   return CRL_OK;
@@ -885,7 +916,6 @@ CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* para
   float* dpsi = WF(ws, x->sl[1].dout);
   float* splitk = WF(ws, x->splitk);
 
-  CRL_HIP(launch_zero_ranges(grads, x->d_gaps[0], x->n_gaps[0], s), "zero padding");
 
   // dL/dphi, dL/dpsi
   if (!x->fused) {
@@ -931,12 +961,14 @@ CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* para
     a.dphi = dphi; a.dpsi = dpsi;
     a.dphi_t = W(ws, x->sl[0].dout_t);
     a.dpsi_t = W(ws, x->sl[1].dout_t);
+    a.bias_part[0] = WF(ws, x->sl[0].bp[x->L]);
+    a.bias_part[1] = WF(ws, x->sl[1].bp[x->L]);
     CRL_HIP(launch_fused_bwd(a, B, D, x->l2, x->sym, beta, x->bf16, s), "fused InfoNCE backward");
   }
 
   NetCall nc[2] = {{0, x_sa, x->net[0].ld_in, params, pb, grads, nullptr, 0, 0, 0},
                    {1, x_g, x->net[1].ld_in, params, pb, grads, nullptr, 0, 0, 0}};
-  return mlp_backward(x, nc, 2, ws, s);
+  return mlp_backward(x, nc, 2, ws, s, x->fused);
 }
 
 CRL_API int crl_actor_step(crl_ctx* x, const float* params, const uint16_t* params_bf16,
@@ -969,7 +1001,6 @@ CRL_API int crl_actor_step(crl_ctx* x, const float* params, const uint16_t* para
   float* dact = WF(ws, x->dact);
   const float* pout = WF(ws, x->sl[2].out);
 
-  CRL_HIP(launch_zero_ranges(actor_grads, x->d_gaps[1], x->n_gaps[1], s), "zero padding");
   // policy MLP on [s, g], then the sampled action and log pi
   NetCall pol = {2, x_sg, x->ld_sg, actor_params, apb, actor_grads, nullptr, 0, 0, 0};
   CRL_TRY(mlp_forward(x, &pol, 1, ws, s));

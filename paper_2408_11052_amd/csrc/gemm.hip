@@ -73,6 +73,14 @@ static int lds_path_bn(const GemmParams& P) {
   return nmax > 64 ? 128 : 64;
 }
 
+int gemm_lds_bn(const GemmParams& P, bool bf16) { return bf16 ? lds_path_bn(P) : 0; }
+
+int64_t frag_partial_floats(const GemmParams& P, int g, int bn) {
+  const GemmDesc& d = P.d[g];
+  if (bn == 0) return (int64_t)d.M * d.N;
+  return (int64_t)((d.M + lds::BM - 1) / lds::BM) * ((d.N + bn - 1) / bn) * lds::BM * bn;
+}
+
 template <typename T, int LA, int LB, typename OutT>
 static hipError_t run(GemmParams& P, hipStream_t s) {
   int maxt = 0;

@@ -62,6 +62,8 @@ struct GemmParams {
   float* partial;      // splits > 1: partial[g][s][M][N] (FP32, no epilogue)
   int64_t partial_len; // floats per problem in `partial`
   int defer_reduce;    // splits > 1: leave the partials for a later reduction
+  int frag;            // with defer_reduce: the direct-to-LDS kernel stores the
+                       // partials in fragment order (see frag_partial_floats)
 };
 
 // Work item (tile, split, problem) of a workgroup.  Workgroups are dealt to

@@ -181,12 +181,25 @@ void gemm_lds_kernel(GemmParams P) {
     const char* st = smem + (kt & 1) * STAGE;
     compute_tile<LA, LB, BN>(acc, st, st + TA, wm, wn, lane);
   }
+  const bool split = P.splits > 1;
+  if (split && P.defer_reduce && P.frag) {
+    // deferred split-K partial in fragment order: wave w's accumulators
+    // acc[i][j] go to floats ((tile * NW + w) * 8 + i * 2 + j) * 256 + 4 lane
+    // of this split's block, one 1 KB store per wave and fragment
+    float* out = P.partial + (int64_t)gi * P.partial_len +
+                 (int64_t)wi.split * ntile * BM * BN + ((int64_t)pid * NW + wave) * (4 * NJ * 256);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        *reinterpret_cast<floatx4*>(out + (i * NJ + j) * 256 + lane * 4) = acc[i][j];
+    return;
+  }
   __syncthreads();
 
   // epilogue: stage the FP32 tile in LDS, then 16-byte row stores
   const int r16 = lane & 15, gq = lane >> 4;
   float* Cs = reinterpret_cast<float*>(smem);
-  const bool split = P.splits > 1;
   const bool has_bias = !split && (D.epi == EPI_BIAS || D.epi == EPI_BIAS_RELU);
   float bcol[NJ];
 #pragma unroll

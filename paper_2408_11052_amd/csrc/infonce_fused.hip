@@ -60,6 +60,35 @@ __global__ void fused_prep_kernel(FusedArgs a, int B, int D) {
   if (lane == 0) nrm[row] = s;
 }
 
+// The same from the output layer's split-K partials: phi / psi = sum of the
+// splits in order + bias (FP32, as the split-K reduction writes them), then
+// the BF16 copies and norms.
+__global__ void fused_prep_reduce_kernel(FusedArgs a, GemmParams P, int B, int D) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int which = blockIdx.y;
+  if (row >= B) return;
+  const GemmDesc& G = P.d[which];
+  const int64_t MN = (int64_t)G.M * G.N;
+  const float* __restrict__ src = P.partial + (int64_t)which * P.partial_len + (int64_t)row * D;
+  float* X = reinterpret_cast<float*>(G.C) + (int64_t)row * G.ldc;
+  bf16_t* Xb = (which ? a.psi_b : a.phi_b) + (int64_t)row * D;
+  float* nrm = which ? a.npsi : a.nphi;
+  float s = 0.f;
+  for (int d = lane; d < D; d += 64) {
+    float v = 0.f;
+    for (int k = 0; k < P.splits; ++k) v += src[k * MN + d];
+    v += G.bias[d];
+    X[d] = v;
+    const bf16_t h = f2bf(v);
+    Xb[d] = h;
+    const float f = bf2f(h);
+    s += f * f;
+  }
+  s = wave_sum(s);
+  if (lane == 0) nrm[row] = s;
+}
+
 // A 64-row tile of Y [B][D] (BF16) moves global -> registers -> LDS.  Each
 // of the 256 threads holds D/32 16-byte vectors; rows past B are zero.  The
 // next tile is fetched into registers while the current one is computed on.
@@ -382,8 +411,8 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
       }
     }
   }
-  // write this split's partials
-  float* dst = a.dX_part + (int64_t)blockIdx.y * B * D;
+  // write this split's partials (the two passes use separate halves)
+  float* dst = a.dX_part + ((int64_t)TRANS * gridDim.y + blockIdx.y) * B * D;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -398,30 +427,53 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
 #pragma unroll
       for (int o = 1; o <= 8; o <<= 1) s += __shfl_xor(s, o, 64);
       const int row = row_base + 4 * g + r;
-      if (r16 == 0 && row < B) a.rs_part[(int64_t)blockIdx.y * B + row] = s;
+      if (r16 == 0 && row < B) a.rs_part[((int64_t)TRANS * gridDim.y + blockIdx.y) * B + row] = s;
     }
   }
 }
 
-// dX = sum_s part[s] (- (sum_s rs[s]) * X_bf16 for L2), FP32 and storage copy.
-template <typename OutT>
-__global__ void bwd_reduce_kernel(const float* __restrict__ part, const float* __restrict__ rs,
-                                  const bf16_t* __restrict__ Xb, int S, int B, int D, int l2,
-                                  float* __restrict__ out, OutT* __restrict__ out_t) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// dphi and dpsi (blockIdx.y) from the S split partials:
+//   dX = sum_s part[s]  (- (sum_s rs[s]) * X_bf16 for L2),
+// FP32 and storage copies, one element per thread; with bias_part set, also
+// the column sums of each block's 256 / D rows (the output layer's
+// bias-gradient partials).
+template <typename OutT, int D>
+__global__ __launch_bounds__(256) void bwd_reduce_kernel(FusedArgs a, int S, int B, int l2) {
+  constexpr int TR = 256 / D;  // rows per block
+  __shared__ float red[256];
+  const int side = blockIdx.y;
+  const int c = threadIdx.x % D;
+  const int row = blockIdx.x * TR + threadIdx.x / D;
   const int64_t n = (int64_t)B * D;
-  if (k >= n) return;
+  const int64_t idx = (int64_t)row * D + c;
   float s = 0.f;
-  for (int i = 0; i < S; ++i) s += part[i * n + k];
-  if (l2) {
-    const int64_t row = k / D;
-    float h = 0.f;
-    for (int i = 0; i < S; ++i) h += rs[(int64_t)i * B + row];
-    s -= h * bf2f(Xb[k]);
+  if (row < B) {
+    const float* __restrict__ part = a.dX_part + (int64_t)side * S * n + idx;
+#pragma unroll 4
+    for (int i = 0; i < S; ++i) s += part[i * n];
+    if (l2) {
+      const float* __restrict__ rs = a.rs_part + (int64_t)side * S * B + row;
+      const bf16_t* __restrict__ Xb = side ? a.psi_b : a.phi_b;
+      float h = 0.f;
+      for (int i = 0; i < S; ++i) h += rs[(int64_t)i * B];
+      s -= h * bf2f(Xb[idx]);
+    }
+    (side ? a.dpsi : a.dphi)[idx] = s;
+    reinterpret_cast<OutT*>(side ? a.dpsi_t : a.dphi_t)[idx] = Store<OutT>::from_f(s);
   }
-  out[k] = s;
-  out_t[k] = Store<OutT>::from_f(s);
+  float* bias = a.bias_part[side];
+  if (bias == nullptr) return;
+  red[threadIdx.x] = s;  // rows past B add 0
+  __syncthreads();
+  if (threadIdx.x < D) {
+    float t = red[threadIdx.x];
+#pragma unroll
+    for (int q = 1; q < TR; ++q) t += red[q * D + threadIdx.x];
+    bias[(int64_t)blockIdx.x * D + threadIdx.x] = t;
+  }
 }
+
+int fused_bias_chunks(int B, int D) { return (int)(((int64_t)B * D + 255) / 256); }
 
 #define CRL_FUSED_DISPATCH(KS_, BODY)                      \
   switch (D) {                                              \
@@ -432,9 +484,14 @@ __global__ void bwd_reduce_kernel(const float* __restrict__ part, const float* _
     default: return hipErrorInvalidValue;                   \
   }
 
-hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, hipStream_t s) {
-  CRL_TIMED("fused_prep_kernel", 0.0, 2.0 * B * D * 6.0, s,
-            fused_prep_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, B, D));
+hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, const GemmParams* top,
+                            hipStream_t s) {
+  if (top)
+    CRL_TIMED("fused_prep_reduce_kernel", 0.0, 2.0 * B * D * (4.0 * top->splits + 10.0), s,
+              fused_prep_reduce_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, *top, B, D));
+  else
+    CRL_TIMED("fused_prep_kernel", 0.0, 2.0 * B * D * 6.0, s,
+              fused_prep_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, B, D));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int S = fused_splits(B), cps = cols_per_split(B, S);
@@ -448,9 +505,10 @@ hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, hipStream_
   timing_end(t);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_lse_merge(a.row_m, a.row_s, S, B, a.r, s);
-  if (e != hipSuccess) return e;
-  return launch_lse_merge(a.col_m, a.col_s, nrb, B, a.c, s);
+  LseMergeArgs m{};  // row LSEs over the column splits, column LSEs over the row blocks
+  m.pm[0] = a.row_m; m.ps[0] = a.row_s; m.nparts[0] = S; m.out[0] = a.r;
+  m.pm[1] = a.col_m; m.ps[1] = a.col_s; m.nparts[1] = nrb; m.out[1] = a.c;
+  return launch_lse_merge(m, 2, B, s);
 }
 
 hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmetric,
@@ -474,19 +532,15 @@ hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmet
     timing_end(t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const bf16_t* Xb = pass ? a.psi_b : a.phi_b;
-    float* out = pass ? a.dpsi : a.dphi;
-    void* out_t = pass ? a.dpsi_t : a.dphi_t;
-    const int blocks = (int)((n + 255) / 256);
-    const double rb = 4.0 * (double)n * (S + 1.0) + (double)n * (out_bf16 ? 2 : 4);
-    if (out_bf16)
-      CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
-                bwd_reduce_kernel<bf16_t><<<blocks, 256, 0, s>>>(a.dX_part, a.rs_part, Xb, S, B, D, l2, out, (bf16_t*)out_t));
-    else
-      CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
-                bwd_reduce_kernel<float><<<blocks, 256, 0, s>>>(a.dX_part, a.rs_part, Xb, S, B, D, l2, out, (float*)out_t));
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  }
+  const dim3 rgrid(fused_bias_chunks(B, D), 2);
+  const double rb = 2.0 * (4.0 * (double)n * (S + 1.0) + (double)n * (out_bf16 ? 2 : 4));
+  if (out_bf16) {
+    CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
+              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<bf16_t, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, l2))));
+  } else {
+    CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
+              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<float, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, l2))));
   }
   return hipSuccess;
 }

@@ -28,6 +28,13 @@ hipError_t launch_gemm(GemmParams& P, bool bf16, int la, int lb, bool out_bf16,
                        hipStream_t s);
 // Split factor and chunk for a batch of problems (fills P.splits, P.k_chunk).
 void plan_split_k(GemmParams& P, bool bf16, int target_wgs);
+// Column-tile width of the direct-to-LDS kernel for this launch (128 or 64),
+// or 0 when the register-staged kernel takes it.  Depends on shapes, leading
+// dimensions and pointer alignment only.
+int gemm_lds_bn(const GemmParams& P, bool bf16);
+// Floats of one split's deferred partial of problem g: the whole 128 x bn
+// tiles in fragment order (bn > 0), or the dense M x N block (bn == 0).
+int64_t frag_partial_floats(const GemmParams& P, int g, int bn);
 
 // kernels.hip
 hipError_t launch_relabel(const float* obs, const float* act, int E, int T,
@@ -80,17 +87,24 @@ int colsum_chunks(int B);
 // (with four interleaved running sums, combined in a fixed order).  `first`
 // is the job's first float4 (few-part jobs) or first 16-output block
 // (many-part jobs) in the launch's index space.
+// Sum of nparts partial blocks (src + k * stride floats, k = 0..nparts-1, in
+// that order) into g + dst.  bn == 0: n contiguous floats.  bn > 0: split-K
+// partials of an M x N GEMM in the direct-to-LDS kernel's fragment order
+// (128 x bn tiles, tiles_n per row of tiles), scattered into the row-major
+// M x N block at dst.
 struct RedJob {
   int64_t src;
   int64_t stride;
   int64_t dst;
   int64_t first;
   int32_t nparts, n;
+  int32_t M, N, tiles_n, bn;
 };
-hipError_t launch_grad_reduce_few(const char* ws, float* g, const RedJob* jobs, int njobs,
-                                  int64_t total4, double bytes, hipStream_t s);
-hipError_t launch_grad_reduce_many(const char* ws, float* g, const RedJob* jobs, int njobs,
-                                   int64_t nblocks, double bytes, hipStream_t s);
+// few-part jobs (total4 float4 outputs) and many-part jobs (nblocks blocks of
+// 16 outputs) in one launch
+hipError_t launch_grad_reduce(const char* ws, float* g, const RedJob* few, int nfew,
+                              int64_t total4, const RedJob* many, int nmany, int64_t nblocks,
+                              double bytes, hipStream_t s);
 
 hipError_t launch_sqnorm(const float* X, float* out, int B, int D, hipStream_t s);
 hipError_t launch_cast_bf16(const float* src, bf16_t* dst, int64_t n, hipStream_t s);
@@ -101,13 +115,20 @@ struct AdamCoef {
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, bf16_t* pb,
                        int64_t n, const int64_t* step, const AdamCoef& c, hipStream_t s);
 hipError_t launch_counter_add(int64_t* c, int64_t inc, hipStream_t s);
-hipError_t launch_zero_ranges(float* base, const int64_t* ranges, int nranges,
-                              hipStream_t s);
 
 // materialised InfoNCE (FP32 B x B in the workspace, row stride ld)
 hipError_t launch_row_lse(const float* F, int B, int ld, float* r, float* diag, hipStream_t s);
 hipError_t launch_col_lse_partial(const float* F, int B, int ld, int rchunks, float* pm,
                                   float* ps, hipStream_t s);
+// log-sum-exp of (max, sum) partials [nparts][B] per column j, for `count`
+// problems in one launch
+struct LseMergeArgs {
+  const float* pm[2];
+  const float* ps[2];
+  int nparts[2];
+  float* out[2];
+};
+hipError_t launch_lse_merge(const LseMergeArgs& a, int count, int B, hipStream_t s);
 hipError_t launch_lse_merge(const float* pm, const float* ps, int nparts, int B,
                             float* out, hipStream_t s);
 hipError_t launch_loss(const float* r, const float* c, const float* diag, int B,
@@ -133,15 +154,21 @@ struct FusedArgs {
   float* r;
   float* c;
   float* diag;
-  float* dX_part;     // [S][B][D] backward partials
-  float* rs_part;     // [S][B]   sum_b H_ab (L2)
+  float* dX_part;     // [2][S][B][D] backward partials (rows pass, columns pass)
+  float* rs_part;     // [2][S][B]   sum_b H_ab (L2)
   float* dphi;        // [B][D] FP32 out
   float* dpsi;
   void* dphi_t;       // storage-type copies for the encoder GEMMs
   void* dpsi_t;
+  float* bias_part[2]; // [chunks][D] column sums of dphi / dpsi per 256/D rows, or nullptr
 };
 int fused_splits(int B);
-hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, hipStream_t s);
+int fused_bias_chunks(int B, int D);  // row blocks of the backward reduction
+// top: the output layer's deferred split-K launch (phi = d[0].C, psi =
+// d[1].C), summed with its bias by the prep kernel; nullptr: phi and psi are
+// final already.
+hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, const GemmParams* top,
+                            hipStream_t s);
 hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmetric,
                             float beta, bool out_bf16, hipStream_t s);
 

@@ -447,14 +447,28 @@ __device__ inline int find_job(const RedJob* __restrict__ jobs, int njobs, int64
 }
 
 // few parts (split-K partials): one float4 of one job per thread
-__global__ __launch_bounds__(256) void grad_reduce_few_kernel(const char* __restrict__ ws,
-                                                              float* __restrict__ g,
-                                                              const RedJob* __restrict__ jobs,
-                                                              int njobs, int64_t total4) {
-  const int64_t v = blockIdx.x * 256ll + threadIdx.x;
+__device__ __forceinline__ void reduce_few(const char* __restrict__ ws, float* __restrict__ g,
+                                           const RedJob* __restrict__ jobs, int njobs,
+                                           int64_t total4, int64_t blk) {
+  const int64_t v = blk * 256ll + threadIdx.x;
   if (v >= total4) return;
   const RedJob J = jobs[find_job(jobs, njobs, v)];
   const int64_t i4 = v - J.first;
+  int64_t o0 = -1;  // fragment order: row-major offset of this float4's first row
+  if (J.bn > 0) {
+    // float4 i4 = lane's 4 accumulator rows of fragment (i, j) of wave w of
+    // tile t (the direct-to-LDS kernel's 64 x 32 wave blocks)
+    const int64_t e = i4 * 4;
+    const int64_t tsz = (int64_t)128 * J.bn;
+    const int t = (int)(e / tsz);
+    const int rem = (int)(e - (int64_t)t * tsz);
+    const int w = rem >> 11, f = (rem >> 8) & 7, lane = (rem >> 2) & 63;
+    const int wpr = J.bn / 32;  // waves per row of wave blocks
+    const int row = (t / J.tiles_n) * 128 + (w / wpr) * 64 + (f >> 1) * 16 + (lane >> 4) * 4;
+    const int col = (t % J.tiles_n) * J.bn + (w % wpr) * 32 + (f & 1) * 16 + (lane & 15);
+    if (row >= J.M || col >= J.N) return;
+    o0 = (int64_t)row * J.N + col;
+  }
   const float4* p = reinterpret_cast<const float4*>(ws + J.src) + i4;
   const int64_t st = J.stride / 4;
   float4 s[4];
@@ -477,19 +491,28 @@ __global__ __launch_bounds__(256) void grad_reduce_few_kernel(const char* __rest
   r.y = (s[0].y + s[1].y) + (s[2].y + s[3].y);
   r.z = (s[0].z + s[1].z) + (s[2].z + s[3].z);
   r.w = (s[0].w + s[1].w) + (s[2].w + s[3].w);
-  reinterpret_cast<float4*>(g + J.dst)[i4] = r;
+  if (o0 < 0) {
+    reinterpret_cast<float4*>(g + J.dst)[i4] = r;
+  } else {  // rows past M inside the last tile are not stored
+    float* q = g + J.dst + o0;
+    const int nrow = min(4, J.M - (int)(o0 / J.N));
+    q[0] = r.x;
+    if (nrow > 1) q[J.N] = r.y;
+    if (nrow > 2) q[2 * (int64_t)J.N] = r.z;
+    if (nrow > 3) q[3 * (int64_t)J.N] = r.w;
+  }
 }
 
 // many parts (per-chunk column partials): 16 outputs per workgroup, the parts
-// over 16 groups, then a fixed-order tree in LDS
-__global__ __launch_bounds__(256) void grad_reduce_many_kernel(const char* __restrict__ ws,
-                                                               float* __restrict__ g,
-                                                               const RedJob* __restrict__ jobs,
-                                                               int njobs) {
+// over 16 groups, then a fixed-order tree in LDS.  A job with no parts writes
+// zeros (the padding between parameter tensors).
+__device__ __forceinline__ void reduce_many(const char* __restrict__ ws, float* __restrict__ g,
+                                            const RedJob* __restrict__ jobs, int njobs,
+                                            int64_t blk) {
   __shared__ float red[16][17];
-  const RedJob J = jobs[find_job(jobs, njobs, blockIdx.x)];
+  const RedJob J = jobs[find_job(jobs, njobs, blk)];
   const int col = threadIdx.x & 15, grp = threadIdx.x >> 4;
-  const int64_t i = (blockIdx.x - J.first) * 16 + col;
+  const int64_t i = (blk - J.first) * 16 + col;
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
   if (i < J.n) {
     const float* p = reinterpret_cast<const float*>(ws + J.src) + i;
@@ -511,20 +534,27 @@ __global__ __launch_bounds__(256) void grad_reduce_many_kernel(const char* __res
   if (grp == 0 && i < J.n) g[J.dst + i] = red[0][col];
 }
 
-hipError_t launch_grad_reduce_few(const char* ws, float* g, const RedJob* jobs, int njobs,
-                                  int64_t total4, double bytes, hipStream_t s) {
-  if (njobs == 0 || total4 == 0) return hipSuccess;
-  CRL_TIMED("grad_reduce_few_kernel", 0.0, bytes, s,
-            grad_reduce_few_kernel<<<(unsigned)((total4 + 255) / 256), 256, 0, s>>>(
-                ws, g, jobs, njobs, total4));
-  return hipGetLastError();
+// Both reductions in one launch: blocks [0, nbf) take the few-part jobs,
+// the rest the many-part jobs.
+__global__ __launch_bounds__(256) void grad_reduce_kernel(const char* __restrict__ ws,
+                                                          float* __restrict__ g,
+                                                          const RedJob* __restrict__ few,
+                                                          int nfew, int64_t total4,
+                                                          const RedJob* __restrict__ many,
+                                                          int nmany, int64_t nbf) {
+  if (blockIdx.x < nbf) reduce_few(ws, g, few, nfew, total4, blockIdx.x);
+  else reduce_many(ws, g, many, nmany, blockIdx.x - nbf);
 }
 
-hipError_t launch_grad_reduce_many(const char* ws, float* g, const RedJob* jobs, int njobs,
-                                   int64_t nblocks, double bytes, hipStream_t s) {
-  if (njobs == 0 || nblocks == 0) return hipSuccess;
-  CRL_TIMED("grad_reduce_many_kernel", 0.0, bytes, s,
-            grad_reduce_many_kernel<<<(unsigned)nblocks, 256, 0, s>>>(ws, g, jobs, njobs));
+hipError_t launch_grad_reduce(const char* ws, float* g, const RedJob* few, int nfew,
+                              int64_t total4, const RedJob* many, int nmany, int64_t nblocks,
+                              double bytes, hipStream_t s) {
+  const int64_t nbf = nfew > 0 ? (total4 + 255) / 256 : 0;
+  const int64_t nbm = nmany > 0 ? nblocks : 0;
+  if (nbf + nbm == 0) return hipSuccess;
+  CRL_TIMED("grad_reduce_kernel", 0.0, bytes, s,
+            grad_reduce_kernel<<<(unsigned)(nbf + nbm), 256, 0, s>>>(ws, g, few, nfew, total4,
+                                                                      many, nmany, nbf));
   return hipGetLastError();
 }
 
@@ -627,15 +657,6 @@ hipError_t launch_counter_add(int64_t* c, int64_t inc, hipStream_t s) {
 }
 
 // ranges: [nranges][2] = (offset, length) in floats
-__global__ void zero_ranges_kernel(float* base, const int64_t* ranges) {
-  const int64_t off = ranges[2 * blockIdx.x], len = ranges[2 * blockIdx.x + 1];
-  for (int64_t i = threadIdx.x; i < len; i += blockDim.x) base[off + i] = 0.f;
-}
-hipError_t launch_zero_ranges(float* base, const int64_t* ranges, int nranges, hipStream_t s) {
-  if (nranges <= 0) return hipSuccess;
-  zero_ranges_kernel<<<nranges, 64, 0, s>>>(base, ranges);
-  return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // materialised InfoNCE: F [B][B] FP32 in memory
@@ -685,12 +706,15 @@ hipError_t launch_col_lse_partial(const float* F, int B, int ld, int rchunks, fl
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void lse_merge_kernel(const float* __restrict__ pm,
-                                                        const float* __restrict__ ps, int nparts,
-                                                        int B, float* __restrict__ out) {
-  // 16 columns per workgroup, the parts split over 16 groups (p = grp,
-  // grp + 16, ...), then a fixed-order tree over the groups in LDS
+__global__ __launch_bounds__(256) void lse_merge_kernel(LseMergeArgs a, int B) {
+  // problem blockIdx.y; 16 columns per workgroup, the parts split over 16
+  // groups (p = grp, grp + 16, ...), then a fixed-order tree over the groups
+  // in LDS
   __shared__ float sm[16][17], ss[16][17];
+  const int e = blockIdx.y;
+  const float* __restrict__ pm = a.pm[e];
+  const float* __restrict__ ps = a.ps[e];
+  const int nparts = a.nparts[e];
   const int col = threadIdx.x & 15, grp = threadIdx.x >> 4;
   const int j = blockIdx.x * 16 + col;
   float m = -INFINITY, s = 0.f;
@@ -709,13 +733,20 @@ __global__ __launch_bounds__(256) void lse_merge_kernel(const float* __restrict_
     }
     __syncthreads();
   }
-  if (grp == 0 && j < B) out[j] = sm[0][col] + __logf(ss[0][col]);
+  if (grp == 0 && j < B) a.out[e][j] = sm[0][col] + __logf(ss[0][col]);
+}
+hipError_t launch_lse_merge(const LseMergeArgs& a, int count, int B, hipStream_t s) {
+  double parts = 0.0;
+  for (int e = 0; e < count; ++e) parts += a.nparts[e];
+  CRL_TIMED("lse_merge_kernel", 0.0, 4.0 * B * (2.0 * parts + count), s,
+            lse_merge_kernel<<<dim3((B + 15) / 16, count), 256, 0, s>>>(a, B));
+  return hipGetLastError();
 }
 hipError_t launch_lse_merge(const float* pm, const float* ps, int nparts, int B, float* out,
                             hipStream_t s) {
-  CRL_TIMED("lse_merge_kernel", 0.0, 4.0 * B * (2.0 * nparts + 1.0), s,
-            lse_merge_kernel<<<(B + 15) / 16, 256, 0, s>>>(pm, ps, nparts, B, out));
-  return hipGetLastError();
+  LseMergeArgs a{};
+  a.pm[0] = pm; a.ps[0] = ps; a.nparts[0] = nparts; a.out[0] = out;
+  return launch_lse_merge(a, 1, B, s);
 }
 
 // Loss from r, c, diag in one workgroup: per-thread Kahan sums, then an
