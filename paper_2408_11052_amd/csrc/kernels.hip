@@ -20,12 +20,25 @@ __global__ __launch_bounds__(256) void relabel_kernel(
   const int e = (int)__umul64hi(x[0], (uint64_t)E);
   const int t = (int)__umul64hi(x[1], (uint64_t)(T_ - 1));
   // k = 1 + #{m in [1, T-2] : w2 < thr[m]}; the table is non-increasing, so
-  // the count is the length of its prefix that exceeds w2.
+  // the count is the length p of its prefix that exceeds w2.  64-way search:
+  // the lanes probe 64 evenly spaced entries of [lo, hi) at once, and the
+  // number of probes above w2 narrows p to one gap between probes.
   const uint64_t w2 = x[2];
-  int lo = 0, hi = T_ - 2;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (thr[mid] > w2) lo = mid + 1; else hi = mid;
+  int lo = 0, hi = T_ - 2;  // p in [lo, hi]
+  while (hi - lo > 64) {
+    const int step = (hi - lo + 63) >> 6;
+    const int q = lo + lane * step;
+    const bool above = q < hi && thr[q] > w2;
+    const int c = __popcll(__ballot(above));  // probes 0..c-1 are above w2
+    const int nlo = c > 0 ? lo + (c - 1) * step + 1 : lo;
+    const int qc = lo + c * step;             // first probe not above (or past hi)
+    hi = min(hi, qc);
+    lo = nlo;
+  }
+  {
+    const int q = lo + lane;
+    const bool above = q < hi && thr[q] > w2;
+    lo += __popcll(__ballot(above));
   }
   const int tg = min(t + 1 + lo, T_ - 1);
   if (lane == 0) {
