@@ -50,12 +50,15 @@ __device__ inline float wave_max(float v) {
   return v;
 }
 
-// Merge of two online log-sum-exp states (m, s) meaning log(s) + m, s >= 0.
+// Merge of two online log-sum-exp states (m, s) meaning log(s) + m, s >= 0
+// (s == 0: empty).  Branch-free: the larger max keeps its sum exactly
+// (exp(0) = 1), the other is scaled down; an empty state contributes 0.
 __device__ inline void lse_merge(float& m, float& s, float m2, float s2) {
-  if (s2 == 0.f) return;
-  if (s == 0.f) { m = m2; s = s2; return; }
-  if (m2 > m) { s = s * __expf(m - m2) + s2; m = m2; }
-  else        { s = s + s2 * __expf(m2 - m); }
+  const float mn = s2 == 0.f ? m : (s == 0.f ? m2 : fmaxf(m, m2));
+  const float a = s == 0.f ? 0.f : s * __expf(m - mn);
+  const float b = s2 == 0.f ? 0.f : s2 * __expf(m2 - mn);
+  s = a + b;
+  m = mn;
 }
 
 // logistic function with the hardware reciprocal (about 1 ulp)

@@ -157,12 +157,19 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
   }
 
   // column (max, sum) partials of the previous tile, merged over the 16
-  // (wave, row group) entries in a fixed order
+  // (wave, row group) entries: their max first, then the rescaled sums in a
+  // fixed order (independent exponentials instead of a chain of merges)
   auto flush_cols = [&](int jp) {
     if (tid < kFCols && jp + tid < c1) {
-      float cm = cm_s[0][tid], cs = cs_s[0][tid];
+      float mv[16], sv[16];
 #pragma unroll
-      for (int w = 1; w < 16; ++w) lse_merge(cm, cs, cm_s[w][tid], cs_s[w][tid]);
+      for (int w = 0; w < 16; ++w) { mv[w] = cm_s[w][tid]; sv[w] = cs_s[w][tid]; }
+      float cm = mv[0];
+#pragma unroll
+      for (int w = 1; w < 16; ++w) cm = fmaxf(cm, mv[w]);
+      float cs = 0.f;
+#pragma unroll
+      for (int w = 0; w < 16; ++w) cs += sv[w] == 0.f ? 0.f : sv[w] * __expf(mv[w] - cm);
       a.col_m[(int64_t)rb * B + jp + tid] = cm;
       a.col_s[(int64_t)rb * B + jp + tid] = cs;
     }
@@ -247,15 +254,26 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
     __syncthreads();
     flush_cols(c0 + ((c1 - c0 - 1) / kFCols) * kFCols);
   }
-  // merge the row states across the 16 lanes that share each row
+  // merge the row states across the 16 lanes that share each row: the max
+  // by a butterfly, then the sums rescaled to it by a butterfly (every lane
+  // ends with the same value: each level adds the same two operands)
+  float mrow[4], srow[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) mrow[r] = rm[r];
+#pragma unroll
+  for (int o = 1; o <= 8; o <<= 1)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mrow[r] = fmaxf(mrow[r], __shfl_xor(mrow[r], o, 64));
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    srow[r] = rsum[r] == 0.f ? 0.f : rsum[r] * __expf(rm[r] - mrow[r]);
+#pragma unroll
+  for (int o = 1; o <= 8; o <<= 1)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) srow[r] += __shfl_xor(srow[r], o, 64);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    float m = rm[r], s = rsum[r];
-#pragma unroll
-    for (int o = 1; o <= 8; o <<= 1) {
-      float m2 = __shfl_xor(m, o, 64), s2 = __shfl_xor(s, o, 64);
-      lse_merge(m, s, m2, s2);
-    }
+    const float m = mrow[r], s = srow[r];
     const int row = row_base + 4 * g + r;
     if (r16 == 0 && row < B) {
       a.row_m[(int64_t)blockIdx.y * B + row] = m;
