@@ -398,7 +398,7 @@ void plan_workspace(crl_ctx* x) {
     x->colsumH = take(B * 4);
     x->cpartB = take(((B + 127) / 128) * x->ldF * 4);
   } else {
-    const int S = fused_splits(x->B);
+    const int S = std::max(fused_splits(x->B), fused_bwd_splits(x->B));
     const int nrb = (x->B + 63) / 64;
     x->phi_b = take(B * D * 2);
     x->psi_b = take(B * D * 2);

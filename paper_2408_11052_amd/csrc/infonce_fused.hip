@@ -450,6 +450,216 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
   }
 }
 
+// Both gradients in one pass (D = 64): a workgroup of 16 wavefronts owns 256
+// rows and 256 columns of the critic matrix, computes each 64-column tile of
+// G once, and uses it twice:
+//   dphi[rows] += G . psi[tile]        (wave w: its 16 rows, as in the row pass)
+//   dpsi[tile]  = G^T . phi[rows]      (wave w: 16 columns x 16 features, K = 256)
+// phi's 256 rows and the G tile stay in LDS; both MFMA operands of the second
+// product come from 16-bit transpose reads.  dphi partials go to split
+// blockIdx.y (the column block), dpsi partials to split blockIdx.x (the row
+// block); for L2 the row and column sums of H go with them.
+constexpr int kBRows = 256;  // rows (and columns) per workgroup of the one-pass backward
+int fused_bwd_splits(int B) { return (B + kBRows - 1) / kBRows; }
+
+template <int L2>
+__global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int B, float beta,
+                                                               int symmetric) {
+  constexpr int D = 64, KS = 2, NB = 4;
+  constexpr int LDX = D + 8;       // phi / psi rows in LDS (144 B)
+  constexpr int LDG = kFCols + 8;  // G rows in LDS
+  typedef short v4s __attribute__((ext_vector_type(4)));
+  typedef short v8s __attribute__((ext_vector_type(8)));
+  typedef __attribute__((address_space(3))) v4s lds_v4s;
+  __shared__ __attribute__((aligned(16))) bf16_t Xs[kBRows * LDX];
+  __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDX];
+  __shared__ __attribute__((aligned(16))) bf16_t Gs[kBRows * LDG];
+  __shared__ float csum[16][kFCols];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int r0 = blockIdx.x * kBRows, cb0 = blockIdx.y * kBRows;
+  const int row_base = r0 + wave * 16;
+  const float inv = 1.f / (float)B;
+
+  // phi rows of the block -> LDS (rows past B are zero)
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int v = tid + i * 1024;     // 16-byte vector: row v / 8, chunk v % 8
+    const int r = v >> 3, c = v & 7;
+    u32x4 val = {0u, 0u, 0u, 0u};
+    if (r0 + r < B) val = *reinterpret_cast<const u32x4*>(a.phi_b + (int64_t)(r0 + r) * D + c * 8);
+    *reinterpret_cast<u32x4*>(Xs + r * LDX + c * 8) = val;
+  }
+  bf16x8 xa[KS];
+  {
+    const int row = row_base + r16;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (row < B) xa[ks] = *reinterpret_cast<const bf16x8*>(a.phi_b + (int64_t)row * D + ks * 32 + g * 8);
+      else xa[ks] = bf16x8{};
+    }
+  }
+  float nx[4], lse_r[4], pen_r[4], hrow[4];
+  bool rvalid[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = row_base + 4 * g + r;
+    rvalid[r] = row < B;
+    nx[r] = (L2 && rvalid[r]) ? a.nphi[row] : 0.f;
+    lse_r[r] = rvalid[r] ? a.r[row] : 0.f;
+    pen_r[r] = rvalid[r] ? 2.f * beta * a.r[row] : 0.f;
+    hrow[r] = 0.f;
+  }
+  floatx4 acc_dx[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc_dx[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  // psi tile loader: threads 0..511 move one 16-byte vector each
+  auto y_load = [&](int j0) {
+    u32x4 val = {0u, 0u, 0u, 0u};
+    const int r = (tid & 511) >> 3, c = tid & 7;
+    if (tid < 512 && j0 + r < B) val = *reinterpret_cast<const u32x4*>(a.psi_b + (int64_t)(j0 + r) * D + c * 8);
+    return val;
+  };
+  const int ntiles = min(kBRows, B - cb0 + kFCols - 1) / kFCols;
+  u32x4 ypf = y_load(cb0);
+  for (int t = 0; t < ntiles; ++t) {
+    const int j0 = cb0 + t * kFCols;
+    __syncthreads();  // previous tile's Ys and Gs reads are done (and Xs is written)
+    if (tid < 512) *reinterpret_cast<u32x4*>(Ys + ((tid >> 3) * LDX) + (tid & 7) * 8) = ypf;
+    if (t + 1 < ntiles) ypf = y_load(j0 + kFCols);
+    float cl[4], cp[4], ny[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      const int col = j0 + jb * 16 + r16;
+      const bool cv = col < B;
+      cl[jb] = cv ? a.c[col] : 0.f;
+      cp[jb] = cv ? 1.f : 0.f;
+      ny[jb] = (L2 && cv) ? a.npsi[col] : 0.f;
+    }
+    __syncthreads();
+    floatx4 acc[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      acc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        bf16x8 b = *reinterpret_cast<const bf16x8*>(Ys + (jb * 16 + r16) * LDX + ks * 32 + g * 8);
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b, acc[jb], 0, 0, 0);
+      }
+    }
+    // G (or H = G / d) of the wave's 16 rows; column sums of H for L2
+    float hcol[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      const int col = j0 + jb * 16 + r16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_base + 4 * g + r;
+        float v = acc[jb][r];
+        float d = 0.f;
+        if (L2) { d = sqrtf(fmaxf(nx[r] + ny[jb] - 2.f * v, 0.f)); v = -d; }
+        float gv = 0.f;
+        if (cp[jb] != 0.f && rvalid[r]) {
+          const float dl = (row == col) ? 1.f : 0.f;
+          gv = __expf(v - lse_r[r]) * (1.f + pen_r[r]) - dl;
+          if (symmetric) gv += __expf(v - cl[jb]) - dl;
+          gv *= inv;
+          if (L2) gv = d > 0.f ? gv * __builtin_amdgcn_rcpf(d) : 0.f;
+        }
+        hrow[r] += gv;
+        hcol[jb] += gv;
+        Gs[(wave * 16 + 4 * g + r) * LDG + jb * 16 + r16] = f2bf(gv);
+      }
+    }
+    if (L2) {
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        float h = hcol[jb];
+        h += __shfl_xor(h, 16, 64);
+        h += __shfl_xor(h, 32, 64);
+        if (g == 0) csum[wave][jb * 16 + r16] = h;
+      }
+    }
+    // dphi[16 rows][D] += G[16][64] . Y[64][D] from the wave's own G strip
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      bf16x8 ga = *reinterpret_cast<const bf16x8*>(&Gs[(wave * 16 + r16) * LDG + kk * 32 + g * 8]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        v4s h[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+          const int dcol = nb * 16 + 4 * (r16 & 3);
+          h[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + jrow * LDX + dcol));
+        }
+        v8s yv = {h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+        acc_dx[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, __builtin_bit_cast(bf16x8, yv),
+                                                             acc_dx[nb], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // the whole G tile (and csum) is in LDS
+    {
+      // dpsi[16 columns cb16][16 features nb] = G^T . phi over the 256 rows:
+      // A = G^T (lane (g, j): rows 32kk + 8g..+7 of column j), B = phi
+      // (rows 32kk + 8g..+7 of feature j), both by transpose reads
+      const int cb16 = wave >> 2, nb = wave & 3;
+      floatx4 acc_dy = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < kBRows / 32; ++kk) {
+        v4s ha[2], hb[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+          ha[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+              (lds_v4s*)(Gs + krow * LDG + cb16 * 16 + 4 * (r16 & 3)));
+          hb[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+              (lds_v4s*)(Xs + krow * LDX + nb * 16 + 4 * (r16 & 3)));
+        }
+        v8s av = {ha[0][0], ha[0][1], ha[0][2], ha[0][3], ha[1][0], ha[1][1], ha[1][2], ha[1][3]};
+        v8s bv = {hb[0][0], hb[0][1], hb[0][2], hb[0][3], hb[1][0], hb[1][1], hb[1][2], hb[1][3]};
+        acc_dy = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                         __builtin_bit_cast(bf16x8, bv), acc_dy, 0, 0, 0);
+      }
+      float* dst = a.dX_part + ((int64_t)gridDim.y + blockIdx.x) * B * D;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = j0 + cb16 * 16 + 4 * g + r;
+        if (col < B) dst[(int64_t)col * D + nb * 16 + r16] = acc_dy[r];
+      }
+      if (L2 && tid < kFCols && j0 + tid < B) {
+        float h = 0.f;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) h += csum[w][tid];
+        a.rs_part[((int64_t)gridDim.y + blockIdx.x) * B + j0 + tid] = h;
+      }
+    }
+  }
+  // dphi partial of column block blockIdx.y
+  float* dst = a.dX_part + (int64_t)blockIdx.y * B * D;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row_base + 4 * g + r;
+      if (row < B) dst[(int64_t)row * D + nb * 16 + r16] = acc_dx[nb][r];
+    }
+  if (L2) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float h = hrow[r];
+#pragma unroll
+      for (int o = 1; o <= 8; o <<= 1) h += __shfl_xor(h, o, 64);
+      const int row = row_base + 4 * g + r;
+      if (r16 == 0 && row < B) a.rs_part[(int64_t)blockIdx.y * B + row] = h;
+    }
+  }
+}
+
 // dphi and dpsi (blockIdx.y) from the S split partials:
 //   dX = sum_s part[s]  (- (sum_s rs[s]) * X_bf16 for L2),
 // FP32 and storage copies, one element per thread; with bias_part set, also
@@ -531,13 +741,26 @@ hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, const Gemm
 
 hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmetric,
                             float beta, bool out_bf16, hipStream_t s) {
-  const int S = fused_splits(B), cps = cols_per_split(B, S);
+  const int64_t n = (int64_t)B * D;
+  int S = fused_splits(B);
+  if (D == 64) {  // one pass for both gradients
+    S = fused_bwd_splits(B);
+    const dim3 grid(S, S);
+    const double flops = 4.0 * B * B * D;  // G . psi and G^T . phi; the tile recompute is not counted
+    const double bytes = 2.0 * 2.0 * B * D + 4.0 * 2.0 * B + 2.0 * 4.0 * (double)S * B * (D + 1.0);
+    if (l2) CRL_TIMED("infonce_bwd_both_kernel<l2>", flops, bytes, s,
+                      infonce_bwd_both_kernel<1><<<grid, 1024, 0, s>>>(a, B, beta, symmetric));
+    else    CRL_TIMED("infonce_bwd_both_kernel<dot>", flops, bytes, s,
+                      infonce_bwd_both_kernel<0><<<grid, 1024, 0, s>>>(a, B, beta, symmetric));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int cps = cols_per_split(B, S);
   const int nrb = (B + kFRows - 1) / kFRows;
   dim3 grid(nrb, S);
-  const int64_t n = (int64_t)B * D;
   const double bw_flops = 2.0 * B * B * D;  // G . Y per pass; the tile recompute is not counted
   const double bw_bytes = 2.0 * 2.0 * B * D + 4.0 * 2.0 * B + 4.0 * (double)S * B * (D + 1.0);
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < (D == 64 ? 0 : 2); ++pass) {
     KTimer t = timing_begin(pass ? "infonce_bwd_kernel<cols>" : "infonce_bwd_kernel<rows>",
                             bw_flops, bw_bytes, s);
     if (pass == 0) {

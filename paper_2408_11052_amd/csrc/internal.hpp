@@ -163,6 +163,7 @@ struct FusedArgs {
   float* bias_part[2]; // [chunks][D] column sums of dphi / dpsi per 256/D rows, or nullptr
 };
 int fused_splits(int B);
+int fused_bwd_splits(int B);          // splits of the one-pass backward (D = 64)
 int fused_bias_chunks(int B, int D);  // row blocks of the backward reduction
 // top: the output layer's deferred split-K launch (phi = d[0].C, psi =
 // d[1].C), summed with its bias by the prep kernel; nullptr: phi and psi are
