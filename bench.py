@@ -228,6 +228,7 @@ def main():
     flops = critic_step_flops(w)
     upd = CriticUpdate(w, d_obs, d_act, phi, psi, seed=2)
     nparam = upd.crit.nparam
+    ws_gib = upd.crit.ws_bytes / 2**30
     log(f"[bench] {w.precision}/{w.logits}: {upd.crit.nparam} params, workspace "
         f"{upd.crit.ws_bytes / 2**20:.1f} MiB; timing {args.steps} steps "
         f"(graphs of {args.graph_steps})")
@@ -386,6 +387,7 @@ def main():
         "fp32_plain": fp32,
         "speedup_vs_fp32_plain": round(sps / fp32["steps_per_s"], 2) if fp32 else None,
         "peak_hbm_gib": round(peak_mem, 2),
+        "workspace_gib": round(ws_gib, 3),
         "full_update": full,
         "large_batch": large,
         "roofline": roofline,
