@@ -22,7 +22,7 @@
  *  - Pointers named "device" point to device memory on the current HIP device;
  *    the caller owns every buffer (inputs, outputs, parameters, optimiser
  *    state and the workspace).  The compute calls allocate nothing; only
- *    crl_create allocates (a small device table) and crl_destroy frees it.
+ *    crl_create allocates (small device tables) and crl_destroy frees them.
  *  - All compute calls are asynchronous and ordered on the `stream` argument
  *    (a hipStream_t passed as void*; NULL is the legacy default stream).  No
  *    call synchronises with the host, so every call may be captured into a
@@ -103,7 +103,8 @@ typedef struct crl_layer_info {
 
 /* Create a context on the current HIP device: validates the configuration,
  * plans the workspace and uploads the geometric-offset threshold table for
- * `discount` (see crl_sample_relabel).  On success *out owns that table. */
+ * `discount` (see crl_sample_relabel) and the job tables of the gradient
+ * reductions.  On success *out owns those tables. */
 CRL_API int crl_create(const crl_config* cfg, crl_ctx** out);
 CRL_API int crl_destroy(crl_ctx* ctx);
 
