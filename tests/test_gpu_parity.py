@@ -44,6 +44,10 @@ SMALL = [
                             hidden=(256,) * 3, num_envs=48, episode_len=50),
     WL.SMALL_RELU.with_(name="relu_l2_sym_bf16_mat_b384_tiles", batch_size=384,
                         hidden=(128, 128, 128), precision="bf16", num_envs=32, episode_len=40),
+    # widths that are not whole 128-column tiles on the direct-to-LDS path:
+    # ragged epilogues and ragged fragment-order dW partials
+    WL.DOT_B4096_BF16.with_(name="ln_dot_sym_bf16_fused_b512_ragged_n", batch_size=512,
+                            hidden=(320,) * 2, num_envs=48, episode_len=50),
 ]
 
 
