@@ -398,7 +398,9 @@ void plan_workspace(crl_ctx* x) {
     x->colsumH = take(B * 4);
     x->cpartB = take(((B + 127) / 128) * x->ldF * 4);
   } else {
-    const int S = std::max(fused_splits(x->B), fused_bwd_splits(x->B));
+    // the one-pass backward (D = 64) indexes its partials by 256-row blocks
+    const int S = D == 64 ? std::max(fused_splits(x->B), fused_bwd_splits(x->B))
+                          : fused_splits(x->B);
     const int nrb = (x->B + 63) / 64;
     x->phi_b = take(B * D * 2);
     x->psi_b = take(B * D * 2);

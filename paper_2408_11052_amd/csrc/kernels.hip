@@ -15,6 +15,12 @@ __global__ __launch_bounds__(256) void relabel_kernel(
   const int lane = threadIdx.x & 63;
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (b >= B) return;
+  // the first level of the threshold search probes the same 64 entries for
+  // every sample: fetch them while the counter is read and Philox runs
+  const int n_thr = T_ - 2;
+  const int step0 = (n_thr + 63) >> 6;
+  const int q0 = lane * step0;
+  const uint64_t thr0 = (n_thr > 64 && q0 < n_thr) ? thr[q0] : 0ull;
   uint64_t x[4] = {(uint64_t)b, (uint64_t)(*step), 0ull, 0ull};
   philox4x64_10(x, seed, 0ull);
   const int e = (int)__umul64hi(x[0], (uint64_t)E);
@@ -24,7 +30,14 @@ __global__ __launch_bounds__(256) void relabel_kernel(
   // the lanes probe 64 evenly spaced entries of [lo, hi) at once, and the
   // number of probes above w2 narrows p to one gap between probes.
   const uint64_t w2 = x[2];
-  int lo = 0, hi = T_ - 2;  // p in [lo, hi]
+  int lo = 0, hi = n_thr;  // p in [lo, hi]
+  if (hi - lo > 64) {  // first level from the prefetched probes
+    const bool above = q0 < hi && thr0 > w2;
+    const int c = __popcll(__ballot(above));
+    const int nlo = c > 0 ? (c - 1) * step0 + 1 : 0;
+    hi = min(hi, c * step0);
+    lo = nlo;
+  }
   while (hi - lo > 64) {
     const int step = (hi - lo + 63) >> 6;
     const int q = lo + lane * step;
