@@ -260,7 +260,7 @@ def main():
         if kfl > 0:
             # operand precision: the direct-to-LDS GEMM and the fused InfoNCE
             # kernels always multiply BF16; gemm_kernel names its storage type first
-            bf16_in = (name.startswith("gemm_lds_kernel") or name.startswith("gemm_kernel<bf16")
+            bf16_in = (name.startswith("gemm_lds_") or name.startswith("gemm_kernel<bf16")
                        or name.startswith("infonce"))
             peak = PEAK_BF16_TFLOPS if bf16_in else PEAK_FP32_TFLOPS
             ach = kfl / la / (kms * 1e-3 / la) / 1e12

@@ -7,7 +7,7 @@
 #include <cmath>
 #include <vector>
 
-#include "../../include/crl.h"
+#include "crl.h"
 #include "internal.hpp"
 
 using namespace crl;
@@ -277,8 +277,23 @@ GemmParams dw_params(const crl_ctx* x, const Group& G, int l) {
     P.d[e].lda = l == 0 ? N.ld_in : N.H;
     P.d[e].ldb = P.d[e].ldc = lo.fan_out;
   }
+  // 512 workgroups are resident at once (two per CU).  Layers above the first
+  // run dW in one launch with their input gradient (BF16, both 128-wide
+  // tiles): then dW takes what the dX work items leave of a whole number of
+  // such rounds.
+  int target = 512;
+  if (x->bf16 && l > 0) {
+    int dx_items = 0;
+    bool wide = true;
+    for (int e = 0; e < G.count; ++e) {
+      const LayerOff& lo = x->net[G.nets[e]].lay[l];
+      dx_items += ((x->B + kBM - 1) / kBM) * ((lo.fan_in + kBN - 1) / kBN);
+      wide = wide && lo.fan_in > 64 && lo.fan_out > 64;
+    }
+    if (wide && dx_items % 512) target = 512 - dx_items % 512;
+  }
   P.partial = reinterpret_cast<float*>(1);
-  plan_split_k(P, x->bf16, 512);
+  plan_split_k(P, x->bf16, target);
   P.partial = nullptr;
   return P;
 }
@@ -536,33 +551,32 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
       const Slots& S = x->sl[nc[e].net];
       dZ[e] = top ? (const void*)W(ws, S.dout_t) : (const void*)W(ws, S.dZ[cur]);
     }
+    // dW = in^T . dZ (contraction over the batch); split-K partials are
+    // reduced once, after the last layer
+    GemmParams Pw{};
     if (grads) {
-      {  // dW = in^T . dZ  (contraction over the batch); split-K partials are
-         // reduced once, after the last layer
-        GemmParams P = dw_params(x, G, l);
-        for (int e = 0; e < count; ++e) {
-          const Net& N = x->net[nc[e].net];
-          const Slots& S = x->sl[nc[e].net];
-          const LayerOff& lo = N.lay[l];
-          GemmDesc& d = P.d[e];
-          d.A = l == 0 ? nc[e].x : (const void*)W(ws, S.Hh[l - 1]);
-          d.lda = l == 0 ? nc[e].ld : N.H;
-          d.B = dZ[e]; d.ldb = lo.fan_out;
-          d.C = nc[e].g + lo.w; d.ldc = lo.fan_out;
-          d.alpha = 1.f;
-          d.epi = EPI_NONE;
-        }
-        if (P.splits > 1) {
-          const int bn = gemm_lds_bn(P, x->bf16);
-          if (bn != G.dwbn[l]) return fail(CRL_EINVAL, "internal: dW partial layout mismatch");
-          int64_t ps = 0;
-          for (int e = 0; e < count; ++e) ps = std::max(ps, frag_partial_floats(P, e, bn));
-          P.partial = WF(ws, G.dwp[l]);
-          P.partial_len = (int64_t)P.splits * ps;
-          P.defer_reduce = 1;
-          P.frag = 1;
-        }
-        CRL_HIP(launch_gemm(P, x->bf16, LAY_MC, LAY_MC, false, s), "dW GEMM");
+      Pw = dw_params(x, G, l);
+      for (int e = 0; e < count; ++e) {
+        const Net& N = x->net[nc[e].net];
+        const Slots& S = x->sl[nc[e].net];
+        const LayerOff& lo = N.lay[l];
+        GemmDesc& d = Pw.d[e];
+        d.A = l == 0 ? nc[e].x : (const void*)W(ws, S.Hh[l - 1]);
+        d.lda = l == 0 ? nc[e].ld : N.H;
+        d.B = dZ[e]; d.ldb = lo.fan_out;
+        d.C = nc[e].g + lo.w; d.ldc = lo.fan_out;
+        d.alpha = 1.f;
+        d.epi = EPI_NONE;
+      }
+      if (Pw.splits > 1) {
+        const int bn = gemm_lds_bn(Pw, x->bf16);
+        if (bn != G.dwbn[l]) return fail(CRL_EINVAL, "internal: dW partial layout mismatch");
+        int64_t ps = 0;
+        for (int e = 0; e < count; ++e) ps = std::max(ps, frag_partial_floats(Pw, e, bn));
+        Pw.partial = WF(ws, G.dwp[l]);
+        Pw.partial_len = (int64_t)Pw.splits * ps;
+        Pw.defer_reduce = 1;
+        Pw.frag = 1;
       }
       // bias column partials of this layer (LayerNorm layers get theirs with dZ;
       // top_bias_ready: the output layer's were written with dout)
@@ -579,6 +593,7 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
       }
     }
     if (l == 0) {
+      if (grads) CRL_HIP(launch_gemm(Pw, x->bf16, LAY_MC, LAY_MC, false, s), "dW GEMM");
       if (nc[0].dx) {  // dx[:, j] = dZ . W[c0 + j, :]^T for the requested input columns
         const LayerOff& lo = N0.lay[0];
         GemmParams P{};
@@ -617,7 +632,13 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
         else { d.C = W(ws, S.dZ[nxt]); d.epi = EPI_MASK_POS; d.aux = W(ws, S.Hh[l - 1]); }
       }
       plan_split_k(P, x->bf16, 512);
-      CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_KC, x->bf16, s), "dX GEMM");
+      if (grads && gemm_pair_ok(Pw, P, x->bf16)) {
+        // both products read dZ; one launch, the dW work items first
+        CRL_HIP(launch_gemm_dw_dx(Pw, P, s), "dW + dX GEMM");
+      } else {
+        if (grads) CRL_HIP(launch_gemm(Pw, x->bf16, LAY_MC, LAY_MC, false, s), "dW GEMM");
+        CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_KC, x->bf16, s), "dX GEMM");
+      }
     }
     if (x->ln) {  // column partials of dg, db_ln, db go to the layer's own region
       LnArgs a{};

@@ -81,10 +81,26 @@ int64_t frag_partial_floats(const GemmParams& P, int g, int bn) {
   return (int64_t)((d.M + lds::BM - 1) / lds::BM) * ((d.N + bn - 1) / bn) * lds::BM * bn;
 }
 
-template <typename T, int LA, int LB, typename OutT>
-static hipError_t run(GemmParams& P, hipStream_t s) {
+// algorithmic FLOPs and bytes of one launch (the unpadded K)
+static void algo_counts(const GemmParams& P, double esize, double osize, double& flops,
+                        double& bytes) {
+  for (int g = 0; g < P.count; ++g) {
+    const GemmDesc& d = P.d[g];
+    const double k = d.kb > 0 ? d.kb : d.K;
+    flops += 2.0 * d.M * d.N * k;
+    bytes += esize * ((double)d.M * k + k * d.N) + (P.splits > 1 ? 4.0 : osize) * d.M * d.N;
+  }
+}
+
+static int max_tiles(const GemmParams& P) {
   int maxt = 0;
   for (int g = 0; g < P.count; ++g) maxt = P.tiles[g] > maxt ? P.tiles[g] : maxt;
+  return maxt;
+}
+
+template <typename T, int LA, int LB, typename OutT>
+static hipError_t run(GemmParams& P, hipStream_t s) {
+  const int maxt = max_tiles(P);
   if (maxt == 0) return hipSuccess;
   dim3 grid(maxt, P.splits, P.count), block(kGemmThreads);
   int bn = 0;
@@ -95,14 +111,8 @@ static hipError_t run(GemmParams& P, hipStream_t s) {
         P.d[g].K = P.d[g].kb;
         P.d[g].kb = 0;
       }
-  double flops = 0.0, bytes = 0.0;  // algorithmic: the unpadded K
-  for (int g = 0; g < P.count; ++g) {
-    const GemmDesc& d = P.d[g];
-    const double k = d.kb > 0 ? d.kb : d.K;
-    flops += 2.0 * d.M * d.N * k;
-    bytes += (double)sizeof(T) * ((double)d.M * k + k * d.N) +
-             (double)(P.splits > 1 ? 4 : sizeof(OutT)) * d.M * d.N;
-  }
+  double flops = 0.0, bytes = 0.0;
+  algo_counts(P, sizeof(T), sizeof(OutT), flops, bytes);
   if (bn == 128) {
     KTimer t = timing_begin(lds_kernel_name<LA, LB, OutT, 128>(), flops, bytes, s);
     gemm_lds_kernel<LA, LB, OutT, 128><<<grid, lds::threads<128>(), 0, s>>>(P);
@@ -137,6 +147,31 @@ static hipError_t run_layout(GemmParams& P, int la, int lb, hipStream_t s) {
   if (la == LAY_KC && lb == LAY_MC) return run<T, LAY_KC, LAY_MC, OutT>(P, s);
   if (la == LAY_MC && lb == LAY_KC) return run<T, LAY_MC, LAY_KC, OutT>(P, s);
   return run<T, LAY_MC, LAY_MC, OutT>(P, s);
+}
+
+bool gemm_pair_ok(const GemmParams& Pw, const GemmParams& Px, bool bf16) {
+  return bf16 && lds_path_bn(Pw) == 128 && lds_path_bn(Px) == 128 &&
+         (Pw.splits == 1 || Pw.defer_reduce) && Px.splits == 1 && max_tiles(Pw) > 0 &&
+         max_tiles(Px) > 0;
+}
+
+hipError_t launch_gemm_dw_dx(GemmParams& Pw, GemmParams& Px, hipStream_t s) {
+  if (!gemm_pair_ok(Pw, Px, true)) return hipErrorInvalidValue;
+  PairGrid G;
+  G.gx1 = max_tiles(Pw);
+  G.gy1 = Pw.splits;
+  G.n1 = G.gx1 * G.gy1 * Pw.count;
+  G.gx2 = max_tiles(Px);
+  G.gy2 = 1;
+  G.n2 = G.gx2 * Px.count;
+  double flops = 0.0, bytes = 0.0;
+  algo_counts(Pw, 2.0, 4.0, flops, bytes);
+  algo_counts(Px, 2.0, 2.0, flops, bytes);
+  KTimer t = timing_begin("gemm_lds_pair_kernel<dW,dX>", flops, bytes, s);
+  gemm_lds_pair_kernel<LAY_MC, LAY_MC, float, LAY_KC, LAY_KC, bf16_t>
+      <<<G.n1 + G.n2, lds::threads<128>(), 0, s>>>(Pw, Px, G);
+  timing_end(t);
+  return hipGetLastError();
 }
 
 void plan_split_k(GemmParams& P, bool bf16, int target_wgs) {

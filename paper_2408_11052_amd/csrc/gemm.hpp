@@ -72,16 +72,20 @@ struct GemmParams {
 // of tiles sharing one K range of one problem, whose operand panels then stay
 // in that XCD's L2.
 struct WorkItem { int tile, split, prob; };
-__device__ __forceinline__ WorkItem gemm_work_item() {
-  const int gx = gridDim.x, gy = gridDim.y;
-  const int total = gx * gy * gridDim.z;
-  int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+// lin = launch-order id within a grid of gx tiles x gy splits x problems
+// (total ids), whose first id sits on XCD 0
+__device__ __forceinline__ WorkItem work_item_of(int lin, int gx, int gy, int total) {
   if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
   WorkItem w;
   w.tile = lin % gx;
   w.split = (lin / gx) % gy;
   w.prob = lin / (gx * gy);
   return w;
+}
+__device__ __forceinline__ WorkItem gemm_work_item() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  return work_item_of(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx, gy,
+                      gx * gy * gridDim.z);
 }
 
 template <typename T> struct GemmCfg;

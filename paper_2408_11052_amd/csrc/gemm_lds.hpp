@@ -128,23 +128,23 @@ template <int N> __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt(N | 0x70 | 0xF00);
 }
 
+// LDS bytes of a 128 x BN tile: two stages, or the FP32 epilogue tile
+template <int BN> constexpr int smem_bytes() {
+  constexpr int stage2 = 2 * (tile_bytes<BM>() + tile_bytes<BN>());
+  constexpr int epi = (int)sizeof(float) * BM * (BN + 4);
+  return stage2 > epi ? stage2 : epi;
+}
 }  // namespace lds
 
-// two workgroups per CU: 2 * waves<BN>() waves over the 4 SIMDs
+// One workgroup's work item wi of launch P; smem holds smem_bytes<BN>().
 template <int LA, int LB, typename OutT, int BN>
-__global__ __launch_bounds__(lds::threads<BN>())
-__attribute__((amdgpu_waves_per_eu(lds::waves<BN>() / 2, lds::waves<BN>() / 2)))
-void gemm_lds_kernel(GemmParams P) {
+__device__ __forceinline__ void gemm_lds_tile(const GemmParams& P, const WorkItem wi, char* smem) {
   using namespace lds;
   constexpr int NW = waves<BN>(), NT = threads<BN>();
   constexpr int TA = tile_bytes<BM>(), TB = tile_bytes<BN>();
   constexpr int STAGE = TA + TB;
   constexpr int kLdc = BN + 4;
-  constexpr int EPI = (int)sizeof(float) * BM * kLdc;
-  constexpr int LDS = 2 * STAGE > EPI ? 2 * STAGE : EPI;
   constexpr int NJ = 2;
-  __shared__ __attribute__((aligned(1024))) char smem[LDS];
-  const WorkItem wi = gemm_work_item();
   const int gi = wi.prob;
   const GemmDesc& D = P.d[gi];
   const int ntile = P.tiles[gi];
@@ -254,6 +254,32 @@ void gemm_lds_kernel(GemmParams P) {
     }
     store8_any(C + o, v);
   }
+}
+
+// two workgroups per CU: 2 * waves<BN>() waves over the 4 SIMDs
+template <int LA, int LB, typename OutT, int BN>
+__global__ __launch_bounds__(lds::threads<BN>())
+__attribute__((amdgpu_waves_per_eu(lds::waves<BN>() / 2, lds::waves<BN>() / 2)))
+void gemm_lds_kernel(GemmParams P) {
+  __shared__ __attribute__((aligned(1024))) char smem[lds::smem_bytes<BN>()];
+  gemm_lds_tile<LA, LB, OutT, BN>(P, gemm_work_item(), smem);
+}
+
+// Two independent launches of 128 x 128 tiles in one grid: ids [0, n1) take
+// launch P1 (grid g1 = tiles x splits x problems), the rest launch P2.  One
+// launch instead of two saves a launch's fixed cost (first stage, epilogue,
+// ramp) and lets the second launch's tiles fill the first one's tail.
+struct PairGrid { int n1, gx1, gy1, gx2, gy2, n2; };
+template <int LA1, int LB1, typename Out1, int LA2, int LB2, typename Out2>
+__global__ __launch_bounds__(lds::threads<128>())
+__attribute__((amdgpu_waves_per_eu(lds::waves<128>() / 2, lds::waves<128>() / 2)))
+void gemm_lds_pair_kernel(GemmParams P1, GemmParams P2, PairGrid G) {
+  __shared__ __attribute__((aligned(1024))) char smem[lds::smem_bytes<128>()];
+  const int id = blockIdx.x;
+  if (id < G.n1)
+    gemm_lds_tile<LA1, LB1, Out1, 128>(P1, work_item_of(id, G.gx1, G.gy1, G.n1), smem);
+  else
+    gemm_lds_tile<LA2, LB2, Out2, 128>(P2, work_item_of(id - G.n1, G.gx2, G.gy2, G.n2), smem);
 }
 
 }  // namespace crl

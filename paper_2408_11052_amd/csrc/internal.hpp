@@ -26,6 +26,12 @@ void timing_end(KTimer& t);
 // gemm.hip: dispatch on storage type / operand layouts / output type.
 hipError_t launch_gemm(GemmParams& P, bool bf16, int la, int lb, bool out_bf16,
                        hipStream_t s);
+// One layer's weight gradient (Pw: MC x MC, FP32 out or deferred split-K
+// partials) and input gradient (Px: KC x KC, BF16 out, unsplit) in one launch
+// of the direct-to-LDS kernel; gemm_pair_ok tells whether both launches
+// qualify (BF16 storage, 128-wide tiles, no split-K reduction left to run).
+bool gemm_pair_ok(const GemmParams& Pw, const GemmParams& Px, bool bf16);
+hipError_t launch_gemm_dw_dx(GemmParams& Pw, GemmParams& Px, hipStream_t s);
 // Split factor and chunk for a batch of problems (fills P.splits, P.k_chunk).
 void plan_split_k(GemmParams& P, bool bf16, int target_wgs);
 // Column-tile width of the direct-to-LDS kernel for this launch (128 or 64),

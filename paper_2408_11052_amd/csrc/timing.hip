@@ -8,7 +8,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/crl.h"
+#include "crl.h"
 #include "internal.hpp"
 
 namespace crl {
