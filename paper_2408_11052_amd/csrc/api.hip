@@ -292,8 +292,10 @@ GemmParams dw_params(const crl_ctx* x, const Group& G, int l) {
     }
     if (wide && dx_items % 512) target = 512 - dx_items % 512;
   }
+  // each split's partial (a full M x N block) is written out and read back by
+  // the reduction: splits stay at least 8 steps deep
   P.partial = reinterpret_cast<float*>(1);
-  plan_split_k(P, x->bf16, target);
+  plan_split_k(P, x->bf16, target, 8);
   P.partial = nullptr;
   return P;
 }

@@ -174,7 +174,7 @@ hipError_t launch_gemm_dw_dx(GemmParams& Pw, GemmParams& Px, hipStream_t s) {
   return hipGetLastError();
 }
 
-void plan_split_k(GemmParams& P, bool bf16, int target_wgs) {
+void plan_split_k(GemmParams& P, bool bf16, int target_wgs, int min_steps) {
   const int BK = bf16 ? GemmCfg<bf16_t>::BK : GemmCfg<float>::BK;
   int tiles = 0, kmax = 0;
   for (int g = 0; g < P.count; ++g) {
@@ -185,8 +185,7 @@ void plan_split_k(GemmParams& P, bool bf16, int target_wgs) {
   }
   int splits = 1;
   if (tiles > 0 && P.partial != nullptr) {
-    // at least 4 K steps per split
-    int max_splits = kmax / (4 * BK);
+    int max_splits = kmax / (min_steps * BK);
     while (splits * 2 <= max_splits && tiles * splits * 2 <= target_wgs) splits *= 2;
   }
   int kc = (kmax + splits - 1) / splits;

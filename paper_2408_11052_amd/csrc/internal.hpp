@@ -32,8 +32,10 @@ hipError_t launch_gemm(GemmParams& P, bool bf16, int la, int lb, bool out_bf16,
 // qualify (BF16 storage, 128-wide tiles, no split-K reduction left to run).
 bool gemm_pair_ok(const GemmParams& Pw, const GemmParams& Px, bool bf16);
 hipError_t launch_gemm_dw_dx(GemmParams& Pw, GemmParams& Px, hipStream_t s);
-// Split factor and chunk for a batch of problems (fills P.splits, P.k_chunk).
-void plan_split_k(GemmParams& P, bool bf16, int target_wgs);
+// Split factor and chunk for a batch of problems (fills P.splits, P.k_chunk):
+// the largest power of two that keeps the launch within target_wgs workgroups
+// and every split at least min_steps K steps deep.
+void plan_split_k(GemmParams& P, bool bf16, int target_wgs, int min_steps = 4);
 // Column-tile width of the direct-to-LDS kernel for this launch (128 or 64),
 // or 0 when the register-staged kernel takes it.  Depends on shapes, leading
 // dimensions and pointer alignment only.
