@@ -288,7 +288,7 @@ GemmParams dw_params(const crl_ctx* x, const Group& G, int l) {
     for (int e = 0; e < G.count; ++e) {
       const LayerOff& lo = x->net[G.nets[e]].lay[l];
       dx_items += ((x->B + kBM - 1) / kBM) * ((lo.fan_in + kBN - 1) / kBN);
-      wide = wide && lo.fan_in > 64 && lo.fan_out > 64;
+      wide = wide && lo.fan_in > 64;
     }
     if (wide && dx_items % 512) target = 512 - dx_items % 512;
   }
@@ -298,6 +298,35 @@ GemmParams dw_params(const crl_ctx* x, const Group& G, int l) {
   plan_split_k(P, x->bf16, target, 8);
   P.partial = nullptr;
   return P;
+}
+
+// dX = dZ . W^T of layer l > 0 for the nets of a group: shapes and split plan
+// (no split: the launch has no partial buffer)
+GemmParams dx_params(const crl_ctx* x, const Group& G, int l) {
+  GemmParams P{};
+  P.count = G.count;
+  for (int e = 0; e < G.count; ++e) {
+    const LayerOff& lo = x->net[G.nets[e]].lay[l];
+    GemmDesc& d = P.d[e];
+    d.M = x->B; d.N = lo.fan_in; d.K = lo.fan_out;
+    d.lda = d.ldb = lo.fan_out;
+    d.ldc = lo.fan_in;
+    d.alpha = 1.f;
+    d.epi = x->ln ? EPI_NONE : EPI_MASK_POS;
+  }
+  plan_split_k(P, x->bf16, 512);
+  return P;
+}
+
+// Whether layer l's dW runs in one launch with its dX (launch_gemm_dw_dx).
+// The dW split-K partials are then in the 128-wide fragment order, also where
+// dW alone would take 64-wide tiles (N <= 64: the output layer).  Shapes
+// decide it; the workspace and every operand are 16-byte aligned.
+bool dw_dx_paired(const crl_ctx* x, const Group& G, int l) {
+  if (l == 0) return false;
+  GemmParams Pw = dw_params(x, G, l);
+  Pw.defer_reduce = Pw.splits > 1;
+  return gemm_pair_ok(Pw, dx_params(x, G, l), x->bf16);
 }
 
 // Partial buffers of a group's backward and the jobs that reduce them into
@@ -328,7 +357,7 @@ void plan_group(crl_ctx* x, int gi, int64_t& off) {
     if (P.splits > 1) {
       // partial layout of the kernel that will run: fragment order on the
       // direct-to-LDS kernel, dense otherwise
-      const int bn = gemm_lds_bn(P, x->bf16);
+      const int bn = dw_dx_paired(x, G, l) ? 128 : gemm_lds_bn(P, x->bf16);
       int64_t ps = 0;
       for (int e = 0; e < G.count; ++e) ps = std::max(ps, frag_partial_floats(P, e, bn));
       G.dwbn[l] = bn;
@@ -553,9 +582,30 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
       const Slots& S = x->sl[nc[e].net];
       dZ[e] = top ? (const void*)W(ws, S.dout_t) : (const void*)W(ws, S.dZ[cur]);
     }
+    // dZ of layer l-1 (l > 0): dH = dZ . W^T, then through ReLU or Swish(LayerNorm)
+    const int nxt = top ? 0 : (cur ^ 1);
+    GemmParams Px{};
+    if (l > 0) {
+      Px.count = count;
+      for (int e = 0; e < count; ++e) {
+        const Slots& S = x->sl[nc[e].net];
+        const LayerOff& lo = x->net[nc[e].net].lay[l];
+        GemmDesc& d = Px.d[e];
+        d.A = dZ[e]; d.lda = lo.fan_out;
+        d.B = weights(x, nc[e], lo.w);
+        d.ldb = lo.fan_out;
+        d.M = B; d.N = lo.fan_in; d.K = lo.fan_out;
+        d.alpha = 1.f;
+        d.ldc = lo.fan_in;
+        if (x->ln) { d.C = W(ws, S.dH); d.epi = EPI_NONE; }
+        else { d.C = W(ws, S.dZ[nxt]); d.epi = EPI_MASK_POS; d.aux = W(ws, S.Hh[l - 1]); }
+      }
+      plan_split_k(Px, x->bf16, 512);
+    }
     // dW = in^T . dZ (contraction over the batch); split-K partials are
     // reduced once, after the last layer
     GemmParams Pw{};
+    bool paired = false;
     if (grads) {
       Pw = dw_params(x, G, l);
       for (int e = 0; e < count; ++e) {
@@ -570,14 +620,17 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
         d.alpha = 1.f;
         d.epi = EPI_NONE;
       }
+      Pw.defer_reduce = Pw.splits > 1;
+      paired = dw_dx_paired(x, G, l);
+      if (paired != (l > 0 && gemm_pair_ok(Pw, Px, x->bf16)))
+        return fail(CRL_EINVAL, "internal: dW + dX launch plan mismatch");
       if (Pw.splits > 1) {
-        const int bn = gemm_lds_bn(Pw, x->bf16);
+        const int bn = paired ? 128 : gemm_lds_bn(Pw, x->bf16);
         if (bn != G.dwbn[l]) return fail(CRL_EINVAL, "internal: dW partial layout mismatch");
         int64_t ps = 0;
         for (int e = 0; e < count; ++e) ps = std::max(ps, frag_partial_floats(Pw, e, bn));
         Pw.partial = WF(ws, G.dwp[l]);
         Pw.partial_len = (int64_t)Pw.splits * ps;
-        Pw.defer_reduce = 1;
         Pw.frag = 1;
       }
       // bias column partials of this layer (LayerNorm layers get theirs with dZ;
@@ -594,8 +647,13 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
                 "bias gradient");
       }
     }
+    if (paired) {
+      // both products read dZ; one launch, the dW work items first
+      CRL_HIP(launch_gemm_dw_dx(Pw, Px, s), "dW + dX GEMM");
+    } else if (grads) {
+      CRL_HIP(launch_gemm(Pw, x->bf16, LAY_MC, LAY_MC, false, s), "dW GEMM");
+    }
     if (l == 0) {
-      if (grads) CRL_HIP(launch_gemm(Pw, x->bf16, LAY_MC, LAY_MC, false, s), "dW GEMM");
       if (nc[0].dx) {  // dx[:, j] = dZ . W[c0 + j, :]^T for the requested input columns
         const LayerOff& lo = N0.lay[0];
         GemmParams P{};
@@ -615,33 +673,7 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
       }
       break;
     }
-    // dZ of layer l-1: dH = dZ . W^T, then through ReLU or Swish(LayerNorm)
-    const int nxt = top ? 0 : (cur ^ 1);
-    {
-      GemmParams P{};
-      P.count = count;
-      for (int e = 0; e < count; ++e) {
-        const Slots& S = x->sl[nc[e].net];
-        const LayerOff& lo = x->net[nc[e].net].lay[l];
-        GemmDesc& d = P.d[e];
-        d.A = dZ[e]; d.lda = lo.fan_out;
-        d.B = weights(x, nc[e], lo.w);
-        d.ldb = lo.fan_out;
-        d.M = B; d.N = lo.fan_in; d.K = lo.fan_out;
-        d.alpha = 1.f;
-        d.ldc = lo.fan_in;
-        if (x->ln) { d.C = W(ws, S.dH); d.epi = EPI_NONE; }
-        else { d.C = W(ws, S.dZ[nxt]); d.epi = EPI_MASK_POS; d.aux = W(ws, S.Hh[l - 1]); }
-      }
-      plan_split_k(P, x->bf16, 512);
-      if (grads && gemm_pair_ok(Pw, P, x->bf16)) {
-        // both products read dZ; one launch, the dW work items first
-        CRL_HIP(launch_gemm_dw_dx(Pw, P, s), "dW + dX GEMM");
-      } else {
-        if (grads) CRL_HIP(launch_gemm(Pw, x->bf16, LAY_MC, LAY_MC, false, s), "dW GEMM");
-        CRL_HIP(launch_gemm(P, x->bf16, LAY_KC, LAY_KC, x->bf16, s), "dX GEMM");
-      }
-    }
+    if (!paired) CRL_HIP(launch_gemm(Px, x->bf16, LAY_KC, LAY_KC, x->bf16, s), "dX GEMM");
     if (x->ln) {  // column partials of dg, db_ln, db go to the layer's own region
       LnArgs a{};
       for (int e = 0; e < count; ++e) {

@@ -150,7 +150,7 @@ static hipError_t run_layout(GemmParams& P, int la, int lb, hipStream_t s) {
 }
 
 bool gemm_pair_ok(const GemmParams& Pw, const GemmParams& Px, bool bf16) {
-  return bf16 && lds_path_bn(Pw) == 128 && lds_path_bn(Px) == 128 &&
+  return bf16 && lds_path_bn(Pw) != 0 && lds_path_bn(Px) == 128 &&
          (Pw.splits == 1 || Pw.defer_reduce) && Px.splits == 1 && max_tiles(Pw) > 0 &&
          max_tiles(Px) > 0;
 }

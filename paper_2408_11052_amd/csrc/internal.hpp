@@ -28,8 +28,9 @@ hipError_t launch_gemm(GemmParams& P, bool bf16, int la, int lb, bool out_bf16,
                        hipStream_t s);
 // One layer's weight gradient (Pw: MC x MC, FP32 out or deferred split-K
 // partials) and input gradient (Px: KC x KC, BF16 out, unsplit) in one launch
-// of the direct-to-LDS kernel; gemm_pair_ok tells whether both launches
-// qualify (BF16 storage, 128-wide tiles, no split-K reduction left to run).
+// of the direct-to-LDS kernel with 128-wide tiles (also for a dW with N <= 64);
+// gemm_pair_ok tells whether both launches qualify (BF16 storage, both on the
+// direct-to-LDS kernel, dX 128 wide, no split-K reduction left to run).
 bool gemm_pair_ok(const GemmParams& Pw, const GemmParams& Px, bool bf16);
 hipError_t launch_gemm_dw_dx(GemmParams& Pw, GemmParams& Px, hipStream_t s);
 // Split factor and chunk for a batch of problems (fills P.splits, P.k_chunk):
