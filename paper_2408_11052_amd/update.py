@@ -6,7 +6,9 @@ the policy step on the same batch with the updated critic, and the step of
 the entropy coefficient.  The batch counter
 n (the Philox counter word) and the Adam step t live in device memory and are
 advanced by the library on the stream, so the same enqueued sequence can be
-captured once into a HIP graph and replayed for consecutive updates.
+captured once into a HIP graph and replayed for consecutive updates.  In the
+critic-only update t is n itself: n is advanced once the relabelling has read
+it, so the Adam step of update k sees k + 1, as a separate step counter would.
 """
 from __future__ import annotations
 
@@ -40,21 +42,23 @@ class CriticUpdate:
         self.ws = c.workspace(self.dev)
         self.loss = torch.zeros(8, dtype=torch.float32, device=self.dev)
         self.n = torch.zeros(1, dtype=torch.int64, device=self.dev)  # batch counter
-        self.t = torch.zeros(1, dtype=torch.int64, device=self.dev)  # Adam step
+        self.t = self.n  # Adam step (the full update keeps its own)
 
-    def _critic_step(self, x_sg):
+    def _critic_grads(self, x_sg):
         c = self.crit
         c.crl_sample_relabel(self.obs, self.act, self.seed, self.n, self.idx, self.x_sa,
                              self.x_g, x_sg)
         c.crl_critic_fwd(self.params, self.pbf, self.x_sa, self.x_g, self.ws, self.loss)
         c.crl_critic_bwd(self.params, self.pbf, self.x_sa, self.x_g, self.ws, self.grads)
-        crl_counter_add(self.t, 1)
+
+    def _critic_adam(self):
         crl_adam_step(self.params, self.grads, self.m, self.v, self.pbf, self.t, self.lr)
 
     def enqueue(self):
         """Enqueue one critic update on the current stream (no host sync)."""
-        self._critic_step(None)
-        crl_counter_add(self.n, 1)
+        self._critic_grads(None)
+        crl_counter_add(self.n, 1)  # also the Adam step
+        self._critic_adam()
 
     def capture(self, steps: int = 1) -> torch.cuda.CUDAGraph:
         """A HIP graph of `steps` consecutive updates (replay advances n, t)."""
@@ -102,11 +106,15 @@ class FullUpdate(CriticUpdate):
         self.m_alpha = torch.zeros(4, dtype=torch.float32, device=self.dev)
         self.v_alpha = torch.zeros(4, dtype=torch.float32, device=self.dev)
         self.actor_loss = torch.zeros(4, dtype=torch.float32, device=self.dev)
+        # the policy step reads n after the critic's Adam step: t is its own counter
+        self.t = torch.zeros(1, dtype=torch.int64, device=self.dev)
 
     def enqueue(self):
         """Enqueue one full update (critic, policy, alpha) on the current stream."""
         c = self.crit
-        self._critic_step(self.x_sg)
+        self._critic_grads(self.x_sg)
+        crl_counter_add(self.t, 1)
+        self._critic_adam()
         c.crl_actor_step(self.params, self.pbf, self.aparams, self.apbf, self.log_alpha,
                          self.x_sa, self.x_g, self.x_sg, self.seed, self.n, self.ws,
                          self.agrads, self.alpha_grad, self.actor_loss)
