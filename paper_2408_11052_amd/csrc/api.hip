@@ -263,43 +263,6 @@ void plan_slots(crl_ctx* x, int e, int64_t (*take)(crl_ctx*, int64_t&, int64_t),
   S.dZ[1] = take(x, off, B * H * es);
 }
 
-// dW = in^T . dZ of layer l for the nets of a group: shapes and split plan
-// (the same function plans the workspace and the launch)
-GemmParams dw_params(const crl_ctx* x, const Group& G, int l) {
-  GemmParams P{};
-  P.count = G.count;
-  for (int e = 0; e < G.count; ++e) {
-    const Net& N = x->net[G.nets[e]];
-    const LayerOff& lo = N.lay[l];
-    P.d[e].M = lo.fan_in;
-    P.d[e].N = lo.fan_out;
-    P.d[e].K = x->B;
-    P.d[e].lda = l == 0 ? N.ld_in : N.H;
-    P.d[e].ldb = P.d[e].ldc = lo.fan_out;
-  }
-  // 512 workgroups are resident at once (two per CU).  Layers above the first
-  // run dW in one launch with their input gradient (BF16, both 128-wide
-  // tiles): then dW takes what the dX work items leave of a whole number of
-  // such rounds.
-  int target = 512;
-  if (x->bf16 && l > 0) {
-    int dx_items = 0;
-    bool wide = true;
-    for (int e = 0; e < G.count; ++e) {
-      const LayerOff& lo = x->net[G.nets[e]].lay[l];
-      dx_items += ((x->B + kBM - 1) / kBM) * ((lo.fan_in + kBN - 1) / kBN);
-      wide = wide && lo.fan_in > 64;
-    }
-    if (wide && dx_items % 512) target = 512 - dx_items % 512;
-  }
-  // each split's partial (a full M x N block) is written out and read back by
-  // the reduction: splits stay at least 8 steps deep
-  P.partial = reinterpret_cast<float*>(1);
-  plan_split_k(P, x->bf16, target, 8);
-  P.partial = nullptr;
-  return P;
-}
-
 // dX = dZ . W^T of layer l > 0 for the nets of a group: shapes and split plan
 // (no split: the launch has no partial buffer)
 GemmParams dx_params(const crl_ctx* x, const Group& G, int l) {
@@ -315,6 +278,52 @@ GemmParams dx_params(const crl_ctx* x, const Group& G, int l) {
     d.epi = x->ln ? EPI_NONE : EPI_MASK_POS;
   }
   plan_split_k(P, x->bf16, 512);
+  return P;
+}
+
+// dW = in^T . dZ of layer l for the nets of a group: shapes and split plan
+// (the same function plans the workspace and the launch)
+GemmParams dw_params(const crl_ctx* x, const Group& G, int l) {
+  GemmParams P{};
+  P.count = G.count;
+  for (int e = 0; e < G.count; ++e) {
+    const Net& N = x->net[G.nets[e]];
+    const LayerOff& lo = N.lay[l];
+    P.d[e].M = lo.fan_in;
+    P.d[e].N = lo.fan_out;
+    P.d[e].K = x->B;
+    P.d[e].lda = l == 0 ? N.ld_in : N.H;
+    P.d[e].ldb = P.d[e].ldc = lo.fan_out;
+  }
+  // Each split's partial (a full M x N block) is written out and read back by
+  // the reduction, so splits stay at least 8 steps deep and there are no more
+  // than the launch needs.  Alone, dW fills the 512 resident workgroups (two
+  // per CU).  In one launch with its layer's dX (launch_gemm_dw_dx) the launch
+  // takes about (total 64-deep steps) / 512 steps, and dW is split only until
+  // one split is no deeper than that, and than 64 steps (deeper splits leave
+  // the end of the launch to a few long work items).
+  P.partial = reinterpret_cast<float*>(1);
+  int target = 512;
+  if (l > 0) {
+    GemmParams P1 = P;
+    plan_split_k(P1, x->bf16, 0, 8);  // unsplit: the tile counts
+    const GemmParams Px = dx_params(x, G, l);
+    if (gemm_pair_ok(P1, Px, x->bf16)) {
+      int64_t tiles = 0, work = 0;
+      for (int e = 0; e < G.count; ++e) {
+        tiles += P1.tiles[e];
+        work += (int64_t)Px.tiles[e] * (Px.d[e].K / 64);
+      }
+      const int64_t ksteps = x->B / 64;
+      work += tiles * ksteps;
+      const int64_t span = (work + 511) / 512;
+      int64_t sp = 1;
+      while ((ksteps / sp > span || ksteps / sp > 64) && ksteps / (2 * sp) >= 8) sp *= 2;
+      target = (int)(tiles * sp);
+    }
+  }
+  plan_split_k(P, x->bf16, target, 8);
+  P.partial = nullptr;
   return P;
 }
 
