@@ -331,9 +331,19 @@ __global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int 
     }
   }
   __syncthreads();
-  float* part = a.part[e] + (int64_t)blockIdx.x * 3 * N;
-  for (int k = threadIdx.x; k < 3 * N; k += 256)
-    part[k] = (red[k] + red[3 * N + k]) + (red[6 * N + k] + red[9 * N + k]);
+  // N is a multiple of 8: the four wave rows and the partial row in float4s
+  const float4* r4 = reinterpret_cast<const float4*>(red);
+  float4* p4 = reinterpret_cast<float4*>(a.part[e] + (int64_t)blockIdx.x * 3 * N);
+  const int n4 = 3 * N / 4;
+  for (int k = threadIdx.x; k < n4; k += 256) {
+    const float4 w0 = r4[k], w1 = r4[n4 + k], w2 = r4[2 * n4 + k], w3 = r4[3 * n4 + k];
+    float4 o;
+    o.x = (w0.x + w1.x) + (w2.x + w3.x);
+    o.y = (w0.y + w1.y) + (w2.y + w3.y);
+    o.z = (w0.z + w1.z) + (w2.z + w3.z);
+    o.w = (w0.w + w1.w) + (w2.w + w3.w);
+    p4[k] = o;
+  }
 }
 
 int ln_bwd_partials(int B, int) { return (B + kLnRows - 1) / kLnRows; }
