@@ -48,6 +48,14 @@ SMALL = [
     # ragged epilogues and ragged fragment-order dW partials
     WL.DOT_B4096_BF16.with_(name="ln_dot_sym_bf16_fused_b512_ragged_n", batch_size=512,
                             hidden=(320,) * 2, num_envs=48, episode_len=50),
+    # every layer's dW and dX in one launch with split-K dW partials (4 splits of
+    # 8 steps), the output layer's on 128-wide tiles over its 64 columns
+    WL.DOT_B4096_BF16.with_(name="ln_dot_sym_bf16_fused_b2048_paired", batch_size=2048,
+                            hidden=(512,) * 2, num_envs=64, episode_len=60),
+    # 64-wide hidden layers: dX takes 64-wide tiles, so dW and dX run apart
+    WL.SMALL_RELU.with_(name="relu_dot_sym_bf16_fused_b256_h64", batch_size=256,
+                        hidden=(64, 64), energy_function="dot", precision="bf16",
+                        logits="fused", num_envs=24, episode_len=30),
 ]
 
 
