@@ -325,7 +325,11 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
       else xa[ks] = bf16x8{};
     }
   }
-  float nx[4], lse_a[4], pen_a[4], hsum[4];
+  // the penalty factor 2 beta r_i is formed from the row LSE where it is
+  // used (lse_a for the rows pass, the column values for the columns pass):
+  // fewer live registers keep the D = 256 kernels at two waves per SIMD
+  const float beta2 = 2.f * beta;
+  float nx[4], lse_a[4], hsum[4];
   bool rvalid[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -333,7 +337,6 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
     rvalid[r] = row < B;
     nx[r] = (L2 && rvalid[r]) ? nX[row] : 0.f;
     lse_a[r] = rvalid[r] ? lseX[row] : 0.f;
-    pen_a[r] = rvalid[r] ? (TRANS ? 0.f : 2.f * beta * a.r[row]) : 0.f;
     hsum[r] = 0.f;
   }
   floatx4 acc_dx[NB];
@@ -341,14 +344,13 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
   for (int nb = 0; nb < NB; ++nb) acc_dx[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   // per-lane column values of a tile (columns j0 + jb*16 + r16)
-  struct ColVals { float lse[4], pen[4], ny[4]; };
+  struct ColVals { float lse[4], ny[4]; };
   auto col_load = [&](ColVals& cvv, int j0) {
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
       const int col = j0 + jb * 16 + r16;
       const bool cv = col < c1;
       cvv.lse[jb] = cv ? lseY[col] : 0.f;
-      cvv.pen[jb] = (cv && TRANS) ? 2.f * beta * a.r[col] : 0.f;
       cvv.ny[jb] = (L2 && cv) ? nY[col] : 0.f;
     }
   };
@@ -392,10 +394,10 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
           const float pa = __expf(v - lse_a[r]);
           const float pb = __expf(v - cvals.lse[jb]);
           if (TRANS == 0) {
-            gv = pa * (1.f + pen_a[r]) - dl;
+            gv = pa * (1.f + beta2 * lse_a[r]) - dl;
             if (symmetric) gv += pb - dl;
           } else {
-            gv = pb * (1.f + cvals.pen[jb]) - dl;
+            gv = pb * (1.f + beta2 * cvals.lse[jb]) - dl;
             if (symmetric) gv += pa - dl;
           }
           gv *= inv;
