@@ -714,6 +714,41 @@ int fused_bias_chunks(int B, int D) { return (int)(((int64_t)B * D + 255) / 256)
     default: return hipErrorInvalidValue;                   \
   }
 
+// Workgroups of the forward kernel for (D, l2) that the device holds at once
+// (its register and LDS use decide how many fit on a CU), or 0 if unknown.
+static int fwd_resident_wgs(int D, int l2) {
+  const void* k = nullptr;
+#define CRL_FWD_PTR(KS_, L2_) k = reinterpret_cast<const void*>(&infonce_fwd_kernel<KS_, L2_>)
+  switch (D) {
+    case 32:  if (l2) CRL_FWD_PTR(1, 1); else CRL_FWD_PTR(1, 0); break;
+    case 64:  if (l2) CRL_FWD_PTR(2, 1); else CRL_FWD_PTR(2, 0); break;
+    case 128: if (l2) CRL_FWD_PTR(4, 1); else CRL_FWD_PTR(4, 0); break;
+    case 256: if (l2) CRL_FWD_PTR(8, 1); else CRL_FWD_PTR(8, 0); break;
+    default: return 0;
+  }
+#undef CRL_FWD_PTR
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+// Column splits of the forward: fused_splits(B), or fewer where the kernel's
+// resident capacity takes the launch in one round that way (D = 256 holds
+// three workgroups per CU: 3 splits at B=16384 run in one round, 4 in two).
+static int fused_fwd_splits(int B, int D, int l2) {
+  const int S = fused_splits(B);
+  const int nrb = (B + kFRows - 1) / kFRows;
+  const int cap = fwd_resident_wgs(D, l2);
+  if (cap <= 0 || (int64_t)nrb * S <= cap) return S;
+  const int S1 = std::max(1, cap / nrb);
+  // one round of S1 splits against ceil(nrb S / cap) rounds of S splits
+  const int64_t rounds = ((int64_t)nrb * S + cap - 1) / cap;
+  return (int64_t)S1 * rounds > S ? S1 : S;
+}
+
 hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, const GemmParams* top,
                             hipStream_t s) {
   if (top)
@@ -724,7 +759,7 @@ hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, const Gemm
               fused_prep_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, B, D));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int S = fused_splits(B), cps = cols_per_split(B, S);
+  const int S = fused_fwd_splits(B, D, l2), cps = cols_per_split(B, S);
   const int nrb = (B + kFRows - 1) / kFRows;
   dim3 grid(nrb, S);
   const double fw_flops = 2.0 * B * B * D;
