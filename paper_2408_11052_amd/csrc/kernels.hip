@@ -549,19 +549,20 @@ __device__ __forceinline__ void reduce_many(const char* __restrict__ ws, float* 
   const RedJob J = jobs[find_job(jobs, njobs, blk)];
   const int col = threadIdx.x & 15, grp = threadIdx.x >> 4;
   const int64_t i = (blk - J.first) * 16 + col;
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  // eight running sums: eight loads in flight per thread
+  float sk[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) sk[q] = 0.f;
   if (i < J.n) {
     const float* p = reinterpret_cast<const float*>(ws + J.src) + i;
     int k = grp;
-    for (; k + 48 < J.nparts; k += 64) {
-      s0 += p[k * J.stride];
-      s1 += p[(k + 16) * J.stride];
-      s2 += p[(k + 32) * J.stride];
-      s3 += p[(k + 48) * J.stride];
+    for (; k + 112 < J.nparts; k += 128) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sk[q] += p[(k + 16 * q) * J.stride];
     }
-    for (; k < J.nparts; k += 16) s0 += p[k * J.stride];
+    for (; k < J.nparts; k += 16) sk[0] += p[k * J.stride];
   }
-  red[grp][col] = (s0 + s1) + (s2 + s3);
+  red[grp][col] = ((sk[0] + sk[1]) + (sk[2] + sk[3])) + ((sk[4] + sk[5]) + (sk[6] + sk[7]));
   __syncthreads();
   for (int h = 8; h >= 1; h >>= 1) {
     if (grp < h) red[grp][col] += red[grp + h][col];
