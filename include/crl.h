@@ -4,19 +4,19 @@
  * One critic update of contrastive RL (Algorithm 1, the update loop):
  *   1. draw a batch of (s, a) uniformly from a GPU-resident replay buffer and
  *      relabel each goal to a future state of the same trajectory at a
- *      geometric offset (Section 2.2 "Policy Learning"; Preliminaries, the
- *      discounted state-visitation law; Appendix E)        -> crl_sample_relabel
+ *      geometric offset (Section 3.2 "Policy Learning"; Preliminaries, the
+ *      discounted state-visitation law; Appendix D)        -> crl_sample_relabel
  *   2. run the encoders phi(s, a) and psi(g), form the B x B critic matrix
- *      with the dot or L2 energy (Section 2.1; Appendix B energy table), and
- *      the InfoNCE loss with the logsumexp penalty (Section 2.1 critic
- *      objective; Appendix B InfoNCE-forward/backward/symmetric)
+ *      with the dot or L2 energy (Section 3.1; Appendix A.2 energy table), and
+ *      the InfoNCE loss with the logsumexp penalty (Section 3.1 critic
+ *      objective; Appendix A.2 InfoNCE-forward/backward/symmetric)
  *                                                          -> crl_critic_fwd
  *   3. the gradient of that loss w.r.t. every encoder parameter
  *                                                          -> crl_critic_bwd
  *   4. the optimiser step on the flat parameter vector     -> crl_adam_step
  * and, when the context has a policy, the policy step that follows the critic
- * step on the same batch (Section 2.2 policy learning; Algorithm 1, policy
- * update; Section 4 setup, tunable entropy coefficient)   -> crl_actor_step
+ * step on the same batch (Section 3.2 policy learning; Algorithm 1, policy
+ * update; Section 5.1 setup, tunable entropy coefficient)   -> crl_actor_step
  *
  * Conventions shared by every call
  *  - Pointers named "device" point to device memory on the current HIP device;
@@ -128,7 +128,7 @@ CRL_API int crl_workspace_size(const crl_ctx* ctx, int64_t* bytes);
 CRL_API int crl_input_layout(const crl_ctx* ctx, int32_t* ld_sa, int32_t* ld_g,
                              int32_t* ld_sg, int32_t* elem_bytes);
 
-/* Step 1: sample and relabel one batch (Section 2.2; Algorithm 1, batch
+/* Step 1: sample and relabel one batch (Section 3.2; Algorithm 1, batch
  * sampling "with discount"; Preliminaries: the offset T ~ Geom(1 - gamma)).
  *   obs    device FP32 [num_envs][episode_len][obs_dim], one episode per row
  *   act    device FP32 [num_envs][episode_len][act_dim]
@@ -150,7 +150,7 @@ CRL_API int crl_sample_relabel(crl_ctx* ctx, const float* obs, const float* act,
                                uint64_t seed, const int64_t* step, int32_t* idx,
                                void* x_sa, void* x_g, void* x_sg, void* stream);
 
-/* Step 2: encoders, critic matrix and loss (Section 2.1 objective; Appendix B
+/* Step 2: encoders, critic matrix and loss (Section 3.1 objective; Appendix A.2
  * energies and InfoNCE variants; Algorithm 1 critic update with the
  * logsumexp penalty).
  *   params       device FP32 flat parameters (layout above)
@@ -179,8 +179,8 @@ CRL_API int crl_critic_bwd(crl_ctx* ctx, const float* params,
                            const void* x_g, void* ws, float* grads,
                            void* stream);
 
-/* Policy step (Section 2.2, the policy objective; Algorithm 1 takes it after
- * the critic update, on the same batch; Section 4 setup, SAC-style tunable
+/* Policy step (Section 3.2, the policy objective; Algorithm 1 takes it after
+ * the critic update, on the same batch; Section 5.1 setup, SAC-style tunable
  * entropy coefficient).  With the critic frozen at `params`:
  *   o = pi_MLP(x_sg) = [mu | rho | pad],  sigma = softplus(rho) + 1e-3,
  *   u = mu + sigma eps,  a' = tanh(u),

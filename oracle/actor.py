@@ -1,7 +1,7 @@
 """Policy (actor) step of contrastive RL, in FP64 numpy.
 
-What is computed (Section 2.2 "Policy Learning", the DDPG-style policy
-objective; Section 4 setup: SAC-style tunable entropy coefficient; Algorithm 1,
+What is computed (Section 3.2 "Policy Learning", the DDPG-style policy
+objective; Section 5.1 setup: SAC-style tunable entropy coefficient; Algorithm 1,
 policy update after the critic update):
 
 * the policy pi(a | s, g) is a tanh-squashed Gaussian: an MLP on [s, g]

@@ -4,7 +4,7 @@ Algorithm 1 writes the critic and policy updates as gradient steps with a
 learning rate and names no optimiser; the readings here are Adam
 (Kingma & Ba, 2015, Algorithm 1) with beta1 = 0.9, beta2 = 0.999,
 eps = 1e-8 added outside the square root, bias correction with the step
-number t >= 1, and no weight decay (Appendix F reports weight decay did not
+number t >= 1, and no weight decay (Appendix E reports weight decay did not
 help).  Learning rates follow the hyperparameter table (critic 3e-4,
 policy 6e-4).
 

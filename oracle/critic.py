@@ -1,16 +1,16 @@
 """Contrastive critic: encoders, energies, InfoNCE + logsumexp penalty, and
 their gradients, in plain FP64 numpy.
 
-What is computed (Section 2.1, "Contrastive Critic Learning"; Appendix B,
+What is computed (Section 3.1, "Contrastive Critic Learning"; Appendix A.2,
 "Energy functions and contrastive objectives"; Algorithm 1, critic update):
 
 * phi(s, a) and psi(g) are MLPs.  A hidden layer is z = x W + b followed by
   ReLU, or by LayerNorm (over features, biased variance) with affine
-  scale/offset and then Swish y * sigmoid(y) (Section 4.3 puts LayerNorm
+  scale/offset and then Swish y * sigmoid(y) (Section 5.4 puts LayerNorm
   before every activation).  The output layer is linear.
 * The critic matrix is F_ij = f(s_i, a_i, g_j) over the batch, with the dot
   energy <phi_i, psi_j> or the L2 energy -||phi_i - psi_j||_2 (the table of
-  energies in Appendix B; the sign follows that table).
+  energies in Appendix A.2; the sign follows that table).
 * InfoNCE-forward contrasts each row against its batch, InfoNCE-backward each
   column; the symmetric objective is their sum.  Each is averaged over the
   batch (so all-zero logits give log B per direction).

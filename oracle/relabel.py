@@ -2,8 +2,8 @@
 
 Preliminaries: the discounted state-visitation distribution is the law of the
 state T steps ahead with T ~ Geom(1 - gamma), and it equals the Q-function of
-the goal-reaching reward (Appendix E, "Q-function is probability").
-Section 2.2 ("Policy Learning") and Algorithm 1 ("Contrastive Reinforcement
+the goal-reaching reward (Appendix D, "Q-function is probability").
+Section 3.2 ("Policy Learning") and Algorithm 1 ("Contrastive Reinforcement
 Learning", the update loop) form a batch by drawing (s, a) uniformly from the
 buffer and a goal from the *future* of the same trajectory, sampled with
 discount.

@@ -1,6 +1,6 @@
 // Policy (actor) step kernels: the tanh-Gaussian head with its reparameterised
 // sample, the energy of the policy's action under the frozen critic, the head
-// backward and the loss reduction (Section 2.2, policy learning; Section 4
+// backward and the loss reduction (Section 3.2, policy learning; Section 5.1
 // setup, tunable entropy coefficient).  The MLPs around them are the encoder
 // GEMM / LayerNorm kernels.
 #include "internal.hpp"

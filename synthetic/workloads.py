@@ -3,7 +3,7 @@
 Each workload fixes the replay-buffer shape, the synthetic state process, the
 batch size and the encoder architecture.  These are plain records: nothing
 here computes any part of the method.  Field names follow the hyperparameter
-table of the paper (Appendix B, "Benchmark parameters": ``batch_size``,
+table of the paper (Appendix B.3, "Benchmark parameters": ``batch_size``,
 ``discounting``, ``energy_function``, ``contrastive_loss_function``,
 ``logsumexp_penalty``, hidden layers, representation dimension).
 """
