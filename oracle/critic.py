@@ -8,9 +8,11 @@ What is computed (Section 3.1, "Contrastive Critic Learning"; Appendix A.2,
   ReLU, or by LayerNorm (over features, biased variance) with affine
   scale/offset and then Swish y * sigmoid(y) (Section 5.4 puts LayerNorm
   before every activation).  The output layer is linear.
-* The critic matrix is F_ij = f(s_i, a_i, g_j) over the batch, with the dot
-  energy <phi_i, psi_j> or the L2 energy -||phi_i - psi_j||_2 (the table of
-  energies in Appendix A.2; the sign follows that table).
+* The critic matrix is F_ij = f(s_i, a_i, g_j) over the batch, with one of
+  the energies of Appendix A.2 (the sign follows that table): dot
+  <phi_i, psi_j>; cosine <phi_i, psi_j> / (||phi_i|| ||psi_j||) (read as 0
+  where a norm is 0); L1 -||phi_i - psi_j||_1; L2 -||phi_i - psi_j||_2; and
+  L2 without the square root -||phi_i - psi_j||_2^2.
 * InfoNCE-forward contrasts each row against its batch, InfoNCE-backward each
   column; the symmetric objective is their sum.  Each is averaged over the
   batch (so all-zero logits give log B per direction).
@@ -104,17 +106,30 @@ def mlp_backward(layers, caches, dout, activation: str):
 # --------------------------------------------------------------------------
 # energies
 # --------------------------------------------------------------------------
+def _unit(X):
+    n = np.sqrt((X * X).sum(axis=1))
+    return X / np.where(n > 0.0, n, 1.0)[:, None] * (n > 0.0)[:, None], n
+
+
 def energy_matrix(phi, psi, kind: str, block: int = 256):
-    """F_ij for all pairs.  L2 is evaluated directly from the differences."""
+    """F_ij for all pairs.  The distances are evaluated directly from the
+    differences phi_i - psi_j."""
     phi = np.asarray(phi, f64)
     psi = np.asarray(psi, f64)
     if kind == "dot":
         return phi @ psi.T
-    if kind == "l2":
+    if kind == "cos":
+        return _unit(phi)[0] @ _unit(psi)[0].T
+    if kind in ("l2", "l2sq", "l1"):
         F = np.empty((phi.shape[0], psi.shape[0]), f64)
         for i0 in range(0, phi.shape[0], block):
             diff = phi[i0:i0 + block, None, :] - psi[None, :, :]
-            F[i0:i0 + block] = -np.sqrt((diff * diff).sum(axis=2))
+            if kind == "l1":
+                F[i0:i0 + block] = -np.abs(diff).sum(axis=2)
+            elif kind == "l2":
+                F[i0:i0 + block] = -np.sqrt((diff * diff).sum(axis=2))
+            else:
+                F[i0:i0 + block] = -(diff * diff).sum(axis=2)
         return F
     raise ValueError(kind)
 
@@ -125,7 +140,13 @@ def energy_row(phi_i, psi, kind: str):
     psi = np.asarray(psi, f64)
     if kind == "dot":
         return psi @ phi_i
+    if kind == "cos":
+        return energy_matrix(phi_i[None, :], psi, "cos")[0]
     diff = phi_i[None, :] - psi
+    if kind == "l1":
+        return -np.abs(diff).sum(axis=1)
+    if kind == "l2sq":
+        return -(diff * diff).sum(axis=1)
     return -np.sqrt((diff * diff).sum(axis=1))
 
 
@@ -141,6 +162,31 @@ def energy_backward(phi, psi, F, G, kind: str):
         H = np.where(d > 0.0, G / np.where(d > 0.0, d, 1.0), 0.0)
         dphi = -(H.sum(axis=1)[:, None] * phi - H @ psi)
         dpsi = H.T @ phi - H.sum(axis=0)[:, None] * psi
+        return dphi, dpsi
+    if kind == "l2sq":
+        # dF_ij/dphi_i = -2 (phi_i - psi_j), dF_ij/dpsi_j = +2 (phi_i - psi_j)
+        dphi = -2.0 * (G.sum(axis=1)[:, None] * phi - G @ psi)
+        dpsi = 2.0 * (G.T @ phi - G.sum(axis=0)[:, None] * psi)
+        return dphi, dpsi
+    if kind == "cos":
+        # with u_i = phi_i / |phi_i|, v_j = psi_j / |psi_j|, F_ij = u_i . v_j:
+        # dF_ij/dphi_i = (v_j - F_ij u_i) / |phi_i|, dF_ij/dpsi_j = (u_i - F_ij v_j) / |psi_j|
+        u, nu = _unit(phi)
+        v, nv = _unit(psi)
+        iu = np.where(nu > 0.0, 1.0 / np.where(nu > 0.0, nu, 1.0), 0.0)
+        iv = np.where(nv > 0.0, 1.0 / np.where(nv > 0.0, nv, 1.0), 0.0)
+        GF = G * F
+        dphi = (G @ v - GF.sum(axis=1)[:, None] * u) * iu[:, None]
+        dpsi = (G.T @ u - GF.sum(axis=0)[:, None] * v) * iv[:, None]
+        return dphi, dpsi
+    if kind == "l1":
+        # dF_ij/dphi_ik = -sign(phi_ik - psi_jk) (0 where they are equal)
+        dphi = np.empty_like(phi)
+        dpsi = np.zeros_like(psi)
+        for i in range(phi.shape[0]):
+            sg = np.sign(phi[i][None, :] - psi)        # [B_psi][D]
+            dphi[i] = -(G[i][:, None] * sg).sum(axis=0)
+            dpsi += G[i][:, None] * sg
         return dphi, dpsi
     raise ValueError(kind)
 
@@ -192,8 +238,9 @@ def infonce_grad(F, r, c, loss: str, beta: float):
 def critic_forward(phi_layers, psi_layers, x_sa, x_g, w) -> Dict[str, object]:
     phi, c_phi = mlp_forward(phi_layers, x_sa, w.activation, w.ln_eps)
     psi, c_psi = mlp_forward(psi_layers, x_g, w.activation, w.ln_eps)
+    from .objectives import contrastive_loss
     F = energy_matrix(phi, psi, w.energy_function)
-    out = infonce_loss(F, w.contrastive_loss_function, w.logsumexp_penalty)
+    out = contrastive_loss(F, w.contrastive_loss_function, w.logsumexp_penalty)
     out.update(phi=phi, psi=psi, F=F, c_phi=c_phi, c_psi=c_psi)
     return out
 
@@ -201,8 +248,9 @@ def critic_forward(phi_layers, psi_layers, x_sa, x_g, w) -> Dict[str, object]:
 def critic_loss_and_grads(phi_layers, psi_layers, x_sa, x_g, w):
     """Forward and backward of the critic loss; grads per layer for phi, psi."""
     fw = critic_forward(phi_layers, psi_layers, x_sa, x_g, w)
-    G = infonce_grad(fw["F"], fw["r"], fw["c"], w.contrastive_loss_function,
-                     w.logsumexp_penalty)
+    from .objectives import contrastive_grad
+    G = contrastive_grad(fw["F"], fw["r"], fw["c"], w.contrastive_loss_function,
+                         w.logsumexp_penalty)
     dphi, dpsi = energy_backward(fw["phi"], fw["psi"], fw["F"], G,
                                  w.energy_function)
     g_phi, _ = mlp_backward(phi_layers, fw["c_phi"], dphi, w.activation)
