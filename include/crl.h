@@ -58,12 +58,32 @@ typedef enum {
   CRL_OK = 0,
   CRL_EINVAL = -1,        /* bad argument (null pointer, size, alignment) */
   CRL_EUNSUPPORTED = -2,  /* valid but not supported by this build */
-  CRL_EHIP = -3           /* a HIP runtime call or launch failed */
+  CRL_EHIP = -3,          /* a HIP runtime call or launch failed */
+  CRL_ENONFINITE = -4     /* crl_check_finite: the loss or a row term is not finite */
 } crl_status;
 
 enum { CRL_ACT_RELU = 0, CRL_ACT_LN_SWISH = 1 };
-enum { CRL_ENERGY_DOT = 0, CRL_ENERGY_L2 = 1 };
-enum { CRL_LOSS_FWD = 0, CRL_LOSS_SYM = 1 };
+/* Energies of Appendix A.2: <phi, psi>; -||phi - psi||_2; the cosine
+ * <phi, psi> / (||phi|| ||psi||) (0 where a norm is 0); -||phi - psi||_2^2
+ * ("L2 without the square root"); -||phi - psi||_1. */
+enum { CRL_ENERGY_DOT = 0, CRL_ENERGY_L2 = 1, CRL_ENERGY_COS = 2, CRL_ENERGY_L2SQ = 3,
+       CRL_ENERGY_L1 = 4 };
+/* Contrastive objectives of Appendix A.2 (every one with the logsumexp
+ * penalty beta * mean_i r_i^2, Section 5.3), averaged over the positives i,
+ * sums over j over the whole batch; r_i = LSE_j F_ij, c_j = LSE_i F_ij:
+ *   FWD   InfoNCE-forward   mean_i (r_i - F_ii)
+ *   SYM   InfoNCE-symmetric FWD + BWD
+ *   BWD   InfoNCE-backward  mean_j (c_j - F_jj)
+ *   FLATNCE_FWD / _BWD      mean_i S_i / stopgrad(S_i), S_i = sum_j
+ *                           exp(F_ij - F_ii) (rows) or sum_j exp(F_ji - F_ii)
+ *                           (columns): value 1, the gradient of mean log S
+ *   FB    Forward-Backward  mean_i [-exp(F_ii) + sum_{j!=i} exp(2 F_ij) / (2(B-1))]
+ *   DPO   mean_i sum_j -log sigmoid(F_ii - F_ij)
+ *   IPO   mean_i sum_j (F_ii - F_ij - 1)^2
+ *   SPPO  mean_i sum_j [(F_ii - 1)^2 + (F_ij + 1)^2] */
+enum { CRL_LOSS_FWD = 0, CRL_LOSS_SYM = 1, CRL_LOSS_BWD = 2, CRL_LOSS_FLATNCE_FWD = 3,
+       CRL_LOSS_FLATNCE_BWD = 4, CRL_LOSS_FB = 5, CRL_LOSS_DPO = 6, CRL_LOSS_IPO = 7,
+       CRL_LOSS_SPPO = 8 };
 enum { CRL_PREC_FP32 = 0, CRL_PREC_BF16 = 1 };
 /* materialised: the B x B critic matrix is written to the workspace (FP32);
  * fused: online log-sum-exp over tiles, the matrix never exists in memory. */
@@ -77,10 +97,11 @@ typedef struct crl_config {
   int32_t goal_lo;
   int32_t n_hidden;       /* hidden layers per encoder (>= 1) */
   int32_t hidden;         /* hidden width (multiple of 8, at most 1024) */
-  int32_t repr_dim;       /* D, multiple of 8 (fused logits: 64 or 256) */
+  int32_t repr_dim;       /* D, multiple of 8 (fused logits: 32, 64, 128 or 256;
+                             L1 energy: at most 256) */
   int32_t activation;     /* CRL_ACT_* : ReLU, or LayerNorm then Swish */
-  int32_t energy;         /* CRL_ENERGY_*: <phi,psi> or -||phi - psi||_2 */
-  int32_t loss;           /* CRL_LOSS_*: InfoNCE forward, or symmetric */
+  int32_t energy;         /* CRL_ENERGY_* (fused logits: DOT, L2, COS, L2SQ) */
+  int32_t loss;           /* CRL_LOSS_* (fused logits: FWD, SYM, BWD, FLATNCE_*) */
   int32_t precision;      /* CRL_PREC_*: arithmetic of GEMM and logit tiles */
   int32_t logits;         /* CRL_LOGITS_* */
   float logsumexp_penalty;/* beta of beta * mean_i (LSE_j F_ij)^2 */
@@ -160,10 +181,12 @@ CRL_API int crl_sample_relabel(crl_ctx* ctx, const float* obs, const float* act,
  *   ws           device workspace of crl_workspace_size bytes; keeps the
  *                activations that crl_critic_bwd needs
  *   loss_out     device FP32 [8] out: {total, L_fwd, L_bwd, L_pen,
- *                mean_i r_i, mean_j c_j, #non-finite row/col terms, 0}
- * with F_ij = <phi_i, psi_j> or -||phi_i - psi_j||, r_i = LSE_j F_ij,
- * c_j = LSE_i F_ij, L_fwd = mean_i (r_i - F_ii), L_bwd = mean_j (c_j - F_jj),
- * L_pen = beta * mean_i r_i^2 and total = L_fwd (+ L_bwd if symmetric) + L_pen. */
+ *                mean_i r_i, mean_j c_j, #non-finite row/col terms, L_obj}
+ * with F_ij = energy(phi_i, psi_j) (CRL_ENERGY_*), r_i = LSE_j F_ij,
+ * c_j = LSE_i F_ij, L_fwd = mean_i (r_i - F_ii), L_bwd = mean_j (c_j - F_jj)
+ * (the two InfoNCE directions, reported for every objective),
+ * L_pen = beta * mean_i r_i^2, L_obj the objective (CRL_LOSS_*) and
+ * total = L_obj + L_pen. */
 CRL_API int crl_critic_fwd(crl_ctx* ctx, const float* params,
                            const uint16_t* params_bf16, const void* x_sa,
                            const void* x_g, void* ws, float* loss_out,
@@ -178,6 +201,33 @@ CRL_API int crl_critic_bwd(crl_ctx* ctx, const float* params,
                            const uint16_t* params_bf16, const void* x_sa,
                            const void* x_g, void* ws, float* grads,
                            void* stream);
+
+/* The critic matrix and the loss alone, from given representations: the
+ * energy and objective steps of crl_critic_fwd / crl_critic_bwd (Section 3.1
+ * objective; Appendix A.2 energies and objectives; the logsumexp penalty of
+ * Algorithm 1) with phi and psi supplied by the caller instead of the
+ * encoders, for tests of the loss on chosen logits (all-zero logits, logits
+ * whose row log-sum-exps vanish, B = 1 or 2, large |F|).
+ *   phi, psi   device FP32 [B][repr_dim] (read; BF16 precision rounds them
+ *              to BF16 tiles as the encoder outputs are)
+ *   ws         the context's workspace (r, c and F_ii land in the views
+ *              CRL_WS_ROW_LSE, CRL_WS_COL_LSE, CRL_WS_DIAG)
+ *   loss_out   device FP32 [8] out, as crl_critic_fwd's
+ * crl_infonce_bwd must follow crl_infonce_fwd on the same phi, psi, ws and
+ * stream; it writes dL/dphi and dL/dpsi (device FP32 [B][repr_dim], caller
+ * owned, not accumulated).  Arguments as for crl_critic_fwd; 16-byte aligned
+ * pointers.  Nothing is allocated. */
+CRL_API int crl_infonce_fwd(crl_ctx* ctx, const float* phi, const float* psi, void* ws,
+                            float* loss_out, void* stream);
+CRL_API int crl_infonce_bwd(crl_ctx* ctx, const float* phi, const float* psi, void* ws,
+                            float* dphi, float* dpsi, void* stream);
+
+/* Reads loss_out [8] as a forward left it (crl_critic_fwd, crl_infonce_fwd)
+ * after waiting for `stream`: CRL_ENONFINITE if the total is not finite or
+ * any row / column term was (loss_out[6] > 0), else CRL_OK.  This call
+ * synchronises with the host, so it must not be captured into a graph
+ * (CRL_EINVAL while the stream is capturing). */
+CRL_API int crl_check_finite(const float* loss_out, void* stream);
 
 /* Policy step (Section 3.2, the policy objective; Algorithm 1 takes it after
  * the critic update, on the same batch; Section 5.1 setup, SAC-style tunable

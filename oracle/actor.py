@@ -10,7 +10,8 @@ policy update after the critic update):
 * log pi(a'|s,g) = sum_k [log N(u_k; mu_k, sigma_k) - log(1 - tanh^2 u_k)],
   the tanh correction written stably as 2 (log 2 - u - softplus(-2u));
 * the actor loss is L_pi = mean_i [alpha log pi_i - f(phi(s_i, a'_i), psi(g_i))]
-  with the critic phi, psi frozen (their parameters after the critic update);
+  with the critic phi, psi frozen (their parameters after the critic update),
+  f any of the critic's energies;
   maximising the energy of the policy's action is the objective of the
   policy-learning section;
 * the entropy coefficient: L_alpha = -mean_i [log alpha (log pi_i + H)] with
@@ -97,14 +98,8 @@ def actor_loss_and_grads(actor_layers, phi_layers, psi_layers, x_sg, x_g, obs_t,
     x_sa = np.concatenate([np.asarray(obs_t, np.float64), a], axis=1)
     phi, c_phi = C.mlp_forward(phi_layers, x_sa, w.activation, w.ln_eps)
     psi, _ = C.mlp_forward(psi_layers, x_g, w.activation, w.ln_eps)
-    if w.energy_function == "dot":
-        f = (phi * psi).sum(axis=1)
-        dphi = -psi / B                      # d(-mean f)/d phi
-    else:
-        diff = phi - psi
-        d = np.sqrt((diff * diff).sum(axis=1))
-        f = -d
-        dphi = np.where(d[:, None] > 0, diff / np.where(d > 0, d, 1.0)[:, None], 0.0) / B
+    f, df = C.pair_energy(phi, psi, w.energy_function)
+    dphi = -df / B                           # d(-mean f)/d phi
     loss = math.fsum((alpha * log_pi - f).tolist()) / B
     # through the frozen critic to the action input
     _, dx = C.mlp_backward(phi_layers, c_phi, dphi, w.activation)
@@ -133,8 +128,6 @@ def actor_loss_only(actor_layers, phi_layers, psi_layers, x_sg, x_g, obs_t, eps,
     x_sa = np.concatenate([np.asarray(obs_t, np.float64), a], axis=1)
     phi, _ = C.mlp_forward(phi_layers, x_sa, w.activation, w.ln_eps)
     psi, _ = C.mlp_forward(psi_layers, x_g, w.activation, w.ln_eps)
-    if w.energy_function == "dot":
-        f = (phi * psi).sum(axis=1)
-    else:
-        f = -np.sqrt(((phi - psi) ** 2).sum(axis=1))
+    # the loss alone evaluates f row by row from the energy definitions
+    f = np.array([C.energy_row(phi[b], psi[b:b + 1], w.energy_function)[0] for b in range(B)])
     return math.fsum((math.exp(log_alpha) * log_pi - f).tolist()) / B

@@ -150,6 +150,31 @@ def energy_row(phi_i, psi, kind: str):
     return -np.sqrt((diff * diff).sum(axis=1))
 
 
+def pair_energy(phi, psi, kind: str):
+    """f_b = energy(phi_b, psi_b) for matching rows b (the critic's diagonal),
+    and df_b / dphi_b."""
+    phi = np.asarray(phi, f64)
+    psi = np.asarray(psi, f64)
+    diff = phi - psi
+    if kind == "dot":
+        return (phi * psi).sum(axis=1), psi.copy()
+    if kind == "l2":
+        d = np.sqrt((diff * diff).sum(axis=1))
+        inv = np.where(d > 0.0, 1.0 / np.where(d > 0.0, d, 1.0), 0.0)
+        return -d, -diff * inv[:, None]
+    if kind == "l2sq":
+        return -(diff * diff).sum(axis=1), -2.0 * diff
+    if kind == "l1":
+        return -np.abs(diff).sum(axis=1), -np.sign(diff)
+    if kind == "cos":
+        u, nu = _unit(phi)
+        v, _ = _unit(psi)
+        f = (u * v).sum(axis=1)
+        iu = np.where(nu > 0.0, 1.0 / np.where(nu > 0.0, nu, 1.0), 0.0)
+        return f, (v - f[:, None] * u) * iu[:, None]
+    raise ValueError(kind)
+
+
 def energy_backward(phi, psi, F, G, kind: str):
     """Push dL/dF through the energy: returns (dphi, dpsi)."""
     phi = np.asarray(phi, f64)

@@ -62,8 +62,8 @@ def sigmoid(x):
 
 
 def contrastive_loss(F, loss: str, beta: float) -> Dict[str, object]:
-    """Loss parts: total, obj (the objective), fwd / bwd (InfoNCE directions
-    where they exist, else obj and 0), pen; and r, c, diag."""
+    """Loss parts: total, obj (the objective), fwd / bwd (the InfoNCE
+    directions mean(r - diag), mean(c - diag)), pen; and r, c, diag."""
     if loss in INFONCE:
         out = C.infonce_loss(F, loss, beta)
         out["obj"] = out["total"] - out["pen"]
@@ -95,11 +95,10 @@ def contrastive_loss(F, loss: str, beta: float) -> Dict[str, object]:
         obj = _fsum_mean(B * (dg - 1.0) ** 2 + ((F + 1.0) ** 2).sum(axis=1))
     else:
         raise ValueError(loss)
-    fwd, bwd = obj, 0.0
-    if loss == "bwd_infonce":
-        fwd, bwd = 0.0, obj
-    return {"total": obj + pen, "obj": obj, "fwd": fwd, "bwd": bwd, "pen": pen,
-            "r": r, "c": c, "diag": dg}
+    # fwd / bwd: the two InfoNCE directions at this F, reported beside any
+    # objective
+    return {"total": obj + pen, "obj": obj, "fwd": _fsum_mean(r - dg), "bwd": _fsum_mean(c - dg),
+            "pen": pen, "r": r, "c": c, "diag": dg}
 
 
 def contrastive_grad(F, r, c, loss: str, beta: float):

@@ -11,10 +11,11 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcrl.so")
 
-CRL_OK, CRL_EINVAL, CRL_EUNSUPPORTED, CRL_EHIP = 0, -1, -2, -3
+CRL_OK, CRL_EINVAL, CRL_EUNSUPPORTED, CRL_EHIP, CRL_ENONFINITE = 0, -1, -2, -3, -4
 ACT = {"relu": 0, "ln_swish": 1}
-ENERGY = {"dot": 0, "l2": 1}
-LOSS = {"fwd_infonce": 0, "symmetric_infonce": 1}
+ENERGY = {"dot": 0, "l2": 1, "cos": 2, "l2sq": 3, "l1": 4}
+LOSS = {"fwd_infonce": 0, "symmetric_infonce": 1, "bwd_infonce": 2, "flatnce_fwd": 3,
+        "flatnce_bwd": 4, "fb": 5, "dpo": 6, "ipo": 7, "sppo": 8}
 PREC = {"fp32": 0, "bf16": 1}
 LOGITS = {"materialised": 0, "fused": 1}
 WS = {"phi": 0, "psi": 1, "row_lse": 2, "col_lse": 3, "diag": 4, "dphi": 5,
@@ -57,6 +58,9 @@ SIGNATURES = {
     "crl_sample_relabel": (C.c_int, [P, P, P, I32, I32, U64, P, P, P, P, P, P]),
     "crl_critic_fwd": (C.c_int, [P, P, P, P, P, P, P, P]),
     "crl_critic_bwd": (C.c_int, [P, P, P, P, P, P, P, P]),
+    "crl_infonce_fwd": (C.c_int, [P, P, P, P, P, P]),
+    "crl_infonce_bwd": (C.c_int, [P, P, P, P, P, P, P]),
+    "crl_check_finite": (C.c_int, [P, P]),
     "crl_actor_step": (C.c_int, [P, P, P, P, P, P, P, P, P, U64, P, P, P, P, P, P]),
     "crl_adam_step": (C.c_int, [P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_double,
                                 C.c_double, P]),

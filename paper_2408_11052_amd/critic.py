@@ -206,6 +206,14 @@ class Critic:
         check(lib().crl_critic_bwd(self.ctx, _ptr(params), _ptr(params_bf16), _ptr(x_sa),
                                    _ptr(x_g), _ptr(ws), _ptr(grads), _stream(stream)))
 
+    def crl_infonce_fwd(self, phi, psi, ws, loss_out, stream=None):
+        check(lib().crl_infonce_fwd(self.ctx, _ptr(phi), _ptr(psi), _ptr(ws), _ptr(loss_out),
+                                    _stream(stream)))
+
+    def crl_infonce_bwd(self, phi, psi, ws, dphi, dpsi, stream=None):
+        check(lib().crl_infonce_bwd(self.ctx, _ptr(phi), _ptr(psi), _ptr(ws), _ptr(dphi),
+                                    _ptr(dpsi), _stream(stream)))
+
 
     def crl_actor_step(self, params, params_bf16, actor_params, actor_params_bf16, log_alpha,
                        x_sa, x_g, x_sg, seed: int, step, ws, actor_grads, alpha_grad,
@@ -221,6 +229,15 @@ def crl_adam_step(p, g, m, v, p_bf16, step, lr: float, b1: float = 0.9, b2: floa
                   eps: float = 1e-8, stream=None):
     check(lib().crl_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(p_bf16), p.numel(),
                               _ptr(step), lr, b1, b2, eps, _stream(stream)))
+
+
+def crl_check_finite(loss_out, stream=None) -> int:
+    """CRL_OK, or CRL_ENONFINITE when the loss or a row/column term of the
+    last forward into ``loss_out`` is not finite (synchronises the stream)."""
+    rc = lib().crl_check_finite(_ptr(loss_out), _stream(stream))
+    if rc not in (0, -4):
+        check(rc)
+    return rc
 
 
 def crl_counter_add(counter, inc: int = 1, stream=None):

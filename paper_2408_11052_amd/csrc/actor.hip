@@ -75,12 +75,16 @@ __global__ __launch_bounds__(256) void actor_head_fwd_kernel(
   if (lane == 0) logpi[b] = lp;
 }
 
-// One wavefront per sample: f_b = <phi_b, psi_b> or -||phi_b - psi_b||, and
-// the gradient of -mean_b f_b w.r.t. phi_b (-psi_b / B, or (phi_b - psi_b) /
-// (d_b B), 0 at d_b = 0), written in the GEMM storage type.
+// One wavefront per sample: the critic's diagonal energy f_b of the policy's
+// action and d(-mean_b f_b)/dphi_b (the critic is frozen), for each energy:
+//   dot   f = p.q                       -> -q / B
+//   L2    f = -|p - q|                  -> (p - q) / (|p - q| B)  (0 at p = q)
+//   cos   f = p.q / (|p| |q|)           -> -(q/|q| - f p/|p|) / (|p| B)
+//   L2sq  f = -|p - q|^2                -> 2 (p - q) / B
+//   L1    f = -sum |p - q|              -> sign(p - q) / B
 template <typename T>
 __global__ __launch_bounds__(256) void actor_energy_kernel(
-    const float* __restrict__ phi, const float* __restrict__ psi, int D, int l2,
+    const float* __restrict__ phi, const float* __restrict__ psi, int D, int energy,
     float* __restrict__ f, T* __restrict__ dphi, int B) {
   const int lane = threadIdx.x & 63;
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -89,21 +93,46 @@ __global__ __launch_bounds__(256) void actor_energy_kernel(
   const float* q = psi + (int64_t)b * D;
   T* d = dphi + (int64_t)b * D;
   const float invB = 1.f / (float)B;
-  float acc = 0.f;
+  float pq = 0.f, pp = 0.f, qq = 0.f, dd = 0.f, l1 = 0.f;
   for (int k = lane; k < D; k += 64) {
     const float x = p[k], y = q[k];
-    acc += l2 ? (x - y) * (x - y) : x * y;
+    pq += x * y;
+    pp += x * x;
+    qq += y * y;
+    dd += (x - y) * (x - y);
+    l1 += fabsf(x - y);
   }
-  acc = wave_sum(acc);
-  if (!l2) {
-    for (int k = lane; k < D; k += 64) d[k] = Store<T>::from_f(-q[k] * invB);
-    if (lane == 0) f[b] = acc;
-  } else {
-    const float dist = sqrtf(acc);
+  pq = wave_sum(pq);
+  pp = wave_sum(pp);
+  qq = wave_sum(qq);
+  dd = wave_sum(dd);
+  l1 = wave_sum(l1);
+  float fb;
+  if (energy == CRL_ENERGY_L2) {
+    const float dist = sqrtf(dd);
     const float s = dist > 0.f ? invB / dist : 0.f;
     for (int k = lane; k < D; k += 64) d[k] = Store<T>::from_f((p[k] - q[k]) * s);
-    if (lane == 0) f[b] = -dist;
+    fb = -dist;
+  } else if (energy == CRL_ENERGY_COS) {
+    const float np = sqrtf(pp), nq = sqrtf(qq);
+    const float ip = np > 0.f ? 1.f / np : 0.f, iq = nq > 0.f ? 1.f / nq : 0.f;
+    fb = pq * ip * iq;
+    for (int k = lane; k < D; k += 64)
+      d[k] = Store<T>::from_f(-(q[k] * iq - fb * p[k] * ip) * ip * invB);
+  } else if (energy == CRL_ENERGY_L2SQ) {
+    for (int k = lane; k < D; k += 64) d[k] = Store<T>::from_f(2.f * (p[k] - q[k]) * invB);
+    fb = -dd;
+  } else if (energy == CRL_ENERGY_L1) {
+    for (int k = lane; k < D; k += 64) {
+      const float dl = p[k] - q[k];
+      d[k] = Store<T>::from_f((dl > 0.f ? invB : (dl < 0.f ? -invB : 0.f)));
+    }
+    fb = -l1;
+  } else {
+    for (int k = lane; k < D; k += 64) d[k] = Store<T>::from_f(-q[k] * invB);
+    fb = pq;
   }
+  if (lane == 0) f[b] = fb;
 }
 
 // One wavefront per sample: the policy-output gradient
@@ -192,16 +221,16 @@ hipError_t launch_actor_head_fwd(const float* out, int ldo, int A, uint64_t seed
   return hipGetLastError();
 }
 
-hipError_t launch_actor_energy(const float* phi, const float* psi, int D, int l2, float* f,
+hipError_t launch_actor_energy(const float* phi, const float* psi, int D, int energy, float* f,
                                void* dphi, int B, bool bf16, hipStream_t s) {
   dim3 grid((B + 3) / 4), block(256);
   const double bytes = (double)B * (8.0 * D + (bf16 ? 2.0 : 4.0) * D + 4.0);
   if (bf16)
     CRL_TIMED("actor_energy_kernel", 2.0 * B * D, bytes, s,
-      actor_energy_kernel<bf16_t><<<grid, block, 0, s>>>(phi, psi, D, l2, f, (bf16_t*)dphi, B));
+      actor_energy_kernel<bf16_t><<<grid, block, 0, s>>>(phi, psi, D, energy, f, (bf16_t*)dphi, B));
   else
     CRL_TIMED("actor_energy_kernel", 2.0 * B * D, bytes, s,
-      actor_energy_kernel<float><<<grid, block, 0, s>>>(phi, psi, D, l2, f, (float*)dphi, B));
+      actor_energy_kernel<float><<<grid, block, 0, s>>>(phi, psi, D, energy, f, (float*)dphi, B));
   return hipGetLastError();
 }
 

@@ -80,7 +80,8 @@ struct Group {
 struct crl_ctx {
   crl_config cfg;
   int device;
-  bool bf16, ln, l2, sym, fused, actor;
+  bool bf16, ln, fused, actor;
+  int energy, loss;          // CRL_ENERGY_*, CRL_LOSS_*
   int B, H, D, L;            // batch, critic hidden width, repr dim, hidden layers
   int A, P;                  // action dim, padded policy-output width (actor only)
   int ld_sg;
@@ -96,6 +97,7 @@ struct crl_ctx {
   int64_t ws_bytes;
   int64_t splitk, splitk_floats;
   int64_t r, c, diag, nphi, npsi, logits, cpm, cps, rowsumH, colsumH, cpartB;
+  int64_t rowterm, rowaux, uphi, upsi;  // pairwise objectives; cosine unit rows
   int64_t phi_b, psi_b, row_m, row_s, col_m, col_s, dx_part, rs_part;
   int64_t xsa2, noise, logpi, fpol, dact;  // actor step
   int ldd;                                 // row stride of dact
@@ -121,10 +123,12 @@ int validate(const crl_config* c) {
     return fail(CRL_EINVAL, "repr_dim must be a multiple of 8 in [8, 1024]");
   if (c->activation != CRL_ACT_RELU && c->activation != CRL_ACT_LN_SWISH)
     return fail(CRL_EINVAL, "unknown activation %d", c->activation);
-  if (c->energy != CRL_ENERGY_DOT && c->energy != CRL_ENERGY_L2)
+  if (c->energy < CRL_ENERGY_DOT || c->energy > CRL_ENERGY_L1)
     return fail(CRL_EINVAL, "unknown energy %d", c->energy);
-  if (c->loss != CRL_LOSS_FWD && c->loss != CRL_LOSS_SYM)
+  if (c->loss < CRL_LOSS_FWD || c->loss > CRL_LOSS_SPPO)
     return fail(CRL_EINVAL, "unknown loss %d", c->loss);
+  if (c->energy == CRL_ENERGY_L1 && c->repr_dim > 256)
+    return fail(CRL_EUNSUPPORTED, "the L1 energy supports repr_dim <= 256");
   if (c->precision != CRL_PREC_FP32 && c->precision != CRL_PREC_BF16)
     return fail(CRL_EINVAL, "unknown precision %d", c->precision);
   if (c->logits != CRL_LOGITS_MATERIALISED && c->logits != CRL_LOGITS_FUSED)
@@ -134,6 +138,12 @@ int validate(const crl_config* c) {
       return fail(CRL_EUNSUPPORTED, "fused logits are implemented for BF16 tiles only");
     if (c->repr_dim != 32 && c->repr_dim != 64 && c->repr_dim != 128 && c->repr_dim != 256)
       return fail(CRL_EUNSUPPORTED, "fused logits need repr_dim in {32, 64, 128, 256}");
+    if (c->energy == CRL_ENERGY_L1)
+      return fail(CRL_EUNSUPPORTED, "the L1 energy is not a product: materialised logits only");
+    if (c->loss > CRL_LOSS_FLATNCE_BWD)
+      return fail(CRL_EUNSUPPORTED,
+                  "fused logits take the InfoNCE and FlatNCE objectives; the pairwise ones "
+                  "(FB, DPO, IPO, SPPO) need materialised logits");
   } else if (c->batch > 32768) {
     return fail(CRL_EUNSUPPORTED, "materialised logits are limited to batch <= 32768");
   }
@@ -441,6 +451,9 @@ void plan_workspace(crl_ctx* x) {
   x->diag = take(B * 4);
   x->nphi = take(B * 4);
   x->npsi = take(B * 4);
+  x->rowterm = take(B * 4);
+  x->rowaux = take(B * 4);
+  x->uphi = x->upsi = -1;
   x->logits = x->cpm = x->cps = x->rowsumH = x->colsumH = x->cpartB = -1;
   x->phi_b = x->psi_b = x->row_m = x->row_s = x->col_m = x->col_s = x->dx_part = x->rs_part = -1;
   if (!x->fused) {
@@ -452,10 +465,15 @@ void plan_workspace(crl_ctx* x) {
     x->rowsumH = take(B * 4);
     x->colsumH = take(B * 4);
     x->cpartB = take(((B + 127) / 128) * x->ldF * 4);
+    if (x->energy == CRL_ENERGY_COS) {
+      x->uphi = take(B * D * 4);
+      x->upsi = take(B * D * 4);
+    }
   } else {
     // the one-pass backward (D = 64) indexes its partials by 256-row blocks
-    const int S = D == 64 ? std::max(fused_splits(x->B), fused_bwd_splits(x->B))
-                          : fused_splits(x->B);
+    const int S = fused_bwd_one_pass(x->B, x->D)
+                      ? std::max(fused_splits(x->B), fused_bwd_splits(x->B))
+                      : fused_splits(x->B);
     const int nrb = (x->B + 63) / 64;
     x->phi_b = take(B * D * 2);
     x->psi_b = take(B * D * 2);
@@ -710,6 +728,144 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
   return CRL_OK;
 }
 
+// The critic matrix of phi and psi (FP32 [B][D]), its row and column
+// log-sum-exps and diagonal, and the loss parts, for the context's energy and
+// objective.  top (fused logits): the output layer's deferred split-K launch,
+// whose sum the prep kernel takes (phi and psi are then its outputs).
+int contrastive_fwd(crl_ctx* x, const float* phi, const float* psi, void* ws, float* loss_out,
+                    const GemmParams* top, hipStream_t s) {
+  const int B = x->B, D = x->D;
+  float* r = WF(ws, x->r);
+  float* c = WF(ws, x->c);
+  float* dg = WF(ws, x->diag);
+  float* term = WF(ws, x->rowterm);
+  if (!x->fused) {
+    float* F = WF(ws, x->logits);
+    if (x->energy == CRL_ENERGY_L1) {
+      CRL_HIP(launch_l1_energy(phi, psi, F, B, D, x->ldF, s), "L1 energy");
+    } else {
+      GemmParams P{};
+      P.count = 1;
+      GemmDesc& d = P.d[0];
+      d.A = phi; d.lda = D;
+      d.B = psi; d.ldb = D;
+      d.C = F; d.ldc = x->ldF;
+      d.M = B; d.N = B; d.K = D;
+      d.alpha = 1.f;
+      d.epi = EPI_NONE;
+      if (x->energy == CRL_ENERGY_COS) {
+        CRL_HIP(launch_unit_rows(phi, WF(ws, x->uphi), WF(ws, x->nphi), B, D, s), "unit rows");
+        CRL_HIP(launch_unit_rows(psi, WF(ws, x->upsi), WF(ws, x->npsi), B, D, s), "unit rows");
+        d.A = WF(ws, x->uphi);
+        d.B = WF(ws, x->upsi);
+      } else if (x->energy == CRL_ENERGY_L2 || x->energy == CRL_ENERGY_L2SQ) {
+        CRL_HIP(launch_sqnorm(phi, WF(ws, x->nphi), B, D, s), "norms");
+        CRL_HIP(launch_sqnorm(psi, WF(ws, x->npsi), B, D, s), "norms");
+        d.epi = x->energy == CRL_ENERGY_L2 ? EPI_L2 : EPI_L2SQ;
+        d.rowv = WF(ws, x->nphi);
+        d.colv = WF(ws, x->npsi);
+      }
+      plan_split_k(P, false, 512);
+      CRL_HIP(launch_gemm(P, false, LAY_KC, LAY_KC, false, s), "logits GEMM");
+    }
+    CRL_HIP(launch_row_obj(F, B, x->ldF, x->loss, r, dg, term, WF(ws, x->rowaux), s),
+            "row log-sum-exp and objective terms");
+    const int rc_ = std::min(x->rchunks, B);
+    CRL_HIP(launch_col_lse_partial(F, B, x->ldF, rc_, WF(ws, x->cpm), WF(ws, x->cps), s), "column LSE");
+    CRL_HIP(launch_lse_merge(WF(ws, x->cpm), WF(ws, x->cps), rc_, B, c, s), "column LSE merge");
+  } else {
+    FusedArgs a{};
+    a.phi = phi; a.psi = psi;
+    a.phi_b = reinterpret_cast<bf16_t*>(W(ws, x->phi_b));
+    a.psi_b = reinterpret_cast<bf16_t*>(W(ws, x->psi_b));
+    a.nphi = WF(ws, x->nphi); a.npsi = WF(ws, x->npsi);
+    a.row_m = WF(ws, x->row_m); a.row_s = WF(ws, x->row_s);
+    a.col_m = WF(ws, x->col_m); a.col_s = WF(ws, x->col_s);
+    a.r = r; a.c = c; a.diag = dg;
+    CRL_HIP(launch_fused_fwd(a, B, D, x->energy, (top && top->splits > 1) ? top : nullptr, s),
+            "fused InfoNCE forward");
+  }
+  CRL_HIP(launch_loss(r, c, dg, term, B, x->loss, x->cfg.logsumexp_penalty, loss_out, s), "loss");
+  return CRL_OK;
+}
+
+// dL/dphi and dL/dpsi (FP32) after contrastive_fwd on the same phi, psi and
+// ws; dphi_t / dpsi_t get storage-type copies (BF16 precision; FP32: they
+// must be dphi / dpsi themselves); bias: the fused reduction also writes the
+// critic output layer's bias partials.
+int contrastive_bwd(crl_ctx* x, const float* phi, const float* psi, void* ws, float* dphi,
+                    float* dpsi, void* dphi_t, void* dpsi_t, bool bias, hipStream_t s) {
+  const int B = x->B, D = x->D;
+  const float beta = x->cfg.logsumexp_penalty;
+  const float* r = WF(ws, x->r);
+  const float* c = WF(ws, x->c);
+  if (!x->fused) {
+    float* F = WF(ws, x->logits);
+    float* rsH = WF(ws, x->rowsumH);
+    const bool dist = x->energy == CRL_ENERGY_L2 || x->energy == CRL_ENERGY_L2SQ;
+    const bool cosine = x->energy == CRL_ENERGY_COS;
+    CRL_HIP(launch_grad_obj(F, B, x->ldF, r, c, WF(ws, x->diag), WF(ws, x->rowaux), x->loss,
+                            x->energy, beta, rsH, s), "objective gradient");
+    if (x->energy == CRL_ENERGY_L1) {
+      CRL_HIP(launch_l1_backward(phi, psi, F, x->ldF, 0, dphi, B, D, s), "L1 backward");
+      CRL_HIP(launch_l1_backward(psi, phi, F, x->ldF, 1, dpsi, B, D, s), "L1 backward");
+    } else {
+      float* splitk = WF(ws, x->splitk);
+      for (int side = 0; side < 2; ++side) {
+        // side 0: dphi = G psi (G as KC); side 1: dpsi = G^T phi (G as MC);
+        // the unit rows stand in for phi and psi with the cosine energy
+        const float* Y = side == 0 ? (cosine ? WF(ws, x->upsi) : psi)
+                                   : (cosine ? WF(ws, x->uphi) : phi);
+        GemmParams P{};
+        P.count = 1;
+        GemmDesc& d = P.d[0];
+        d.A = F; d.lda = x->ldF;
+        d.B = Y; d.ldb = D;
+        d.C = side == 0 ? dphi : dpsi; d.ldc = D;
+        d.M = B; d.N = D; d.K = B;
+        d.alpha = 1.f;
+        d.epi = EPI_NONE;
+        P.partial = splitk;
+        plan_split_k(P, false, 512);
+        P.partial_len = (int64_t)P.splits * B * D;
+        CRL_HIP(launch_gemm(P, false, side == 0 ? LAY_KC : LAY_MC, LAY_MC, false, s), "dphi/dpsi GEMM");
+      }
+      if (dist) {
+        CRL_HIP(launch_l2_fix(dphi, phi, rsH, B, D, s), "distance row term");
+        ColSumArgs ca{};
+        ca.X[0] = F; ca.out[0] = WF(ws, x->colsumH); ca.part[0] = WF(ws, x->cpartB);
+        CRL_HIP(launch_colsum(ca, 1, B, B, x->ldF, false, s), "distance column sums");
+        CRL_HIP(launch_l2_fix(dpsi, psi, WF(ws, x->colsumH), B, D, s), "distance column term");
+      }
+      if (cosine) {
+        CRL_HIP(launch_cos_fix(dphi, WF(ws, x->uphi), WF(ws, x->nphi), B, D, s), "cosine backward");
+        CRL_HIP(launch_cos_fix(dpsi, WF(ws, x->upsi), WF(ws, x->npsi), B, D, s), "cosine backward");
+      }
+    }
+    if (x->bf16) {
+      CRL_HIP(launch_cast_bf16(dphi, reinterpret_cast<bf16_t*>(dphi_t), (int64_t)B * D, s), "cast");
+      CRL_HIP(launch_cast_bf16(dpsi, reinterpret_cast<bf16_t*>(dpsi_t), (int64_t)B * D, s), "cast");
+    }
+  } else {
+    FusedArgs a{};
+    a.phi = phi; a.psi = psi;
+    a.phi_b = reinterpret_cast<bf16_t*>(W(ws, x->phi_b));
+    a.psi_b = reinterpret_cast<bf16_t*>(W(ws, x->psi_b));
+    a.nphi = WF(ws, x->nphi); a.npsi = WF(ws, x->npsi);
+    a.r = const_cast<float*>(r); a.c = const_cast<float*>(c);
+    a.dX_part = WF(ws, x->dx_part);
+    a.rs_part = WF(ws, x->rs_part);
+    a.dphi = dphi; a.dpsi = dpsi;
+    a.dphi_t = dphi_t;
+    a.dpsi_t = dpsi_t;
+    a.bias_part[0] = bias ? WF(ws, x->sl[0].bp[x->L]) : nullptr;
+    a.bias_part[1] = bias ? WF(ws, x->sl[1].bp[x->L]) : nullptr;
+    CRL_HIP(launch_fused_bwd(a, B, D, x->energy, x->loss, beta, x->bf16, s),
+            "fused InfoNCE backward");
+  }
+  return CRL_OK;
+}
+
 int upload(void** dst, const void* src, size_t bytes) {
   *dst = nullptr;
   if (bytes == 0) return CRL_OK;
@@ -748,8 +904,8 @@ CRL_API int crl_create(const crl_config* cfg, crl_ctx** out) {
   if (he != hipSuccess) { delete x; return hip_fail(he, "hipGetDevice"); }
   x->bf16 = cfg->precision == CRL_PREC_BF16;
   x->ln = cfg->activation == CRL_ACT_LN_SWISH;
-  x->l2 = cfg->energy == CRL_ENERGY_L2;
-  x->sym = cfg->loss == CRL_LOSS_SYM;
+  x->energy = cfg->energy;
+  x->loss = cfg->loss;
   x->fused = cfg->logits == CRL_LOGITS_FUSED;
   x->actor = cfg->actor_n_hidden > 0;
   x->B = cfg->batch;
@@ -905,7 +1061,6 @@ CRL_API int crl_critic_fwd(crl_ctx* x, const float* params, const uint16_t* para
     return fail(CRL_EINVAL, "buffers must be 16-byte aligned");
   CRL_TRY(check_device(x));
   hipStream_t s = (hipStream_t)stream;
-  const int B = x->B, D = x->D;
   const bf16_t* pb = reinterpret_cast<const bf16_t*>(params_bf16);
 
   NetCall nc[2] = {{0, x_sa, x->net[0].ld_in, params, pb, nullptr, nullptr, 0, 0, 0},
@@ -915,49 +1070,8 @@ CRL_API int crl_critic_fwd(crl_ctx* x, const float* params, const uint16_t* para
   GemmParams top{};
   CRL_TRY(mlp_forward(x, nc, 2, ws, s, x->fused ? &top : nullptr));
 
-  float* phi = WF(ws, x->sl[0].out);
-  float* psi = WF(ws, x->sl[1].out);
-  float* r = WF(ws, x->r);
-  float* c = WF(ws, x->c);
-  float* dg = WF(ws, x->diag);
-  if (!x->fused) {
-    float* F = WF(ws, x->logits);
-    GemmParams P{};
-    P.count = 1;
-    GemmDesc& d = P.d[0];
-    d.A = phi; d.lda = D;
-    d.B = psi; d.ldb = D;
-    d.C = F; d.ldc = x->ldF;
-    d.M = B; d.N = B; d.K = D;
-    d.alpha = 1.f;
-    d.epi = EPI_NONE;
-    if (x->l2) {
-      CRL_HIP(launch_sqnorm(phi, WF(ws, x->nphi), B, D, s), "norms");
-      CRL_HIP(launch_sqnorm(psi, WF(ws, x->npsi), B, D, s), "norms");
-      d.epi = EPI_L2;
-      d.rowv = WF(ws, x->nphi);
-      d.colv = WF(ws, x->npsi);
-    }
-    plan_split_k(P, false, 512);
-    CRL_HIP(launch_gemm(P, false, LAY_KC, LAY_KC, false, s), "logits GEMM");
-    CRL_HIP(launch_row_lse(F, B, x->ldF, r, dg, s), "row LSE");
-    const int rc_ = std::min(x->rchunks, B);
-    CRL_HIP(launch_col_lse_partial(F, B, x->ldF, rc_, WF(ws, x->cpm), WF(ws, x->cps), s), "column LSE");
-    CRL_HIP(launch_lse_merge(WF(ws, x->cpm), WF(ws, x->cps), rc_, B, c, s), "column LSE merge");
-  } else {
-    FusedArgs a{};
-    a.phi = phi; a.psi = psi;
-    a.phi_b = reinterpret_cast<bf16_t*>(W(ws, x->phi_b));
-    a.psi_b = reinterpret_cast<bf16_t*>(W(ws, x->psi_b));
-    a.nphi = WF(ws, x->nphi); a.npsi = WF(ws, x->npsi);
-    a.row_m = WF(ws, x->row_m); a.row_s = WF(ws, x->row_s);
-    a.col_m = WF(ws, x->col_m); a.col_s = WF(ws, x->col_s);
-    a.r = r; a.c = c; a.diag = dg;
-    CRL_HIP(launch_fused_fwd(a, B, D, x->l2, top.splits > 1 ? &top : nullptr, s),
-            "fused InfoNCE forward");
-  }
-  CRL_HIP(launch_loss(r, c, dg, B, x->sym, x->cfg.logsumexp_penalty, loss_out, s), "loss");
-  return CRL_OK;
+  return contrastive_fwd(x, WF(ws, x->sl[0].out), WF(ws, x->sl[1].out), ws, loss_out,
+                         x->fused ? &top : nullptr, s);
 }
 
 CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* params_bf16,
@@ -971,70 +1085,60 @@ CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* para
     return fail(CRL_EINVAL, "buffers must be 16-byte aligned");
   CRL_TRY(check_device(x));
   hipStream_t s = (hipStream_t)stream;
-  const int B = x->B, D = x->D;
-  const float beta = x->cfg.logsumexp_penalty;
   const bf16_t* pb = reinterpret_cast<const bf16_t*>(params_bf16);
-  float* phi = WF(ws, x->sl[0].out);
-  float* psi = WF(ws, x->sl[1].out);
-  float* r = WF(ws, x->r);
-  float* c = WF(ws, x->c);
+  const float* phi = WF(ws, x->sl[0].out);
+  const float* psi = WF(ws, x->sl[1].out);
   float* dphi = WF(ws, x->sl[0].dout);
   float* dpsi = WF(ws, x->sl[1].dout);
-  float* splitk = WF(ws, x->splitk);
 
-
-  // dL/dphi, dL/dpsi
-  if (!x->fused) {
-    float* F = WF(ws, x->logits);
-    float* rsH = WF(ws, x->rowsumH);
-    CRL_HIP(launch_grad_matrix(F, B, x->ldF, r, c, x->sym, beta, x->l2, rsH, s), "grad matrix");
-    for (int side = 0; side < 2; ++side) {
-      // side 0: dphi = G psi (G as KC); side 1: dpsi = G^T phi (G as MC)
-      GemmParams P{};
-      P.count = 1;
-      GemmDesc& d = P.d[0];
-      d.A = F; d.lda = x->ldF;
-      d.B = side == 0 ? psi : phi; d.ldb = D;
-      d.C = side == 0 ? dphi : dpsi; d.ldc = D;
-      d.M = B; d.N = D; d.K = B;
-      d.alpha = 1.f;
-      d.epi = EPI_NONE;
-      P.partial = splitk;
-      plan_split_k(P, false, 512);
-      P.partial_len = (int64_t)P.splits * B * D;
-      CRL_HIP(launch_gemm(P, false, side == 0 ? LAY_KC : LAY_MC, LAY_MC, false, s), "dphi/dpsi GEMM");
-    }
-    if (x->l2) {
-      CRL_HIP(launch_l2_fix(dphi, phi, rsH, B, D, s), "L2 row term");
-      ColSumArgs ca{};
-      ca.X[0] = F; ca.out[0] = WF(ws, x->colsumH); ca.part[0] = WF(ws, x->cpartB);
-      CRL_HIP(launch_colsum(ca, 1, B, B, x->ldF, false, s), "L2 column sums");
-      CRL_HIP(launch_l2_fix(dpsi, psi, WF(ws, x->colsumH), B, D, s), "L2 column term");
-    }
-    if (x->bf16) {
-      CRL_HIP(launch_cast_bf16(dphi, reinterpret_cast<bf16_t*>(W(ws, x->sl[0].dout_t)), (int64_t)B * D, s), "cast");
-      CRL_HIP(launch_cast_bf16(dpsi, reinterpret_cast<bf16_t*>(W(ws, x->sl[1].dout_t)), (int64_t)B * D, s), "cast");
-    }
-  } else {
-    FusedArgs a{};
-    a.phi = phi; a.psi = psi;
-    a.phi_b = reinterpret_cast<bf16_t*>(W(ws, x->phi_b));
-    a.psi_b = reinterpret_cast<bf16_t*>(W(ws, x->psi_b));
-    a.nphi = WF(ws, x->nphi); a.npsi = WF(ws, x->npsi);
-    a.r = r; a.c = c;
-    a.dX_part = WF(ws, x->dx_part);
-    a.rs_part = WF(ws, x->rs_part);
-    a.dphi = dphi; a.dpsi = dpsi;
-    a.dphi_t = W(ws, x->sl[0].dout_t);
-    a.dpsi_t = W(ws, x->sl[1].dout_t);
-    a.bias_part[0] = WF(ws, x->sl[0].bp[x->L]);
-    a.bias_part[1] = WF(ws, x->sl[1].bp[x->L]);
-    CRL_HIP(launch_fused_bwd(a, B, D, x->l2, x->sym, beta, x->bf16, s), "fused InfoNCE backward");
-  }
+  // dL/dphi, dL/dpsi, their storage-type copies and (fused) the output
+  // layer's bias partials
+  CRL_TRY(contrastive_bwd(x, phi, psi, ws, dphi, dpsi, W(ws, x->sl[0].dout_t),
+                          W(ws, x->sl[1].dout_t), true, s));
 
   NetCall nc[2] = {{0, x_sa, x->net[0].ld_in, params, pb, grads, nullptr, 0, 0, 0},
                    {1, x_g, x->net[1].ld_in, params, pb, grads, nullptr, 0, 0, 0}};
   return mlp_backward(x, nc, 2, ws, s, x->fused);
+}
+
+CRL_API int crl_infonce_fwd(crl_ctx* x, const float* phi, const float* psi, void* ws,
+                            float* loss_out, void* stream) {
+  if (!x) return fail(CRL_EINVAL, "NULL context");
+  if (!phi || !psi || !ws || !loss_out) return fail(CRL_EINVAL, "NULL buffer argument");
+  if (!aligned16(phi) || !aligned16(psi) || !aligned16(ws))
+    return fail(CRL_EINVAL, "phi, psi and ws must be 16-byte aligned");
+  CRL_TRY(check_device(x));
+  return contrastive_fwd(x, phi, psi, ws, loss_out, nullptr, (hipStream_t)stream);
+}
+
+CRL_API int crl_infonce_bwd(crl_ctx* x, const float* phi, const float* psi, void* ws,
+                            float* dphi, float* dpsi, void* stream) {
+  if (!x) return fail(CRL_EINVAL, "NULL context");
+  if (!phi || !psi || !ws || !dphi || !dpsi) return fail(CRL_EINVAL, "NULL buffer argument");
+  if (!aligned16(phi) || !aligned16(psi) || !aligned16(ws) || !aligned16(dphi) ||
+      !aligned16(dpsi))
+    return fail(CRL_EINVAL, "phi, psi, ws, dphi and dpsi must be 16-byte aligned");
+  CRL_TRY(check_device(x));
+  // the storage-type copies go to the workspace's own slots (FP32: dphi, dpsi)
+  void* dphi_t = x->bf16 ? W(ws, x->sl[0].dout_t) : (void*)dphi;
+  void* dpsi_t = x->bf16 ? W(ws, x->sl[1].dout_t) : (void*)dpsi;
+  return contrastive_bwd(x, phi, psi, ws, dphi, dpsi, dphi_t, dpsi_t, false, (hipStream_t)stream);
+}
+
+CRL_API int crl_check_finite(const float* loss_out, void* stream) {
+  if (!loss_out) return fail(CRL_EINVAL, "NULL loss_out");
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  CRL_HIP(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(CRL_EINVAL, "crl_check_finite synchronises and cannot run under graph capture");
+  float h[8];
+  CRL_HIP(hipMemcpyAsync(h, loss_out, sizeof(h), hipMemcpyDeviceToHost, s), "copy loss_out");
+  CRL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (!std::isfinite(h[0]) || h[6] != 0.f)
+    return fail(CRL_ENONFINITE, "non-finite loss (total %g, %g non-finite row/column terms)",
+                (double)h[0], (double)h[6]);
+  return CRL_OK;
 }
 
 CRL_API int crl_actor_step(crl_ctx* x, const float* params, const uint16_t* params_bf16,
@@ -1076,7 +1180,7 @@ CRL_API int crl_actor_step(crl_ctx* x, const float* params, const uint16_t* para
   NetCall crit[2] = {{0, xsa2, x->net[0].ld_in, params, pb, nullptr, nullptr, 0, 0, 0},
                      {1, x_g, x->net[1].ld_in, params, pb, nullptr, nullptr, 0, 0, 0}};
   CRL_TRY(mlp_forward(x, crit, 2, ws, s));
-  CRL_HIP(launch_actor_energy(WF(ws, x->sl[0].out), WF(ws, x->sl[1].out), x->D, x->l2, fpol,
+  CRL_HIP(launch_actor_energy(WF(ws, x->sl[0].out), WF(ws, x->sl[1].out), x->D, x->energy, fpol,
                               W(ws, x->sl[0].dout_t), B, x->bf16, s), "policy energy");
   // d(-mean f)/da' through phi (no parameter gradients)
   NetCall back = {0, xsa2, x->net[0].ld_in, params, pb, nullptr, dact, x->cfg.obs_dim, x->A, x->ldd};

@@ -64,7 +64,7 @@ static int lds_path_bn(const GemmParams& P) {
     const GemmDesc& d = P.d[g];
     if (d.K % lds::BK || P.k_chunk % lds::BK || d.N % 8) return 0;
     if (d.lda % 8 || d.ldb % 8 || d.ldc % 8) return 0;
-    if (d.epi == EPI_L2 || d.accumulate) return 0;
+    if (d.epi == EPI_L2 || d.epi == EPI_L2SQ || d.accumulate) return 0;
     if ((reinterpret_cast<uintptr_t>(d.A) | reinterpret_cast<uintptr_t>(d.B) |
          reinterpret_cast<uintptr_t>(d.C)) & 15u)
       return 0;

@@ -28,7 +28,8 @@ enum : int {
   EPI_BIAS = 1,      // v + bias[n]
   EPI_BIAS_RELU = 2, // max(v + bias[n], 0)
   EPI_MASK_POS = 3,  // aux(m,n) > 0 ? v : 0      (ReLU backward)
-  EPI_L2 = 4         // -sqrt(max(rowv[m] + colv[n] - 2 v, 0))
+  EPI_L2 = 4,        // -l2_dist(rowv[m], colv[n], v)
+  EPI_L2SQ = 5       // -max(rowv[m] + colv[n] - 2 v, 0)
 };
 
 struct GemmDesc {
@@ -431,7 +432,7 @@ void gemm_kernel(GemmParams P) {
       float bcol = 0.f, ccol = 0.f;
       if (!split && col < D.N) {
         if (D.epi == EPI_BIAS || D.epi == EPI_BIAS_RELU) bcol = D.bias[col];
-        if (D.epi == EPI_L2) ccol = D.colv[col];
+        if (D.epi == EPI_L2 || D.epi == EPI_L2SQ) ccol = D.colv[col];
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -441,10 +442,10 @@ void gemm_kernel(GemmParams P) {
           v *= D.alpha;
           if (D.epi == EPI_BIAS) v += bcol;
           else if (D.epi == EPI_BIAS_RELU) v = fmaxf(v + bcol, 0.f);
-          else if (D.epi == EPI_L2) {
+          else if (D.epi == EPI_L2 || D.epi == EPI_L2SQ) {
             const int row = m0 + rl;
             const float rv = row < D.M ? D.rowv[row] : 0.f;
-            v = -sqrtf(fmaxf(rv + ccol - 2.f * v, 0.f));
+            v = D.epi == EPI_L2 ? -l2_dist(rv, ccol, v) : -fmaxf(rv + ccol - 2.f * v, 0.f);
           }
         }
         Cs[rl * kLdc + cl] = v;

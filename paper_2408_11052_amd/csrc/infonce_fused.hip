@@ -10,19 +10,30 @@
 // Row pairs of all splits and column pairs of all row blocks are merged by
 // lse_merge_kernel; the loss is then a reduction over r, c and the diagonal.
 //
-// Backward: G_ij = dL/dF_ij = (1/B)[(Pr_ij - d_ij)(...)] is recomputed tile by
-// tile from r and c (never stored) and multiplied into the streamed operand
-// with a second MFMA:  dphi = G psi  (row pass)  and  dpsi = G^T phi (column
-// pass, the same kernel with the roles of phi and psi exchanged).  For the L2
-// energy H = G / d replaces G and the row sums of H give the
-// -(sum_j H_ij) phi_i term.  Each split writes its own partial, summed in a
-// fixed order afterwards (no atomics).
+// Backward: G_ij = dL/dF_ij = (1/B)[Pr_ij (wf + 2 beta r_i) - wf d_ij
+// + wb (Pc_ij - d_ij)] (wf, wb in {0, 1}: the row and column directions of
+// InfoNCE / FlatNCE) is recomputed tile by tile from r and c (never stored)
+// and multiplied into the streamed operand with a second MFMA:
+// dphi = G psi (row pass) and dpsi = G^T phi (column pass, the same kernel
+// with the roles of phi and psi exchanged).  For the L2 energy H = G / d
+// replaces G (H = 2 G without the root) and the row sums of H give the
+// -(sum_j H_ij) phi_i term.  The cosine energy runs as the dot product of
+// unit rows; the reduction then projects out the row's own direction and
+// divides by its norm.  Each split writes its own partial, summed in a fixed
+// order afterwards (no atomics).
 #include "internal.hpp"
 
 namespace crl {
 
 constexpr int kFRows = 64;   // rows per workgroup
 constexpr int kFCols = 64;   // columns per tile
+
+// Energy applied to a tile value v = <x_i, y_j> (x, y the BF16 rows, or the
+// BF16 unit rows for the cosine energy) with squared norms nx, ny.
+enum : int { kEnDot = 0, kEnL2 = 1, kEnL2sq = 2 };
+static int fused_energy(int energy) {
+  return energy == CRL_ENERGY_L2 ? kEnL2 : energy == CRL_ENERGY_L2SQ ? kEnL2sq : kEnDot;
+}
 
 // Column splits: enough workgroups for four waves per SIMD (1024 x 4 waves
 // over 1024 SIMDs), at most 16 partials per row to merge.
@@ -40,30 +51,45 @@ static inline int cols_per_split(int B, int S) {
   return (cps + kFCols - 1) / kFCols * kFCols;
 }
 
-// BF16 copies of phi, psi and the squared norms of the rounded rows.
-__global__ void fused_prep_kernel(FusedArgs a, int B, int D) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int which = blockIdx.y;
-  if (row >= B) return;
-  const float* X = which ? a.psi : a.phi;
-  bf16_t* Xb = which ? a.psi_b : a.phi_b;
-  float* nrm = which ? a.npsi : a.nphi;
+// BF16 copies of phi, psi and the squared norms of the rounded rows; for the
+// cosine energy (unit != 0) the BF16 copies are of the unit rows x / |x| and
+// the norm slot holds |x| (FP32).
+__device__ __forceinline__ void prep_row(float* X, bf16_t* Xb, float* nrm, int row, int D,
+                                         int lane, int unit) {
   float s = 0.f;
+  if (unit) {
+    for (int d = lane; d < D; d += 64) s += X[d] * X[d];
+    s = wave_sum(s);
+    const float n = sqrtf(s);
+    const float inv = n > 0.f ? 1.f / n : 0.f;
+    for (int d = lane; d < D; d += 64) Xb[d] = f2bf(X[d] * inv);
+    if (lane == 0) nrm[row] = n;
+    return;
+  }
   for (int d = lane; d < D; d += 64) {
-    bf16_t h = f2bf(X[(int64_t)row * D + d]);
-    Xb[(int64_t)row * D + d] = h;
-    float v = bf2f(h);
+    const bf16_t h = f2bf(X[d]);
+    Xb[d] = h;
+    const float v = bf2f(h);
     s += v * v;
   }
   s = wave_sum(s);
   if (lane == 0) nrm[row] = s;
 }
 
+__global__ void fused_prep_kernel(FusedArgs a, int B, int D, int unit) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int which = blockIdx.y;
+  if (row >= B) return;
+  const float* X = (which ? a.psi : a.phi) + (int64_t)row * D;
+  bf16_t* Xb = (which ? a.psi_b : a.phi_b) + (int64_t)row * D;
+  prep_row(const_cast<float*>(X), Xb, which ? a.npsi : a.nphi, row, D, lane, unit);
+}
+
 // The same from the output layer's split-K partials: phi / psi = sum of the
 // splits in order + bias (FP32, as the split-K reduction writes them), then
 // the BF16 copies and norms.
-__global__ void fused_prep_reduce_kernel(FusedArgs a, GemmParams P, int B, int D) {
+__global__ void fused_prep_reduce_kernel(FusedArgs a, GemmParams P, int B, int D, int unit) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int which = blockIdx.y;
@@ -72,21 +98,13 @@ __global__ void fused_prep_reduce_kernel(FusedArgs a, GemmParams P, int B, int D
   const int64_t MN = (int64_t)G.M * G.N;
   const float* __restrict__ src = P.partial + (int64_t)which * P.partial_len + (int64_t)row * D;
   float* X = reinterpret_cast<float*>(G.C) + (int64_t)row * G.ldc;
-  bf16_t* Xb = (which ? a.psi_b : a.phi_b) + (int64_t)row * D;
-  float* nrm = which ? a.npsi : a.nphi;
-  float s = 0.f;
   for (int d = lane; d < D; d += 64) {
     float v = 0.f;
     for (int k = 0; k < P.splits; ++k) v += src[k * MN + d];
-    v += G.bias[d];
-    X[d] = v;
-    const bf16_t h = f2bf(v);
-    Xb[d] = h;
-    const float f = bf2f(h);
-    s += f * f;
+    X[d] = v + G.bias[d];
   }
-  s = wave_sum(s);
-  if (lane == 0) nrm[row] = s;
+  prep_row(X, (which ? a.psi_b : a.phi_b) + (int64_t)row * D, which ? a.npsi : a.nphi, row, D,
+           lane, unit);
 }
 
 // A 64-row tile of Y [B][D] (BF16) moves global -> registers -> LDS.  Each
@@ -122,8 +140,9 @@ __device__ __forceinline__ void tile_store_rows(bf16_t* __restrict__ Ys, const T
   }
 }
 
-template <int KS, int L2>
+template <int KS, int EN>
 __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, int cps) {
+  constexpr bool L2 = EN != kEnDot;
   constexpr int D = KS * 32;
   constexpr int LDY = D + 8;
   __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDY];
@@ -217,7 +236,8 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         float v = acc[jb][r];
-        if (L2) v = -sqrtf(fmaxf(nx[r] + ny - 2.f * v, 0.f));
+        if (EN == kEnL2) v = -l2_dist(nx[r], ny, v);
+        if (EN == kEnL2sq) v = -fmaxf(nx[r] + ny - 2.f * v, 0.f);
         f[jb][r] = (cv && rvalid[r]) ? v : -INFINITY;
         const int row = row_base + 4 * g + r;
         if (cv && rvalid[r] && row == col) a.diag[row] = v;
@@ -289,9 +309,10 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
 // transpose read (no transposed copy of the tile is kept).  The tile's
 // column values (the other side's LSE, its penalty factor, |y|^2) are
 // fetched together with the tile, one tile ahead.
-template <int KS, int L2, int TRANS>
+template <int KS, int EN, int TRANS>
 __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, int cps,
-                                                          float beta, int symmetric) {
+                                                          float beta, float wf, float wb) {
+  constexpr bool L2 = EN != kEnDot;
   constexpr int D = KS * 32;
   constexpr int LDY = D + 8;
   constexpr int LDT = kFCols + 8;
@@ -386,22 +407,22 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
         const int row = row_base + 4 * g + r;
         float v = acc[jb][r];
         float d = 0.f;
-        if (L2) { d = sqrtf(fmaxf(nx[r] + cvals.ny[jb] - 2.f * v, 0.f)); v = -d; }
+        if (EN == kEnL2) { d = l2_dist(nx[r], cvals.ny[jb], v); v = -d; }
+        if (EN == kEnL2sq) v = -fmaxf(nx[r] + cvals.ny[jb] - 2.f * v, 0.f);
         float gv = 0.f;
         if (cv && rvalid[r]) {
           const float dl = (row == col) ? 1.f : 0.f;
-          // rows-side and columns-side softmax terms
+          // the softmax over this pass's own rows (pa) and over its columns (pb)
           const float pa = __expf(v - lse_a[r]);
           const float pb = __expf(v - cvals.lse[jb]);
           if (TRANS == 0) {
-            gv = pa * (1.f + beta2 * lse_a[r]) - dl;
-            if (symmetric) gv += pb - dl;
+            gv = pa * (wf + beta2 * lse_a[r]) - wf * dl + wb * (pb - dl);
           } else {
-            gv = pb * (1.f + beta2 * cvals.lse[jb]) - dl;
-            if (symmetric) gv += pa - dl;
+            gv = pb * (wf + beta2 * cvals.lse[jb]) - wf * dl + wb * (pa - dl);
           }
           gv *= inv;
-          if (L2) gv = d > 0.f ? gv * __builtin_amdgcn_rcpf(d) : 0.f;
+          if (EN == kEnL2) gv = d > 0.f ? gv * __builtin_amdgcn_rcpf(d) : 0.f;
+          if (EN == kEnL2sq) gv *= 2.f;
         }
         hsum[r] += gv;
         Gs[wave][(4 * g + r) * LDT + jb * 16 + r16] = f2bf(gv);
@@ -464,9 +485,10 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
 constexpr int kBRows = 256;  // rows (and columns) per workgroup of the one-pass backward
 int fused_bwd_splits(int B) { return (B + kBRows - 1) / kBRows; }
 
-template <int L2>
+template <int EN>
 __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int B, float beta,
-                                                               int symmetric) {
+                                                               float wf, float wb) {
+  constexpr bool L2 = EN != kEnDot;
   constexpr int D = 64, KS = 2, NB = 4;
   constexpr int LDX = D + 8;       // phi / psi rows in LDS (144 B)
   constexpr int LDG = kFCols + 8;  // G rows in LDS
@@ -561,14 +583,16 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
         const int row = row_base + 4 * g + r;
         float v = acc[jb][r];
         float d = 0.f;
-        if (L2) { d = sqrtf(fmaxf(nx[r] + ny[jb] - 2.f * v, 0.f)); v = -d; }
+        if (EN == kEnL2) { d = l2_dist(nx[r], ny[jb], v); v = -d; }
+        if (EN == kEnL2sq) v = -fmaxf(nx[r] + ny[jb] - 2.f * v, 0.f);
         float gv = 0.f;
         if (cp[jb] != 0.f && rvalid[r]) {
           const float dl = (row == col) ? 1.f : 0.f;
-          gv = __expf(v - lse_r[r]) * (1.f + pen_r[r]) - dl;
-          if (symmetric) gv += __expf(v - cl[jb]) - dl;
+          gv = __expf(v - lse_r[r]) * (wf + pen_r[r]) - wf * dl;
+          if (wb != 0.f) gv += __expf(v - cl[jb]) - dl;
           gv *= inv;
-          if (L2) gv = d > 0.f ? gv * __builtin_amdgcn_rcpf(d) : 0.f;
+          if (EN == kEnL2) gv = d > 0.f ? gv * __builtin_amdgcn_rcpf(d) : 0.f;
+          if (EN == kEnL2sq) gv *= 2.f;
         }
         hrow[r] += gv;
         hcol[jb] += gv;
@@ -663,12 +687,13 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
 }
 
 // dphi and dpsi (blockIdx.y) from the S split partials:
-//   dX = sum_s part[s]  (- (sum_s rs[s]) * X_bf16 for L2),
+//   dX = sum_s part[s]  (- (sum_s rs[s]) * X_bf16 for the distance energies;
+//   for the cosine energy, with U the BF16 unit rows: (dX - (dX . U) U) / |X|),
 // FP32 and storage copies, one element per thread; with bias_part set, also
 // the column sums of each block's 256 / D rows (the output layer's
-// bias-gradient partials).
+// bias-gradient partials).  en: 0 dot, 1 distance, 2 cosine.
 template <typename OutT, int D>
-__global__ __launch_bounds__(256) void bwd_reduce_kernel(FusedArgs a, int S, int B, int l2) {
+__global__ __launch_bounds__(256) void bwd_reduce_kernel(FusedArgs a, int S, int B, int en) {
   constexpr int TR = 256 / D;  // rows per block
   __shared__ float red[256];
   const int side = blockIdx.y;
@@ -676,24 +701,41 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(FusedArgs a, int S, int
   const int row = blockIdx.x * TR + threadIdx.x / D;
   const int64_t n = (int64_t)B * D;
   const int64_t idx = (int64_t)row * D + c;
+  const bf16_t* __restrict__ Xb = side ? a.psi_b : a.phi_b;
   float s = 0.f;
   if (row < B) {
     const float* __restrict__ part = a.dX_part + (int64_t)side * S * n + idx;
 #pragma unroll 4
     for (int i = 0; i < S; ++i) s += part[i * n];
-    if (l2) {
+    if (en == 1) {
       const float* __restrict__ rs = a.rs_part + (int64_t)side * S * B + row;
-      const bf16_t* __restrict__ Xb = side ? a.psi_b : a.phi_b;
       float h = 0.f;
       for (int i = 0; i < S; ++i) h += rs[(int64_t)i * B];
       s -= h * bf2f(Xb[idx]);
     }
+  }
+  if (en == 2) {  // the row's dot product with its unit vector, a tree over its D threads
+    const float u = row < B ? bf2f(Xb[idx]) : 0.f;
+    red[threadIdx.x] = s * u;
+    __syncthreads();
+    for (int o = D / 2; o > 0; o >>= 1) {
+      if (c < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    const float dot = red[threadIdx.x - c];
+    __syncthreads();
+    if (row < B) {
+      const float nr = (side ? a.npsi : a.nphi)[row];
+      s = nr > 0.f ? (s - dot * u) / nr : 0.f;
+    }
+  }
+  if (row < B) {
     (side ? a.dpsi : a.dphi)[idx] = s;
     reinterpret_cast<OutT*>(side ? a.dpsi_t : a.dphi_t)[idx] = Store<OutT>::from_f(s);
   }
   float* bias = a.bias_part[side];
   if (bias == nullptr) return;
-  red[threadIdx.x] = s;  // rows past B add 0
+  red[threadIdx.x] = row < B ? s : 0.f;  // rows past B add 0
   __syncthreads();
   if (threadIdx.x < D) {
     float t = red[threadIdx.x];
@@ -714,16 +756,19 @@ int fused_bias_chunks(int B, int D) { return (int)(((int64_t)B * D + 255) / 256)
     default: return hipErrorInvalidValue;                   \
   }
 
-// Workgroups of the forward kernel for (D, l2) that the device holds at once
-// (its register and LDS use decide how many fit on a CU), or 0 if unknown.
-static int fwd_resident_wgs(int D, int l2) {
+// Workgroups of the forward kernel for (D, energy) that the device holds at
+// once (its register and LDS use decide how many fit on a CU), or 0 if unknown.
+static int fwd_resident_wgs(int D, int en) {
   const void* k = nullptr;
-#define CRL_FWD_PTR(KS_, L2_) k = reinterpret_cast<const void*>(&infonce_fwd_kernel<KS_, L2_>)
+#define CRL_FWD_PTR(KS_)                                                           \
+  k = en == kEnL2 ? reinterpret_cast<const void*>(&infonce_fwd_kernel<KS_, kEnL2>)   \
+    : en == kEnL2sq ? reinterpret_cast<const void*>(&infonce_fwd_kernel<KS_, kEnL2sq>) \
+                    : reinterpret_cast<const void*>(&infonce_fwd_kernel<KS_, kEnDot>)
   switch (D) {
-    case 32:  if (l2) CRL_FWD_PTR(1, 1); else CRL_FWD_PTR(1, 0); break;
-    case 64:  if (l2) CRL_FWD_PTR(2, 1); else CRL_FWD_PTR(2, 0); break;
-    case 128: if (l2) CRL_FWD_PTR(4, 1); else CRL_FWD_PTR(4, 0); break;
-    case 256: if (l2) CRL_FWD_PTR(8, 1); else CRL_FWD_PTR(8, 0); break;
+    case 32: CRL_FWD_PTR(1); break;
+    case 64: CRL_FWD_PTR(2); break;
+    case 128: CRL_FWD_PTR(4); break;
+    case 256: CRL_FWD_PTR(8); break;
     default: return 0;
   }
 #undef CRL_FWD_PTR
@@ -738,35 +783,51 @@ static int fwd_resident_wgs(int D, int l2) {
 // Column splits of the forward: fused_splits(B), or fewer where the kernel's
 // resident capacity takes the launch in one round that way (D = 256 holds
 // three workgroups per CU: 3 splits at B=16384 run in one round, 4 in two).
-static int fused_fwd_splits(int B, int D, int l2) {
+// The count returned is that of the non-empty splits once each split's
+// columns are rounded up to whole 64-column tiles.
+static int fused_fwd_splits(int B, int D, int en) {
   const int S = fused_splits(B);
   const int nrb = (B + kFRows - 1) / kFRows;
-  const int cap = fwd_resident_wgs(D, l2);
+  const int cap = fwd_resident_wgs(D, en);
   if (cap <= 0 || (int64_t)nrb * S <= cap) return S;
   const int S1 = std::max(1, cap / nrb);
   // one round of S1 splits against ceil(nrb S / cap) rounds of S splits
   const int64_t rounds = ((int64_t)nrb * S + cap - 1) / cap;
-  return (int64_t)S1 * rounds > S ? S1 : S;
+  if ((int64_t)S1 * rounds <= S) return S;
+  const int cps = cols_per_split(B, S1);
+  return (B + cps - 1) / cps;
 }
 
-hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, const GemmParams* top,
+#define CRL_EN_DISPATCH(EN_, BODY)                                  \
+  switch (en) {                                                      \
+    case kEnL2:   { constexpr int EN_ = kEnL2; BODY; } break;        \
+    case kEnL2sq: { constexpr int EN_ = kEnL2sq; BODY; } break;      \
+    default:      { constexpr int EN_ = kEnDot; BODY; } break;       \
+  }
+
+static const char* fused_name(const char* const names[3], int en) { return names[en]; }
+
+hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int energy, const GemmParams* top,
                             hipStream_t s) {
+  const int en = fused_energy(energy);
+  const int unit = energy == CRL_ENERGY_COS;
   if (top)
     CRL_TIMED("fused_prep_reduce_kernel", 0.0, 2.0 * B * D * (4.0 * top->splits + 10.0), s,
-              fused_prep_reduce_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, *top, B, D));
+              fused_prep_reduce_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, *top, B, D, unit));
   else
     CRL_TIMED("fused_prep_kernel", 0.0, 2.0 * B * D * 6.0, s,
-              fused_prep_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, B, D));
+              fused_prep_kernel<<<dim3((B + 3) / 4, 2), 256, 0, s>>>(a, B, D, unit));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int S = fused_fwd_splits(B, D, l2), cps = cols_per_split(B, S);
+  const int S = fused_fwd_splits(B, D, en), cps = cols_per_split(B, S);
   const int nrb = (B + kFRows - 1) / kFRows;
   dim3 grid(nrb, S);
   const double fw_flops = 2.0 * B * B * D;
   const double fw_bytes = 2.0 * 2.0 * B * D + 4.0 * 2.0 * ((double)S * B + (double)nrb * B);
-  KTimer t = timing_begin(l2 ? "infonce_fwd_kernel<l2>" : "infonce_fwd_kernel<dot>", fw_flops, fw_bytes, s);
-  if (l2) { CRL_FUSED_DISPATCH(KS, (infonce_fwd_kernel<KS, 1><<<grid, 256, 0, s>>>(a, B, cps))) }
-  else    { CRL_FUSED_DISPATCH(KS, (infonce_fwd_kernel<KS, 0><<<grid, 256, 0, s>>>(a, B, cps))) }
+  static const char* const names[3] = {"infonce_fwd_kernel<dot>", "infonce_fwd_kernel<l2>",
+                                       "infonce_fwd_kernel<l2sq>"};
+  KTimer t = timing_begin(fused_name(names, en), fw_flops, fw_bytes, s);
+  CRL_EN_DISPATCH(EN, CRL_FUSED_DISPATCH(KS, (infonce_fwd_kernel<KS, EN><<<grid, 256, 0, s>>>(a, B, cps))))
   timing_end(t);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -776,19 +837,32 @@ hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, const Gemm
   return launch_lse_merge(m, 2, B, s);
 }
 
-hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmetric,
-                            float beta, bool out_bf16, hipStream_t s) {
+// The one-pass backward (D = 64) writes ceil(B / 256) partials per row of
+// dphi and of dpsi, B x 64 floats each; above kBothMaxSplits partials the
+// row and column passes run instead, whose partial count is bounded by
+// fused_splits (at most 16).
+constexpr int kBothMaxSplits = 16;
+bool fused_bwd_one_pass(int B, int D) { return D == 64 && fused_bwd_splits(B) <= kBothMaxSplits; }
+
+hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int energy, int loss, float beta,
+                            bool out_bf16, hipStream_t s) {
+  const int en = fused_energy(energy);
+  const float wf = (loss == CRL_LOSS_FWD || loss == CRL_LOSS_SYM || loss == CRL_LOSS_FLATNCE_FWD) ? 1.f : 0.f;
+  const float wb = (loss == CRL_LOSS_SYM || loss == CRL_LOSS_BWD || loss == CRL_LOSS_FLATNCE_BWD) ? 1.f : 0.f;
   const int64_t n = (int64_t)B * D;
+  const bool one = fused_bwd_one_pass(B, D);
   int S = fused_splits(B);
-  if (D == 64) {  // one pass for both gradients
+  if (one) {  // one pass for both gradients
     S = fused_bwd_splits(B);
     const dim3 grid(S, S);
     const double flops = 4.0 * B * B * D;  // G . psi and G^T . phi; the tile recompute is not counted
     const double bytes = 2.0 * 2.0 * B * D + 4.0 * 2.0 * B + 2.0 * 4.0 * (double)S * B * (D + 1.0);
-    if (l2) CRL_TIMED("infonce_bwd_both_kernel<l2>", flops, bytes, s,
-                      infonce_bwd_both_kernel<1><<<grid, 1024, 0, s>>>(a, B, beta, symmetric));
-    else    CRL_TIMED("infonce_bwd_both_kernel<dot>", flops, bytes, s,
-                      infonce_bwd_both_kernel<0><<<grid, 1024, 0, s>>>(a, B, beta, symmetric));
+    static const char* const names[3] = {"infonce_bwd_both_kernel<dot>",
+                                         "infonce_bwd_both_kernel<l2>",
+                                         "infonce_bwd_both_kernel<l2sq>"};
+    KTimer t = timing_begin(fused_name(names, en), flops, bytes, s);
+    CRL_EN_DISPATCH(EN, (infonce_bwd_both_kernel<EN><<<grid, 1024, 0, s>>>(a, B, beta, wf, wb)))
+    timing_end(t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -797,30 +871,29 @@ hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmet
   dim3 grid(nrb, S);
   const double bw_flops = 2.0 * B * B * D;  // G . Y per pass; the tile recompute is not counted
   const double bw_bytes = 2.0 * 2.0 * B * D + 4.0 * 2.0 * B + 4.0 * (double)S * B * (D + 1.0);
-  for (int pass = 0; pass < (D == 64 ? 0 : 2); ++pass) {
+  for (int pass = 0; pass < (one ? 0 : 2); ++pass) {
     KTimer t = timing_begin(pass ? "infonce_bwd_kernel<cols>" : "infonce_bwd_kernel<rows>",
                             bw_flops, bw_bytes, s);
     if (pass == 0) {
-      if (l2) { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 1, 0><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
-      else    { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 0, 0><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
+      CRL_EN_DISPATCH(EN, CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, EN, 0><<<grid, 256, 0, s>>>(a, B, cps, beta, wf, wb))))
     } else {
-      if (l2) { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 1, 1><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
-      else    { CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, 0, 1><<<grid, 256, 0, s>>>(a, B, cps, beta, symmetric))) }
+      CRL_EN_DISPATCH(EN, CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, EN, 1><<<grid, 256, 0, s>>>(a, B, cps, beta, wf, wb))))
     }
     timing_end(t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  const int ren = energy == CRL_ENERGY_COS ? 2 : (en != kEnDot ? 1 : 0);
   const dim3 rgrid(fused_bias_chunks(B, D), 2);
   const double rb = 2.0 * (4.0 * (double)n * (S + 1.0) + (double)n * (out_bf16 ? 2 : 4));
   if (out_bf16) {
     CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
-              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<bf16_t, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, l2))));
+              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<bf16_t, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, ren))));
   } else {
     CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
-              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<float, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, l2))));
+              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<float, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, ren))));
   }
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 }  // namespace crl

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "crl.h"
 #include "gemm.hpp"
 
 namespace crl {
@@ -125,8 +126,7 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, bf16_t* pb,
                        int64_t n, const int64_t* step, const AdamCoef& c, hipStream_t s);
 hipError_t launch_counter_add(int64_t* c, int64_t inc, hipStream_t s);
 
-// materialised InfoNCE (FP32 B x B in the workspace, row stride ld)
-hipError_t launch_row_lse(const float* F, int B, int ld, float* r, float* diag, hipStream_t s);
+// materialised critic matrix (FP32 B x B in the workspace, row stride ld)
 hipError_t launch_col_lse_partial(const float* F, int B, int ld, int rchunks, float* pm,
                                   float* ps, hipStream_t s);
 // log-sum-exp of (max, sum) partials [nparts][B] per column j, for `count`
@@ -140,13 +140,27 @@ struct LseMergeArgs {
 hipError_t launch_lse_merge(const LseMergeArgs& a, int count, int B, hipStream_t s);
 hipError_t launch_lse_merge(const float* pm, const float* ps, int nparts, int B,
                             float* out, hipStream_t s);
-hipError_t launch_loss(const float* r, const float* c, const float* diag, int B,
-                       int symmetric, float beta, float* loss_out, hipStream_t s);
-hipError_t launch_grad_matrix(float* F, int B, int ld, const float* r, const float* c,
-                              int symmetric, float beta, int l2, float* rowsum,
-                              hipStream_t s);
+// loss_out[8] from r, c, diag and (pairwise objectives) the per-row terms
+hipError_t launch_loss(const float* r, const float* c, const float* diag, const float* term,
+                       int B, int loss, float beta, float* loss_out, hipStream_t s);
 hipError_t launch_l2_fix(float* dX, const float* X, const float* rs, int B, int D,
                          hipStream_t s);
+
+// objectives.hip: energies and objectives on the materialised matrix
+hipError_t launch_unit_rows(const float* X, float* U, float* nrm, int B, int D, hipStream_t s);
+hipError_t launch_l1_energy(const float* phi, const float* psi, float* F, int B, int D, int ld,
+                            hipStream_t s);
+hipError_t launch_l1_backward(const float* X, const float* Y, const float* G, int ldg, int trans,
+                              float* dX, int B, int D, hipStream_t s);
+// r, diag, and for the pairwise objectives the row terms and the sums that
+// form dL/dF_ii
+hipError_t launch_row_obj(const float* F, int B, int ld, int loss, float* r, float* diag,
+                          float* term, float* aux, hipStream_t s);
+// in place F -> dL/dF (or H for the distance energies, with its row sums)
+hipError_t launch_grad_obj(float* F, int B, int ld, const float* r, const float* c,
+                           const float* diag, const float* aux, int loss, int energy, float beta,
+                           float* rowsum, hipStream_t s);
+hipError_t launch_cos_fix(float* dX, const float* U, const float* nrm, int B, int D, hipStream_t s);
 
 // fused InfoNCE (BF16 tiles, FP32 online LSE)
 struct FusedArgs {
@@ -177,17 +191,23 @@ int fused_bias_chunks(int B, int D);  // row blocks of the backward reduction
 // top: the output layer's deferred split-K launch (phi = d[0].C, psi =
 // d[1].C), summed with its bias by the prep kernel; nullptr: phi and psi are
 // final already.
-hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int l2, const GemmParams* top,
+// energy: CRL_ENERGY_DOT, _L2, _COS (unit rows, dot product) or _L2SQ
+hipError_t launch_fused_fwd(const FusedArgs& a, int B, int D, int energy, const GemmParams* top,
                             hipStream_t s);
-hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int l2, int symmetric,
-                            float beta, bool out_bf16, hipStream_t s);
+// loss: CRL_LOSS_FWD, _SYM, _BWD, _FLATNCE_FWD or _FLATNCE_BWD
+hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int energy, int loss, float beta,
+                            bool out_bf16, hipStream_t s);
+// whether the backward takes the one-pass kernel (D = 64, at most 16 row
+// blocks of 256), whose partials are indexed by 256-row blocks
+bool fused_bwd_one_pass(int B, int D);
 
 // actor.hip: the policy step's elementwise/row kernels
 hipError_t launch_actor_head_fwd(const float* out, int ldo, int A, uint64_t seed,
                                  const int64_t* step, const void* x_sa, void* x_sa2, int ld,
                                  int d_s, float* eps, float* logpi, int B, bool bf16,
                                  hipStream_t s);
-hipError_t launch_actor_energy(const float* phi, const float* psi, int D, int l2, float* f,
+// f_b = energy(phi_b, psi_b) (CRL_ENERGY_*) and d(-mean f)/dphi
+hipError_t launch_actor_energy(const float* phi, const float* psi, int D, int energy, float* f,
                                void* dphi, int B, bool bf16, hipStream_t s);
 hipError_t launch_actor_head_bwd(const float* out, int ldo, int A, const float* eps,
                                  const float* da, int ldd, const float* log_alpha, float* dout,

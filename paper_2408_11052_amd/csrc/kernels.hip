@@ -698,27 +698,6 @@ hipError_t launch_counter_add(int64_t* c, int64_t inc, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // materialised InfoNCE: F [B][B] FP32 in memory
 // ---------------------------------------------------------------------------
-// r_i = log sum_j exp(F_ij) (max-subtracted, two passes over the row); F_ii.
-__global__ __launch_bounds__(256) void row_lse_kernel(const float* __restrict__ F, int B, int ld,
-                                                      float* __restrict__ r, float* __restrict__ diag) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= B) return;
-  const float* row = F + (int64_t)i * ld;
-  float m = -INFINITY;
-  for (int j = lane; j < B; j += 64) m = fmaxf(m, row[j]);
-  m = wave_max(m);
-  float s = 0.f;
-  for (int j = lane; j < B; j += 64) s += __expf(row[j] - m);
-  s = wave_sum(s);
-  if (lane == 0) { r[i] = m + __logf(s); diag[i] = row[i]; }
-}
-hipError_t launch_row_lse(const float* F, int B, int ld, float* r, float* diag, hipStream_t s) {
-  CRL_TIMED("row_lse_kernel", 0.0, 4.0 * B * B, s,
-            row_lse_kernel<<<(B + 3) / 4, 256, 0, s>>>(F, B, ld, r, diag));
-  return hipGetLastError();
-}
-
 // per (row chunk, column) online (max, sum) over the chunk's rows
 __global__ void col_lse_partial_kernel(const float* __restrict__ F, int B, int ld, int rows_per,
                                        float* __restrict__ pm, float* __restrict__ ps) {
@@ -786,90 +765,67 @@ hipError_t launch_lse_merge(const float* pm, const float* ps, int nparts, int B,
   return launch_lse_merge(a, 1, B, s);
 }
 
-// Loss from r, c, diag in one workgroup: per-thread Kahan sums, then an
-// ordered pairwise tree over the threads (deterministic).
+// Loss from r, c, diag (and the per-row objective terms of the pairwise
+// objectives) in one workgroup: per-thread Kahan sums, then an ordered
+// pairwise tree over the threads (deterministic).
+//   loss_out = {L_obj + L_pen, mean(r - diag), mean(c - diag), L_pen,
+//               mean r, mean c, #non-finite rows, L_obj}
+// with L_obj the objective `loss` (CRL_LOSS_*): the two InfoNCE directions,
+// their sum, FlatNCE (exp(x - x) per row, x = r - diag or c - diag), or the
+// mean of term[] (Forward-Backward, DPO, IPO, SPPO).
 __global__ __launch_bounds__(1024) void loss_kernel(const float* __restrict__ r,
                                                     const float* __restrict__ c,
-                                                    const float* __restrict__ diag, int B,
-                                                    int symmetric, float beta,
+                                                    const float* __restrict__ diag,
+                                                    const float* __restrict__ term, int B,
+                                                    int loss, float beta,
                                                     float* __restrict__ loss_out) {
-  __shared__ float sh[6][1024];
+  __shared__ float sh[7][1024];
   float acc[6] = {0, 0, 0, 0, 0, 0}, cmp[6] = {0, 0, 0, 0, 0, 0};
   float bad = 0.f;
+  const bool pairwise = loss >= CRL_LOSS_FB;
   for (int i = threadIdx.x; i < B; i += 1024) {
     float ri = r[i], ci = c[i], di = diag[i];
-    float t[5] = {ri - di, ci - di, ri * ri, ri, ci};
+    float o = 0.f;
+    if (loss == CRL_LOSS_FLATNCE_FWD) { const float x = ri - di; o = __expf(x - x); }
+    else if (loss == CRL_LOSS_FLATNCE_BWD) { const float x = ci - di; o = __expf(x - x); }
+    else if (pairwise) o = term[i];
+    float t[6] = {ri - di, ci - di, ri * ri, ri, ci, o};
 #pragma unroll
-    for (int k = 0; k < 5; ++k) kahan_add(acc[k], cmp[k], t[k]);
-    if (!isfinite(ri) || !isfinite(ci) || !isfinite(di)) bad += 1.f;
+    for (int k = 0; k < 6; ++k) kahan_add(acc[k], cmp[k], t[k]);
+    if (!isfinite(ri) || !isfinite(ci) || !isfinite(di) || !isfinite(o)) bad += 1.f;
   }
 #pragma unroll
-  for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] = acc[k] - cmp[k];
-  sh[5][threadIdx.x] = bad;
+  for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = acc[k] - cmp[k];
+  sh[6][threadIdx.x] = bad;
   __syncthreads();
   for (int w = 512; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w)
 #pragma unroll
-      for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+      for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     const float inv = 1.f / (float)B;
-    float lf = sh[0][0] * inv, lb = sh[1][0] * inv, lp = beta * sh[2][0] * inv;
-    loss_out[0] = lf + (symmetric ? lb : 0.f) + lp;
+    const float lf = sh[0][0] * inv, lb = sh[1][0] * inv, lp = beta * sh[2][0] * inv;
+    float obj;
+    if (loss == CRL_LOSS_FWD) obj = lf;
+    else if (loss == CRL_LOSS_SYM) obj = lf + lb;
+    else if (loss == CRL_LOSS_BWD) obj = lb;
+    else obj = sh[5][0] * inv;
+    loss_out[0] = obj + lp;
     loss_out[1] = lf;
     loss_out[2] = lb;
     loss_out[3] = lp;
     loss_out[4] = sh[3][0] * inv;
     loss_out[5] = sh[4][0] * inv;
-    loss_out[6] = sh[5][0];
-    loss_out[7] = 0.f;
+    loss_out[6] = sh[6][0];
+    loss_out[7] = obj;
   }
 }
-hipError_t launch_loss(const float* r, const float* c, const float* diag, int B, int symmetric,
-                       float beta, float* loss_out, hipStream_t s) {
-  CRL_TIMED("loss_kernel", 0.0, 12.0 * B, s,
-            loss_kernel<<<1, 1024, 0, s>>>(r, c, diag, B, symmetric, beta, loss_out));
-  return hipGetLastError();
-}
-
-// In place: F_ij -> G_ij = dL/dF_ij, or for the L2 energy H_ij = G_ij / d_ij
-// (d_ij = -F_ij; 0 where d_ij = 0) together with rowsum_i = sum_j H_ij.
-__global__ __launch_bounds__(256) void grad_matrix_kernel(float* __restrict__ F, int B, int ld,
-                                                          const float* __restrict__ r,
-                                                          const float* __restrict__ c,
-                                                          int symmetric, float beta, int l2,
-                                                          float* __restrict__ rowsum) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= B) return;
-  const float inv = 1.f / (float)B;
-  const float ri = r[i];
-  const float pen = 2.f * beta * ri;
-  float* row = F + (int64_t)i * ld;
-  float rs = 0.f;
-  for (int j = lane; j < B; j += 64) {
-    float f = row[j];
-    float pr = __expf(f - ri);
-    float g = pr * (1.f + pen) - (j == i ? 1.f : 0.f);
-    if (symmetric) g += __expf(f - c[j]) - (j == i ? 1.f : 0.f);
-    g *= inv;
-    if (l2) {
-      float d = -f;
-      g = d > 0.f ? g / d : 0.f;
-      rs += g;
-    }
-    row[j] = g;
-  }
-  if (l2) {
-    rs = wave_sum(rs);
-    if (lane == 0) rowsum[i] = rs;
-  }
-}
-hipError_t launch_grad_matrix(float* F, int B, int ld, const float* r, const float* c, int symmetric,
-                              float beta, int l2, float* rowsum, hipStream_t s) {
-  CRL_TIMED("grad_matrix_kernel", 0.0, 8.0 * B * B, s,
-            grad_matrix_kernel<<<(B + 3) / 4, 256, 0, s>>>(F, B, ld, r, c, symmetric, beta, l2, rowsum));
+hipError_t launch_loss(const float* r, const float* c, const float* diag, const float* term,
+                       int B, int loss, float beta, float* loss_out, hipStream_t s) {
+  CRL_TIMED("loss_kernel", 0.0, 16.0 * B, s,
+            loss_kernel<<<1, 1024, 0, s>>>(r, c, diag, term, B, loss, beta, loss_out));
   return hipGetLastError();
 }
 

@@ -29,8 +29,10 @@ class Workload:
     hidden: Tuple[int, ...]  # hidden widths of each encoder
     activation: str          # "relu" | "ln_swish"
     repr_dim: int
-    energy_function: str     # "dot" | "l2"
-    contrastive_loss_function: str  # "fwd_infonce" | "symmetric_infonce"
+    energy_function: str     # "dot" | "l2" | "cos" | "l2sq" | "l1"
+    # "fwd_infonce" | "symmetric_infonce" | "bwd_infonce" | "flatnce_fwd" |
+    # "flatnce_bwd" | "fb" | "dpo" | "ipo" | "sppo"
+    contrastive_loss_function: str
     logsumexp_penalty: float = 0.1
     discounting: float = 0.99
     precision: str = "fp32"  # arithmetic of the GEMM/logit tiles: "fp32" | "bf16"

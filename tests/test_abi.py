@@ -57,7 +57,8 @@ def _create(**kw):
     ("repr_dim", 12, "repr_dim"),
     ("goal_lo", 28, "goal slice"),
     ("energy", 7, "energy"),
-    ("loss", 3, "loss"),
+    ("loss", 9, "loss"),
+    ("energy", -1, "energy"),
     ("discount", 1.0, "discount"),
     ("discount", 0.0, "discount"),
     ("max_episode_len", 1, "max_episode_len"),
@@ -126,6 +127,26 @@ def test_create_rejects_unsupported_combinations():
     assert rc == _lib.CRL_EUNSUPPORTED and "BF16" in err
     rc, err = _create(logits=1, precision=1, repr_dim=48)
     assert rc == _lib.CRL_EUNSUPPORTED and "repr_dim" in err
+    # the L1 energy is not a product, the pairwise objectives need the matrix
+    rc, err = _create(logits=1, precision=1, energy=_lib.ENERGY["l1"])
+    assert rc == _lib.CRL_EUNSUPPORTED and "L1" in err
+    for loss in ("fb", "dpo", "ipo", "sppo"):
+        rc, err = _create(logits=1, precision=1, loss=_lib.LOSS[loss])
+        assert rc == _lib.CRL_EUNSUPPORTED and "pairwise" in err
+    rc, err = _create(energy=_lib.ENERGY["l1"], repr_dim=512)
+    assert rc == _lib.CRL_EUNSUPPORTED and "L1" in err
+
+
+def test_enums_follow_the_header():
+    src = open(HEADER).read()
+    for name, v in _lib.ENERGY.items():
+        key = {"l2sq": "L2SQ"}.get(name, name.upper())
+        assert re.search(rf"CRL_ENERGY_{key}\s*=\s*{v}\b", src), name
+    for name, v in _lib.LOSS.items():
+        key = {"fwd_infonce": "FWD", "symmetric_infonce": "SYM", "bwd_infonce": "BWD"}.get(
+            name, name.upper())
+        assert re.search(rf"CRL_LOSS_{key}\s*=\s*{v}\b", src), name
+    assert re.search(r"CRL_ENONFINITE\s*=\s*-4", src)
 
 
 def test_reserved_fields_must_be_zero():
@@ -149,6 +170,9 @@ def test_null_arguments_rejected_without_device():
                             None, None, None, None, None) == _lib.CRL_EINVAL
     n64 = C.c_int64()
     assert L.crl_actor_param_count(None, C.byref(n64)) == _lib.CRL_EINVAL
+    assert L.crl_infonce_fwd(None, None, None, None, None, None) == _lib.CRL_EINVAL
+    assert L.crl_infonce_bwd(None, None, None, None, None, None, None) == _lib.CRL_EINVAL
+    assert L.crl_check_finite(None, None) == _lib.CRL_EINVAL
     n = C.c_int32()
     assert L.crl_timing_count(C.byref(n)) == _lib.CRL_OK
 

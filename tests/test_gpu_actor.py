@@ -81,6 +81,10 @@ CASES = {
     "fp32_dot_ln": SMALL,
     "fp32_l2_relu": SMALL.with_(name="actor_l2_relu", energy_function="l2", activation="relu",
                                 batch_size=133),
+    # the other energies of the critic on the policy's action
+    "fp32_cos_ln": SMALL.with_(name="actor_cos", energy_function="cos"),
+    "fp32_l2sq_ln": SMALL.with_(name="actor_l2sq", energy_function="l2sq"),
+    "fp32_l1_ln": SMALL.with_(name="actor_l1", energy_function="l1", batch_size=150),
     # 64-deep K steps throughout: the policy's and critic's GEMMs take the
     # direct-to-LDS kernel, with ragged M (first-layer dW) and N (16-wide head)
     "bf16_dot_ln": SMALL.with_(name="actor_bf16", precision="bf16", logits="fused",

@@ -60,9 +60,11 @@ SMALL = [
 
 
 def _tol(w):
+    # vec: relative L2 of phi, psi, r, c (BF16 encoders round every layer's
+    # activations to 8 bits, so phi and psi carry ~1e-2 relative error)
     if w.precision == "fp32":
-        return dict(loss=1e-4, cos=0.99999)
-    return dict(loss=1e-2, cos=0.999)
+        return dict(loss=1e-4, cos=0.99999, vec=1e-4)
+    return dict(loss=1e-2, cos=0.999, vec=3e-2)
 
 
 def _check_relabel(w, g, o, obs, act):
@@ -88,7 +90,11 @@ def test_critic_parity_small(w):
     rep = compare(w, g, o)
     print_report(w.name, rep)
     tol = _tol(w)
-    assert rep["loss_total"] <= tol["loss"]
+    for i, k in enumerate(("total", "fwd", "bwd", "pen")):
+        assert abs(g.loss[i] - o[k]) <= tol["loss"] * max(abs(o[k]), 1.0), (k, g.loss[i], o[k])
+    for k in ("phi", "psi", "r", "c"):
+        assert rep[k] <= tol["vec"], (k, rep[k])
+    assert rep["dphi_cos"] >= tol["cos"] and rep["dpsi_cos"] >= tol["cos"]
     assert rep["min_cos"] >= tol["cos"]
     # padding of the flat gradient is exactly zero
     assert np.all(np.isfinite(g.grads))

@@ -78,7 +78,7 @@ def test_log_pi_matches_torch_tanh_gaussian():
     assert np.allclose(log_pi[ok], plain[ok], rtol=1e-12)
 
 
-@pytest.mark.parametrize("energy", ["dot", "l2"])
+@pytest.mark.parametrize("energy", ["dot", "l2", "cos", "l2sq", "l1"])
 def test_actor_gradients_central_differences(energy):
     w, phi, psi, actor, x_sg, g, obs_t, eps = _setup(energy)
     actor = [{k: v.astype(np.float64) for k, v in L.items()} for L in actor]
@@ -109,8 +109,21 @@ def test_actor_gradients_central_differences(energy):
     assert out["d_log_alpha"] == pytest.approx(fd, rel=1e-8)
 
 
-def test_actor_gradients_match_torch_autograd():
-    w, phi, psi, actor, x_sg, g, obs_t, eps = _setup("dot")
+def _torch_pair_energy(p, q, kind):
+    if kind == "dot":
+        return (p * q).sum(1)
+    if kind == "l2":
+        return -torch.linalg.vector_norm(p - q, dim=1)
+    if kind == "l2sq":
+        return -((p - q) ** 2).sum(1)
+    if kind == "l1":
+        return -(p - q).abs().sum(1)
+    return torch.nn.functional.cosine_similarity(p, q, dim=1, eps=1e-300)
+
+
+@pytest.mark.parametrize("energy", ["dot", "l2", "cos", "l2sq", "l1"])
+def test_actor_gradients_match_torch_autograd(energy):
+    w, phi, psi, actor, x_sg, g, obs_t, eps = _setup(energy)
     out = A.actor_loss_and_grads(actor, phi, psi, x_sg, g, obs_t, eps, -0.2, w)
     T = lambda a, rg=False: torch.tensor(np.asarray(a, np.float64), requires_grad=rg)
     ta = [{k: T(v, True) for k, v in L.items()} for L in actor]
@@ -136,7 +149,7 @@ def test_actor_gradients_match_torch_autograd():
     tpsi = [{k: T(v) for k, v in L.items()} for L in psi]
     p = mlp(tphi, torch.cat([T(obs_t), torch.tanh(u)], 1))
     q = mlp(tpsi, T(g))
-    f = (p * q).sum(1)
+    f = _torch_pair_energy(p, q, w.energy_function)
     loss = (math.exp(-0.2) * logp - f).mean()
     loss.backward()
     assert out["loss"] == pytest.approx(loss.item(), rel=1e-12)
