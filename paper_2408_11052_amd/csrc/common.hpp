@@ -61,18 +61,24 @@ __device__ inline void lse_merge(float& m, float& s, float m2, float s2) {
   m = mn;
 }
 
-// logistic function with the hardware reciprocal (about 1 ulp)
 // The L2 distance from the norm expansion d^2 = |x|^2 + |y|^2 - 2 <x, y>.
 // Below 2^-14 (|x|^2 + |y|^2) the expansion's value is rounding noise of the
 // product and the norms (an FP32 sum over up to 256 terms errs by about
 // 2^-18 of them), so the distance is taken as 0 there: the energy is 0 and
-// its subgradient, scaled by 1/d, is 0 too.
+// its subgradient, scaled by 1/d, is 0 too.  Both tests are written so that
+// a NaN operand fails them and stays NaN (the loss then reports it).
 constexpr float kL2Floor = 1.f / 16384.f;
 __device__ __forceinline__ float l2_dist(float nx, float ny, float v) {
   const float d2 = nx + ny - 2.f * v;
-  return d2 > kL2Floor * (nx + ny) ? sqrtf(d2) : 0.f;
+  return d2 <= kL2Floor * (nx + ny) ? 0.f : sqrtf(d2);
+}
+// The squared distance from the same expansion, clamped at 0 (NaN kept).
+__device__ __forceinline__ float l2sq_dist(float nx, float ny, float v) {
+  const float d2 = nx + ny - 2.f * v;
+  return d2 < 0.f ? 0.f : d2;
 }
 
+// logistic function with the hardware reciprocal (about 1 ulp)
 __device__ inline float sigmoidf_(float y) { return __builtin_amdgcn_rcpf(1.f + __expf(-y)); }
 
 

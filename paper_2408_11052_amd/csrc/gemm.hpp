@@ -29,7 +29,7 @@ enum : int {
   EPI_BIAS_RELU = 2, // max(v + bias[n], 0)
   EPI_MASK_POS = 3,  // aux(m,n) > 0 ? v : 0      (ReLU backward)
   EPI_L2 = 4,        // -l2_dist(rowv[m], colv[n], v)
-  EPI_L2SQ = 5       // -max(rowv[m] + colv[n] - 2 v, 0)
+  EPI_L2SQ = 5       // -l2sq_dist(rowv[m], colv[n], v)
 };
 
 struct GemmDesc {
@@ -445,7 +445,7 @@ void gemm_kernel(GemmParams P) {
           else if (D.epi == EPI_L2 || D.epi == EPI_L2SQ) {
             const int row = m0 + rl;
             const float rv = row < D.M ? D.rowv[row] : 0.f;
-            v = D.epi == EPI_L2 ? -l2_dist(rv, ccol, v) : -fmaxf(rv + ccol - 2.f * v, 0.f);
+            v = D.epi == EPI_L2 ? -l2_dist(rv, ccol, v) : -l2sq_dist(rv, ccol, v);
           }
         }
         Cs[rl * kLdc + cl] = v;

@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
       for (int r = 0; r < 4; ++r) {
         float v = acc[jb][r];
         if (EN == kEnL2) v = -l2_dist(nx[r], ny, v);
-        if (EN == kEnL2sq) v = -fmaxf(nx[r] + ny - 2.f * v, 0.f);
+        if (EN == kEnL2sq) v = -l2sq_dist(nx[r], ny, v);
         f[jb][r] = (cv && rvalid[r]) ? v : -INFINITY;
         const int row = row_base + 4 * g + r;
         if (cv && rvalid[r] && row == col) a.diag[row] = v;
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
         float v = acc[jb][r];
         float d = 0.f;
         if (EN == kEnL2) { d = l2_dist(nx[r], cvals.ny[jb], v); v = -d; }
-        if (EN == kEnL2sq) v = -fmaxf(nx[r] + cvals.ny[jb] - 2.f * v, 0.f);
+        if (EN == kEnL2sq) v = -l2sq_dist(nx[r], cvals.ny[jb], v);
         float gv = 0.f;
         if (cv && rvalid[r]) {
           const float dl = (row == col) ? 1.f : 0.f;
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
         float v = acc[jb][r];
         float d = 0.f;
         if (EN == kEnL2) { d = l2_dist(nx[r], ny[jb], v); v = -d; }
-        if (EN == kEnL2sq) v = -fmaxf(nx[r] + ny[jb] - 2.f * v, 0.f);
+        if (EN == kEnL2sq) v = -l2sq_dist(nx[r], ny[jb], v);
         float gv = 0.f;
         if (cp[jb] != 0.f && rvalid[r]) {
           const float dl = (row == col) ? 1.f : 0.f;
