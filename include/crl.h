@@ -222,6 +222,31 @@ CRL_API int crl_infonce_fwd(crl_ctx* ctx, const float* phi, const float* psi, vo
 CRL_API int crl_infonce_bwd(crl_ctx* ctx, const float* phi, const float* psi, void* ws,
                             float* dphi, float* dpsi, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * crl_infonce_fwd without the workspace argument.  The same kernels run on a
+ * static device array of CRL_NOALLOC_SCRATCH_BYTES instead, one per device,
+ * which the library holds from its first crl_create on that device until the
+ * process ends.  Nothing is allocated or freed by this call (with kernel
+ * timing off, the default).
+ *   phi, psi    device FP32 [B][repr_dim], 16-byte aligned (read)
+ *   loss_out    device FP32 [8] out, as crl_critic_fwd's
+ *   r_out, c_out, diag_out   device FP32 [B] out, or NULL: r_i, c_j, F_ii
+ * Returns CRL_EINVAL, launching nothing, when the context's loss step needs
+ * more scratch than the array holds.  Bytes needed, each buffer rounded up
+ * to 256: fused logits 4 B D (BF16 rows) + 8 B (S + ceil(B / 64)) (log-sum-exp
+ * partials, S <= 16 column splits) + 28 B (B = 16384 with D = 256 fits);
+ * materialised 4 B ldF + 512 B + 28 B, + 8 B D for the cosine energy
+ * (B = 2048 fits, B = 4096 does not).  Every call on a device shares its array
+ * and leaves its contents there; nothing in it needs to start at zero (every
+ * value is written before it is read).  Calls that overlap in time on one
+ * device (other streams, other threads) race on the array and must not be
+ * issued. */
+#define CRL_NOALLOC_SCRATCH_BYTES (64u << 20)
+CRL_API int crl_infonce_fwd_noalloc(crl_ctx* ctx, const float* phi, const float* psi,
+                                    float* loss_out, float* r_out, float* c_out,
+                                    float* diag_out, void* stream);
+
 /* Reads loss_out [8] as a forward left it (crl_critic_fwd, crl_infonce_fwd)
  * after waiting for `stream`: CRL_ENONFINITE if the total is not finite or
  * any row / column term was (loss_out[6] > 0), else CRL_OK.  This call

@@ -60,6 +60,7 @@ SIGNATURES = {
     "crl_critic_bwd": (C.c_int, [P, P, P, P, P, P, P, P]),
     "crl_infonce_fwd": (C.c_int, [P, P, P, P, P, P]),
     "crl_infonce_bwd": (C.c_int, [P, P, P, P, P, P, P]),
+    "crl_infonce_fwd_noalloc": (C.c_int, [P, P, P, P, P, P, P, P]),
     "crl_check_finite": (C.c_int, [P, P]),
     "crl_actor_step": (C.c_int, [P, P, P, P, P, P, P, P, P, U64, P, P, P, P, P, P]),
     "crl_adam_step": (C.c_int, [P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_double,

@@ -214,6 +214,11 @@ class Critic:
         check(lib().crl_infonce_bwd(self.ctx, _ptr(phi), _ptr(psi), _ptr(ws), _ptr(dphi),
                                     _ptr(dpsi), _stream(stream)))
 
+    def crl_infonce_fwd_noalloc(self, phi, psi, loss_out, r_out=None, c_out=None,
+                                diag_out=None, stream=None):
+        check(lib().crl_infonce_fwd_noalloc(self.ctx, _ptr(phi), _ptr(psi), _ptr(loss_out),
+                                            _ptr(r_out), _ptr(c_out), _ptr(diag_out),
+                                            _stream(stream)))
 
     def crl_actor_step(self, params, params_bf16, actor_params, actor_params_bf16, log_alpha,
                        x_sa, x_g, x_sg, seed: int, step, ws, actor_grads, alpha_grad,

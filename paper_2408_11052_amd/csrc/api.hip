@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "crl.h"
@@ -12,7 +13,32 @@
 
 using namespace crl;
 
+// Scratch memory of crl_infonce_fwd_noalloc: one copy per device, held from
+// the library's first use on that device until the process ends.  In host
+// code `scratch` names the symbol only; its device address comes from
+// hipGetSymbolAddress (scratch_address below) and is what kernels receive.
+static __device__ __align__(256) unsigned char scratch[CRL_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+// This device's address of `scratch`, looked up once per device with that
+// device current (crl_create calls it).
+hipError_t scratch_address(int dev, void** out) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDev] = {};
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
 
 thread_local char g_err[512] = "";
 
@@ -75,6 +101,14 @@ struct Group {
   double few_bytes = 0, many_bytes = 0;
 };
 
+// Byte offsets of the buffers the loss forward (critic matrix, log-sum-exps,
+// objective terms) uses, inside whichever scratch memory it runs on.
+struct LossWs {
+  int64_t r, c, diag, nphi, npsi, rowterm, rowaux, uphi, upsi;
+  int64_t logits, cpm, cps;                          // materialised logits
+  int64_t phi_b, psi_b, row_m, row_s, col_m, col_s;  // fused logits
+};
+
 }  // namespace
 
 struct crl_ctx {
@@ -103,6 +137,10 @@ struct crl_ctx {
   int ldd;                                 // row stride of dact
   int ln_rows_per_wave, ln_nparts, rchunks;
   int ldF;                     // row stride of the materialised logits
+  LossWs na;                   // the loss forward packed from offset 0 (no-alloc entry point)
+  int64_t na_bytes;            // bytes that layout needs
+  void* scratch;               // this device's address of `scratch`, NULL if unavailable
+  hipError_t scratch_err;      // why it is unavailable
 };
 
 namespace {
@@ -495,6 +533,41 @@ void plan_workspace(crl_ctx* x) {
     x->dact = take(B * x->ldd * 4);
   }
   x->ws_bytes = align_up(off, 256);
+
+  // The loss forward alone, packed from offset 0: the layout
+  // crl_infonce_fwd_noalloc uses inside the static scratch array.
+  int64_t so = 0;
+  auto st = [&](int64_t bytes) { return take_bytes(x, so, bytes); };
+  LossWs& n = x->na;
+  n.r = st(B * 4); n.c = st(B * 4); n.diag = st(B * 4);
+  n.nphi = st(B * 4); n.npsi = st(B * 4);
+  n.rowterm = st(B * 4); n.rowaux = st(B * 4);
+  n.uphi = n.upsi = n.logits = n.cpm = n.cps = -1;
+  n.phi_b = n.psi_b = n.row_m = n.row_s = n.col_m = n.col_s = -1;
+  if (!x->fused) {
+    n.logits = st(B * x->ldF * 4);
+    n.cpm = st((int64_t)x->rchunks * B * 4);
+    n.cps = st((int64_t)x->rchunks * B * 4);
+    if (x->energy == CRL_ENERGY_COS) { n.uphi = st(B * D * 4); n.upsi = st(B * D * 4); }
+  } else {
+    const int S = fused_splits(x->B);  // bounds the forward's split count
+    const int nrb = (x->B + 63) / 64;
+    n.phi_b = st(B * D * 2); n.psi_b = st(B * D * 2);
+    n.row_m = st((int64_t)S * B * 4); n.row_s = st((int64_t)S * B * 4);
+    n.col_m = st((int64_t)nrb * B * 4); n.col_s = st((int64_t)nrb * B * 4);
+  }
+  x->na_bytes = align_up(so, 256);
+}
+
+// The same offsets inside the context's own workspace.
+LossWs loss_ws(const crl_ctx* x) {
+  LossWs o;
+  o.r = x->r; o.c = x->c; o.diag = x->diag; o.nphi = x->nphi; o.npsi = x->npsi;
+  o.rowterm = x->rowterm; o.rowaux = x->rowaux; o.uphi = x->uphi; o.upsi = x->upsi;
+  o.logits = x->logits; o.cpm = x->cpm; o.cps = x->cps;
+  o.phi_b = x->phi_b; o.psi_b = x->psi_b; o.row_m = x->row_m; o.row_s = x->row_s;
+  o.col_m = x->col_m; o.col_s = x->col_s;
+  return o;
 }
 
 inline char* W(void* ws, int64_t off) { return static_cast<char*>(ws) + off; }
@@ -730,17 +803,17 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
 
 // The critic matrix of phi and psi (FP32 [B][D]), its row and column
 // log-sum-exps and diagonal, and the loss parts, for the context's energy and
-// objective.  top (fused logits): the output layer's deferred split-K launch,
+// objective, with its buffers at the offsets o inside ws.  top (fused logits): the output layer's deferred split-K launch,
 // whose sum the prep kernel takes (phi and psi are then its outputs).
-int contrastive_fwd(crl_ctx* x, const float* phi, const float* psi, void* ws, float* loss_out,
-                    const GemmParams* top, hipStream_t s) {
+int contrastive_fwd(crl_ctx* x, const float* phi, const float* psi, void* ws, const LossWs& o,
+                    float* loss_out, const GemmParams* top, hipStream_t s) {
   const int B = x->B, D = x->D;
-  float* r = WF(ws, x->r);
-  float* c = WF(ws, x->c);
-  float* dg = WF(ws, x->diag);
-  float* term = WF(ws, x->rowterm);
+  float* r = WF(ws, o.r);
+  float* c = WF(ws, o.c);
+  float* dg = WF(ws, o.diag);
+  float* term = WF(ws, o.rowterm);
   if (!x->fused) {
-    float* F = WF(ws, x->logits);
+    float* F = WF(ws, o.logits);
     if (x->energy == CRL_ENERGY_L1) {
       CRL_HIP(launch_l1_energy(phi, psi, F, B, D, x->ldF, s), "L1 energy");
     } else {
@@ -754,33 +827,33 @@ int contrastive_fwd(crl_ctx* x, const float* phi, const float* psi, void* ws, fl
       d.alpha = 1.f;
       d.epi = EPI_NONE;
       if (x->energy == CRL_ENERGY_COS) {
-        CRL_HIP(launch_unit_rows(phi, WF(ws, x->uphi), WF(ws, x->nphi), B, D, s), "unit rows");
-        CRL_HIP(launch_unit_rows(psi, WF(ws, x->upsi), WF(ws, x->npsi), B, D, s), "unit rows");
-        d.A = WF(ws, x->uphi);
-        d.B = WF(ws, x->upsi);
+        CRL_HIP(launch_unit_rows(phi, WF(ws, o.uphi), WF(ws, o.nphi), B, D, s), "unit rows");
+        CRL_HIP(launch_unit_rows(psi, WF(ws, o.upsi), WF(ws, o.npsi), B, D, s), "unit rows");
+        d.A = WF(ws, o.uphi);
+        d.B = WF(ws, o.upsi);
       } else if (x->energy == CRL_ENERGY_L2 || x->energy == CRL_ENERGY_L2SQ) {
-        CRL_HIP(launch_sqnorm(phi, WF(ws, x->nphi), B, D, s), "norms");
-        CRL_HIP(launch_sqnorm(psi, WF(ws, x->npsi), B, D, s), "norms");
+        CRL_HIP(launch_sqnorm(phi, WF(ws, o.nphi), B, D, s), "norms");
+        CRL_HIP(launch_sqnorm(psi, WF(ws, o.npsi), B, D, s), "norms");
         d.epi = x->energy == CRL_ENERGY_L2 ? EPI_L2 : EPI_L2SQ;
-        d.rowv = WF(ws, x->nphi);
-        d.colv = WF(ws, x->npsi);
+        d.rowv = WF(ws, o.nphi);
+        d.colv = WF(ws, o.npsi);
       }
       plan_split_k(P, false, 512);
       CRL_HIP(launch_gemm(P, false, LAY_KC, LAY_KC, false, s), "logits GEMM");
     }
-    CRL_HIP(launch_row_obj(F, B, x->ldF, x->loss, r, dg, term, WF(ws, x->rowaux), s),
+    CRL_HIP(launch_row_obj(F, B, x->ldF, x->loss, r, dg, term, WF(ws, o.rowaux), s),
             "row log-sum-exp and objective terms");
     const int rc_ = std::min(x->rchunks, B);
-    CRL_HIP(launch_col_lse_partial(F, B, x->ldF, rc_, WF(ws, x->cpm), WF(ws, x->cps), s), "column LSE");
-    CRL_HIP(launch_lse_merge(WF(ws, x->cpm), WF(ws, x->cps), rc_, B, c, s), "column LSE merge");
+    CRL_HIP(launch_col_lse_partial(F, B, x->ldF, rc_, WF(ws, o.cpm), WF(ws, o.cps), s), "column LSE");
+    CRL_HIP(launch_lse_merge(WF(ws, o.cpm), WF(ws, o.cps), rc_, B, c, s), "column LSE merge");
   } else {
     FusedArgs a{};
     a.phi = phi; a.psi = psi;
-    a.phi_b = reinterpret_cast<bf16_t*>(W(ws, x->phi_b));
-    a.psi_b = reinterpret_cast<bf16_t*>(W(ws, x->psi_b));
-    a.nphi = WF(ws, x->nphi); a.npsi = WF(ws, x->npsi);
-    a.row_m = WF(ws, x->row_m); a.row_s = WF(ws, x->row_s);
-    a.col_m = WF(ws, x->col_m); a.col_s = WF(ws, x->col_s);
+    a.phi_b = reinterpret_cast<bf16_t*>(W(ws, o.phi_b));
+    a.psi_b = reinterpret_cast<bf16_t*>(W(ws, o.psi_b));
+    a.nphi = WF(ws, o.nphi); a.npsi = WF(ws, o.npsi);
+    a.row_m = WF(ws, o.row_m); a.row_s = WF(ws, o.row_s);
+    a.col_m = WF(ws, o.col_m); a.col_s = WF(ws, o.col_s);
     a.r = r; a.c = c; a.diag = dg;
     CRL_HIP(launch_fused_fwd(a, B, D, x->energy, (top && top->splits > 1) ? top : nullptr, s),
             "fused InfoNCE forward");
@@ -902,6 +975,9 @@ CRL_API int crl_create(const crl_config* cfg, crl_ctx** out) {
   x->cfg = *cfg;
   hipError_t he = hipGetDevice(&x->device);
   if (he != hipSuccess) { delete x; return hip_fail(he, "hipGetDevice"); }
+  // the no-alloc entry point's scratch; without it only that entry point fails
+  x->scratch_err = scratch_address(x->device, &x->scratch);
+  if (x->scratch_err != hipSuccess) (void)hipGetLastError();
   x->bf16 = cfg->precision == CRL_PREC_BF16;
   x->ln = cfg->activation == CRL_ACT_LN_SWISH;
   x->energy = cfg->energy;
@@ -1070,8 +1146,8 @@ CRL_API int crl_critic_fwd(crl_ctx* x, const float* params, const uint16_t* para
   GemmParams top{};
   CRL_TRY(mlp_forward(x, nc, 2, ws, s, x->fused ? &top : nullptr));
 
-  return contrastive_fwd(x, WF(ws, x->sl[0].out), WF(ws, x->sl[1].out), ws, loss_out,
-                         x->fused ? &top : nullptr, s);
+  return contrastive_fwd(x, WF(ws, x->sl[0].out), WF(ws, x->sl[1].out), ws, loss_ws(x),
+                         loss_out, x->fused ? &top : nullptr, s);
 }
 
 CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* params_bf16,
@@ -1108,7 +1184,33 @@ CRL_API int crl_infonce_fwd(crl_ctx* x, const float* phi, const float* psi, void
   if (!aligned16(phi) || !aligned16(psi) || !aligned16(ws))
     return fail(CRL_EINVAL, "phi, psi and ws must be 16-byte aligned");
   CRL_TRY(check_device(x));
-  return contrastive_fwd(x, phi, psi, ws, loss_out, nullptr, (hipStream_t)stream);
+  return contrastive_fwd(x, phi, psi, ws, loss_ws(x), loss_out, nullptr, (hipStream_t)stream);
+}
+
+CRL_API int crl_infonce_fwd_noalloc(crl_ctx* x, const float* phi, const float* psi,
+                                    float* loss_out, float* r_out, float* c_out,
+                                    float* diag_out, void* stream) {
+  if (!x) return fail(CRL_EINVAL, "NULL context");
+  if (!phi || !psi || !loss_out) return fail(CRL_EINVAL, "NULL buffer argument");
+  if (!aligned16(phi) || !aligned16(psi)) return fail(CRL_EINVAL, "phi and psi must be 16-byte aligned");
+  CRL_TRY(check_device(x));
+  if (x->na_bytes > (int64_t)CRL_NOALLOC_SCRATCH_BYTES)
+    return fail(CRL_EINVAL,
+                "the loss of this context (batch %d, repr_dim %d) needs %lld bytes of scratch, "
+                "more than the %lld of the static array",
+                x->B, x->D, (long long)x->na_bytes, (long long)CRL_NOALLOC_SCRATCH_BYTES);
+  if (!x->scratch) return hip_fail(x->scratch_err, "hipGetSymbolAddress(scratch)");
+  hipStream_t s = (hipStream_t)stream;
+  CRL_TRY(contrastive_fwd(x, phi, psi, x->scratch, x->na, loss_out, nullptr, s));
+  const size_t nb = (size_t)x->B * sizeof(float);
+  if (r_out)
+    CRL_HIP(hipMemcpyAsync(r_out, WF(x->scratch, x->na.r), nb, hipMemcpyDeviceToDevice, s), "copy r");
+  if (c_out)
+    CRL_HIP(hipMemcpyAsync(c_out, WF(x->scratch, x->na.c), nb, hipMemcpyDeviceToDevice, s), "copy c");
+  if (diag_out)
+    CRL_HIP(hipMemcpyAsync(diag_out, WF(x->scratch, x->na.diag), nb, hipMemcpyDeviceToDevice, s),
+            "copy diag");
+  return CRL_OK;
 }
 
 CRL_API int crl_infonce_bwd(crl_ctx* x, const float* phi, const float* psi, void* ws,
