@@ -8,4 +8,4 @@ from the product path.  It is written from the paper, in the paper's order
 and notation, with numpy in float64 and Python integers for the random
 stream.
 """
-from . import philox, relabel, critic, objectives, adam  # noqa: F401
+from . import philox, relabel, replay, critic, objectives, adam  # noqa: F401
