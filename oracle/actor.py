@@ -17,6 +17,19 @@ policy update after the critic update):
 * the entropy coefficient: L_alpha = -mean_i [log alpha (log pi_i + H)] with
   log pi detached and target entropy H = -|A|, optimised in log alpha.
 
+Random goals (Appendix C): the policy objective generalised with a ratio
+alpha_rand in [0, 1], (1 - alpha_rand) E[f(s, a', g)] with g from the future
+of s's trajectory plus alpha_rand E[f(s, a', g-)] with g- drawn from the
+goal marginal of the buffer.  Reading: each sample's goal is replaced, with
+probability alpha_rand, by the relabelled goal of another sample of the same
+batch (the batch goals are independent draws of that marginal), for both
+the policy input [s, g] and the critic's psi(g); the estimate is unbiased
+for the mixed objective.  The draw uses Philox4x64-10 stream 2: counter
+(b, step, 2, 0), key (seed, 0), words w0, w1; sample b is mixed iff
+floor(w0 / 2^11) < floor(alpha_rand * 2^53) (so P = that floor / 2^53) and
+takes the goal of j = (b + 1 + floor(w1 (B - 1) / 2^64)) mod B, uniform over
+the other samples; with B = 1 nothing is mixed.
+
 The Gaussian noise is drawn without any floating-point step in the random
 stream itself: Philox4x64-10 with key (seed, 0) and counter (b, step, 1, j)
 gives four 64-bit words; each word w becomes u = (2 floor(w / 2^41) + 1) / 2^24
@@ -33,7 +46,9 @@ import math
 import numpy as np
 
 from . import critic as C
-from .philox import philox4x64_10
+from fractions import Fraction
+
+from .philox import mulhi64, philox4x64_10
 
 SIGMA_MIN = 1e-3
 LOG_2PI = math.log(2.0 * math.pi)
@@ -59,6 +74,26 @@ def box_muller_noise(seed: int, step: int, batch: int, act_dim: int, stream: int
                 z.append(r * math.sin(2.0 * math.pi * u2))
         eps[b] = z[:act_dim]
     return eps
+
+
+def random_goal_mix(x_sg, x_g, obs_dim: int, ratio: float, seed: int, step: int,
+                    stream: int = 2):
+    """(x_sg', x_g', mixed [B] bool, partner [B]) of the random-goal reading above."""
+    x_sg = np.asarray(x_sg, np.float64)
+    x_g = np.asarray(x_g, np.float64)
+    B, d_g = x_g.shape
+    R = int(Fraction(float(ratio)) * (1 << 53))  # floor, ratio >= 0
+    partner = np.arange(B)
+    mixed = np.zeros(B, bool)
+    for b in range(B if B >= 2 else 0):
+        w0, w1, _, _ = philox4x64_10((b, step, stream, 0), (seed, 0))
+        if (w0 >> 11) < R:
+            mixed[b] = True
+            partner[b] = (b + 1 + mulhi64(w1, B - 1)) % B
+    g = x_g[partner].copy()
+    sg = x_sg.copy()
+    sg[:, obs_dim:obs_dim + d_g] = g
+    return sg, g, mixed, partner
 
 
 def softplus(x):

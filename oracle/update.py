@@ -1,7 +1,8 @@
 """One full contrastive-RL update in FP64: critic step, then actor step, then
 the entropy-coefficient step (Algorithm 1: sample a batch with hindsight
 goals, update the critic, update the policy; the policy step uses the critic
-after its update).
+after its update).  With a random-goal ratio the policy step takes the goals
+mixed as in ``actor.random_goal_mix`` (Appendix C).
 
 Test infrastructure only (see ``oracle/__init__.py``).
 """
@@ -54,6 +55,9 @@ class FullUpdate:
                         w.critic_lr)
         eps = A.box_muller_noise(self.seed, n, w.batch_size, w.act_dim)
         obs_t = x_sa[:, :w.obs_dim]
+        ratio = float(getattr(w, "random_goal_ratio", 0.0))
+        if ratio > 0.0:  # Appendix C: the policy's goals mixed with random ones
+            x_sg, x_g, _, _ = A.random_goal_mix(x_sg, x_g, w.obs_dim, ratio, self.seed, n)
         la_used = self.log_alpha
         act_out = A.actor_loss_and_grads(self.actor, self.phi, self.psi, x_sg, x_g, obs_t, eps,
                                          la_used, w)

@@ -47,6 +47,8 @@ class Workload:
     # actor (full update only)
     actor_hidden: Tuple[int, ...] = ()
     alpha_lr: float = 3e-4
+    # share of the policy's goals replaced by another sample's (0 = none)
+    random_goal_ratio: float = 0.0
 
     @property
     def in_sa(self) -> int:

@@ -90,6 +90,12 @@ class TorchFullUpdate:
         lc = _critic_loss(F, w)
         lc.backward()
         self.opt_c.step()
+        # random goals (Appendix C) for the policy step only; the mixing draw
+        # is pinned on its own
+        if w.random_goal_ratio > 0:
+            sg, g, _, _ = OA.random_goal_mix(x_sg.numpy(), x_g.numpy(), w.obs_dim,
+                                             w.random_goal_ratio, self.seed, n)
+            x_sg, x_g = torch.tensor(sg), torch.tensor(g)
         # policy step on the updated, frozen critic, with alpha before its step
         alpha = torch.exp(self.log_alpha.detach())[0]
         eps = torch.tensor(OA.box_muller_noise(self.seed, n, w.batch_size, w.act_dim))
@@ -133,10 +139,12 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
 
 
-@pytest.mark.parametrize("energy,act_fn", [("dot", "ln_swish"), ("l2", "ln_swish"),
-                                           ("l2", "relu")])
-def test_full_update_matches_torch_autograd_and_adam(energy, act_fn):
+@pytest.mark.parametrize("energy,act_fn,ratio", [("dot", "ln_swish", 0.0),
+                                                 ("l2", "ln_swish", 0.0), ("l2", "relu", 0.0),
+                                                 ("dot", "ln_swish", 0.5)])
+def test_full_update_matches_torch_autograd_and_adam(energy, act_fn, ratio):
     w, phi, psi, actor, obs, act = _setup(energy, act_fn)
+    w = w.with_(random_goal_ratio=ratio)
     o = FullUpdate(w, phi, psi, actor, seed=2, log_alpha=0.1)
     t = TorchFullUpdate(w, phi, psi, actor, seed=2, log_alpha=0.1)
     for n in range(3):
