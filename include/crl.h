@@ -112,7 +112,10 @@ typedef struct crl_config {
   int32_t actor_hidden;   /* its width (multiple of 8, at most 1024); 0 without */
   float target_entropy;   /* H of the entropy-coefficient objective (-act_dim
                              is the usual choice); used with a policy only */
-  int32_t reserved[4];    /* must be zero */
+  double random_goal_ratio;/* share of the policy step's goals replaced by
+                             another sample's (Appendix C random goals), in
+                             [0, 1]; 0 = none.  Used with a policy only. */
+  int32_t reserved[2];    /* must be zero */
 } crl_config;
 
 typedef struct crl_ctx crl_ctx;
@@ -170,6 +173,56 @@ CRL_API int crl_sample_relabel(crl_ctx* ctx, const float* obs, const float* act,
                                int32_t num_envs, int32_t episode_len,
                                uint64_t seed, const int64_t* step, int32_t* idx,
                                void* x_sa, void* x_g, void* x_sg, void* stream);
+
+/* The replay buffer as a ring of steps per environment (Algorithm 1: each
+ * iteration's unroll of every environment is appended to the buffer D, a new
+ * trajectory starting after each terminal step; Appendix B, benchmark
+ * parameters: the buffer keeps max_replay_size steps per environment and
+ * each iteration appends unroll_length steps of every environment).
+ *   obs    device FP32 [num_envs][capacity][obs_dim] ring (written)
+ *   act    device FP32 [num_envs][capacity][act_dim] ring (written; may be
+ *          NULL with new_act when act_dim == 0)
+ *   traj   device int32 [num_envs][capacity]: the trajectory id of each
+ *          stored step (written).  Within one environment a trajectory is a
+ *          maximal run of equal ids in append order; ids that never repeat
+ *          after changing (an episode counter) are the intended use.
+ *   new_obs  device FP32 [steps][num_envs][obs_dim], time-major as a
+ *          vectorised simulator emits them; new_act [steps][num_envs][act_dim];
+ *          new_traj device int32 [steps][num_envs]
+ *   count  device int64: steps appended per environment so far.  Read, then
+ *          advanced by `steps` on the stream (a second, one-thread launch),
+ *          so a captured graph appends a fresh chunk on every replay.
+ * Step u of the chunk lands in ring row (count + u) mod capacity, so the
+ * ring holds the last min(count, capacity) steps of every environment.
+ * Requires 1 <= steps <= capacity, num_envs >= 1, capacity >= 2.  Nothing
+ * is allocated; the caller owns every buffer. */
+CRL_API int crl_replay_insert(float* obs, float* act, int32_t* traj, int32_t num_envs,
+                              int32_t capacity, int32_t obs_dim, int32_t act_dim,
+                              const float* new_obs, const float* new_act,
+                              const int32_t* new_traj, int32_t steps, int64_t* count,
+                              void* stream);
+
+/* Step 1 on the ring buffer: crl_sample_relabel with goals that never leave
+ * the trajectory of the drawn step (Section 3.2: the goal is a state that
+ * follows s in the same trajectory).  With size = min(*count, capacity)
+ * steps stored and logical index i in [0, size) at ring row
+ * (*count - size + i) mod capacity (0 = oldest), sample b draws, from the
+ * same Philox4x64-10 block as crl_sample_relabel (counter (b, n, 0, 0)):
+ *   e = floor(w0 * E / 2^64), i = floor(w1 * (size - 1) / 2^64),
+ *   k = 1 + #{m in [1, L - 2] : w2 < thr[m]}  (L = cfg.max_episode_len),
+ *   t_g = min(i + k, end(i)), end(i) the last logical index of the run of
+ *   i's trajectory id inside the buffer (a step that ends its trajectory
+ *   takes itself as goal).
+ *   idx   device int32 [B][3] out: (e, ring row of i, ring row of t_g)
+ *   x_sa, x_g, x_sg as crl_sample_relabel, gathered from those rows.
+ * With fewer than two steps stored nothing is drawn: idx rows are
+ * (-1, -1, -1) and the input rows are 0.  The buffer arguments are those of
+ * crl_replay_insert; obs_dim and act_dim are the context's. */
+CRL_API int crl_ring_sample_relabel(crl_ctx* ctx, const float* obs, const float* act,
+                                    const int32_t* traj, int32_t num_envs, int32_t capacity,
+                                    const int64_t* count, uint64_t seed, const int64_t* step,
+                                    int32_t* idx, void* x_sa, void* x_g, void* x_sg,
+                                    void* stream);
 
 /* Step 2: encoders, critic matrix and loss (Section 3.1 objective; Appendix A.2
  * energies and InfoNCE variants; Algorithm 1 critic update with the
@@ -264,6 +317,15 @@ CRL_API int crl_check_finite(const float* loss_out, void* stream);
  *   f_b = energy(phi(s_b, a'_b), psi(g_b))   (the diagonal of the critic),
  *   L_pi = mean_b [alpha log pi_b - f_b],  alpha = exp(*log_alpha),
  *   L_alpha = -log alpha * (mean_b log pi_b + target_entropy).
+ * With cfg.random_goal_ratio = r > 0 (Appendix C, random goals: the policy
+ * objective (1 - r) E f(s, a', g) + r E f(s, a', g-) with g- a goal from
+ * the buffer's marginal), sample b's goal g (in the policy input [s, g] and
+ * in psi(g)) is first replaced by the goal of sample
+ * j = (b + 1 + floor(v1 (B - 1) / 2^64)) mod B when
+ * floor(v0 / 2^11) < floor(r 2^53), v0, v1 the first two words of the
+ * Philox4x64-10 block with counter (b, n, 2, 0), key (seed, 0); with B = 1
+ * nothing is replaced.  The goals of a batch are independent draws of the
+ * marginal, so the step's estimate is unbiased for the mixed objective. 
  * eps is standard normal from Box-Muller on the Philox4x64-10 stream 1: for
  * sample b the block with counter (b, n, 1, j), key (seed, 0), gives words
  * w0..w3; each word w becomes the uniform (2 floor(w / 2^41) + 1) / 2^24,

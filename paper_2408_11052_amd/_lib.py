@@ -33,7 +33,7 @@ class crl_config(C.Structure):
         ("ln_eps", C.c_float), ("discount", C.c_double),
         ("max_episode_len", C.c_int32), ("actor_n_hidden", C.c_int32),
         ("actor_hidden", C.c_int32), ("target_entropy", C.c_float),
-        ("reserved", C.c_int32 * 4),
+        ("random_goal_ratio", C.c_double), ("reserved", C.c_int32 * 2),
     ]
 
 
@@ -56,6 +56,8 @@ SIGNATURES = {
     "crl_input_layout": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
                                    C.POINTER(I32)]),
     "crl_sample_relabel": (C.c_int, [P, P, P, I32, I32, U64, P, P, P, P, P, P]),
+    "crl_replay_insert": (C.c_int, [P, P, P, I32, I32, I32, I32, P, P, P, I32, P, P]),
+    "crl_ring_sample_relabel": (C.c_int, [P, P, P, P, I32, I32, P, U64, P, P, P, P, P, P]),
     "crl_critic_fwd": (C.c_int, [P, P, P, P, P, P, P, P]),
     "crl_critic_bwd": (C.c_int, [P, P, P, P, P, P, P, P]),
     "crl_infonce_fwd": (C.c_int, [P, P, P, P, P, P]),

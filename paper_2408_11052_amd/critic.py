@@ -58,6 +58,7 @@ def make_config(w, max_episode_len: int | None = None) -> crl_config:
         c.actor_n_hidden = len(ahid)
         c.actor_hidden = ahid[0]
         c.target_entropy = -float(w.act_dim)
+        c.random_goal_ratio = float(getattr(w, "random_goal_ratio", 0.0))
     return c
 
 
@@ -198,6 +199,14 @@ class Critic:
                                        _ptr(step), _ptr(idx), _ptr(x_sa), _ptr(x_g),
                                        _ptr(x_sg), _stream(stream)))
 
+    def crl_ring_sample_relabel(self, obs, act, traj, count, seed: int, step, idx, x_sa, x_g,
+                                x_sg=None, stream=None):
+        E, Cap = traj.shape[0], traj.shape[1]
+        check(lib().crl_ring_sample_relabel(self.ctx, _ptr(obs), _ptr(act), _ptr(traj), E, Cap,
+                                            _ptr(count), seed, _ptr(step), _ptr(idx),
+                                            _ptr(x_sa), _ptr(x_g), _ptr(x_sg),
+                                            _stream(stream)))
+
     def crl_critic_fwd(self, params, params_bf16, x_sa, x_g, ws, loss_out, stream=None):
         check(lib().crl_critic_fwd(self.ctx, _ptr(params), _ptr(params_bf16), _ptr(x_sa),
                                    _ptr(x_g), _ptr(ws), _ptr(loss_out), _stream(stream)))
@@ -228,6 +237,16 @@ class Critic:
                                    _ptr(log_alpha), _ptr(x_sa), _ptr(x_g), _ptr(x_sg), seed,
                                    _ptr(step), _ptr(ws), _ptr(actor_grads), _ptr(alpha_grad),
                                    _ptr(loss_out), _stream(stream)))
+
+
+def crl_replay_insert(obs, act, traj, new_obs, new_act, new_traj, count, stream=None):
+    """Append new_* ([U][E][...], time-major) to the ring obs/act/traj ([E][C][...])."""
+    E, Cap, d_s = obs.shape
+    d_a = act.shape[2] if act is not None else 0
+    U = new_obs.shape[0]
+    check(lib().crl_replay_insert(_ptr(obs), _ptr(act), _ptr(traj), E, Cap, d_s, d_a,
+                                  _ptr(new_obs), _ptr(new_act), _ptr(new_traj), U, _ptr(count),
+                                  _stream(stream)))
 
 
 def crl_adam_step(p, g, m, v, p_bf16, step, lr: float, b1: float = 0.9, b2: float = 0.999,

@@ -250,6 +250,53 @@ hipError_t launch_actor_head_bwd(const float* out, int ldo, int A, const float* 
   return hipGetLastError();
 }
 
+// One wavefront per sample: the Philox block (b, n, 2, 0) decides whether
+// sample b takes another sample's goal and whose.  Storage values are copied
+// as they are, so a mixed row equals the row the sampler would have written
+// for that goal.
+template <typename T>
+__global__ __launch_bounds__(256) void goal_mix_kernel(
+    const T* __restrict__ x_g, int ld_g, const T* __restrict__ x_sg, int ld_sg, int d_s,
+    int d_g, uint64_t seed, const int64_t* __restrict__ step, uint64_t thr53, int B,
+    T* __restrict__ xg_out, T* __restrict__ xsg_out) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= B) return;
+  uint64_t x[4] = {(uint64_t)b, (uint64_t)(*step), 2ull, 0ull};
+  philox4x64_10(x, seed, 0ull);
+  int j = b;
+  if (B >= 2 && (x[0] >> 11) < thr53) {
+    j = b + 1 + (int)__umul64hi(x[1], (uint64_t)(B - 1));
+    if (j >= B) j -= B;
+  }
+  const T* __restrict__ g = x_g + (int64_t)j * ld_g;
+  for (int c = lane; c < ld_g; c += 64) xg_out[(int64_t)b * ld_g + c] = g[c];
+  const T* __restrict__ sg = x_sg + (int64_t)b * ld_sg;
+  for (int c = lane; c < ld_sg; c += 64) {
+    T v = sg[c];
+    if (c >= d_s && c < d_s + d_g) v = g[c - d_s];
+    xsg_out[(int64_t)b * ld_sg + c] = v;
+  }
+}
+
+hipError_t launch_goal_mix(const void* x_g, int ld_g, const void* x_sg, int ld_sg, int d_s,
+                           int d_g, uint64_t seed, const int64_t* step, uint64_t thr53, int B,
+                           void* xg_out, void* xsg_out, bool bf16, hipStream_t s) {
+  dim3 grid((B + 3) / 4), block(256);
+  const double bytes = 2.0 * B * (ld_g + ld_sg) * (bf16 ? 2.0 : 4.0);
+  if (bf16)
+    CRL_TIMED("goal_mix_kernel", 0.0, bytes, s,
+      goal_mix_kernel<bf16_t><<<grid, block, 0, s>>>((const bf16_t*)x_g, ld_g,
+        (const bf16_t*)x_sg, ld_sg, d_s, d_g, seed, step, thr53, B, (bf16_t*)xg_out,
+        (bf16_t*)xsg_out));
+  else
+    CRL_TIMED("goal_mix_kernel", 0.0, bytes, s,
+      goal_mix_kernel<float><<<grid, block, 0, s>>>((const float*)x_g, ld_g,
+        (const float*)x_sg, ld_sg, d_s, d_g, seed, step, thr53, B, (float*)xg_out,
+        (float*)xsg_out));
+  return hipGetLastError();
+}
+
 hipError_t launch_actor_loss(const float* logpi, const float* f, int B, const float* log_alpha,
                              float target_entropy, float* loss_out, float* alpha_grad,
                              hipStream_t s) {

@@ -134,6 +134,8 @@ struct crl_ctx {
   int64_t rowterm, rowaux, uphi, upsi;  // pairwise objectives; cosine unit rows
   int64_t phi_b, psi_b, row_m, row_s, col_m, col_s, dx_part, rs_part;
   int64_t xsa2, noise, logpi, fpol, dact;  // actor step
+  int64_t xg_mix, xsg_mix;                 // random-goal inputs of the actor step, or -1
+  uint64_t mix_thr;                        // floor(random_goal_ratio * 2^53)
   int ldd;                                 // row stride of dact
   int ln_rows_per_wave, ln_nparts, rchunks;
   int ldF;                     // row stride of the materialised logits
@@ -147,8 +149,10 @@ namespace {
 
 int validate(const crl_config* c) {
   if (!c) return fail(CRL_EINVAL, "config is NULL");
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
     if (c->reserved[i] != 0) return fail(CRL_EINVAL, "reserved config fields must be zero");
+  if (!(c->random_goal_ratio >= 0.0 && c->random_goal_ratio <= 1.0))
+    return fail(CRL_EINVAL, "random_goal_ratio must lie in [0, 1]");
   if (c->batch < 1 || c->batch > 65536) return fail(CRL_EINVAL, "batch must be in [1, 65536]");
   if (c->obs_dim < 1 || c->act_dim < 0 || c->goal_dim < 1)
     return fail(CRL_EINVAL, "obs_dim >= 1, act_dim >= 0, goal_dim >= 1 required");
@@ -523,6 +527,8 @@ void plan_workspace(crl_ctx* x) {
     x->rs_part = take((int64_t)2 * S * B * 4);
   }
   x->xsa2 = x->noise = x->logpi = x->fpol = x->dact = -1;
+  x->xg_mix = x->xsg_mix = -1;
+  x->mix_thr = 0;
   x->ldd = 0;
   if (x->actor) {
     x->ldd = (int)align_up(x->A, 8);
@@ -531,6 +537,12 @@ void plan_workspace(crl_ctx* x) {
     x->logpi = take(B * 4);
     x->fpol = take(B * 4);
     x->dact = take(B * x->ldd * 4);
+    // r * 2^53 is exact in double (a power-of-two scaling of r <= 1)
+    x->mix_thr = (uint64_t)std::floor(x->cfg.random_goal_ratio * 9007199254740992.0);
+    if (x->mix_thr > 0) {
+      x->xg_mix = take(B * x->net[1].ld_in * x->esz);
+      x->xsg_mix = take(B * x->ld_sg * x->esz);
+    }
   }
   x->ws_bytes = align_up(off, 256);
 
@@ -1126,6 +1138,44 @@ CRL_API int crl_sample_relabel(crl_ctx* x, const float* obs, const float* act, i
   return CRL_OK;
 }
 
+CRL_API int crl_replay_insert(float* obs, float* act, int32_t* traj, int32_t E, int32_t C,
+                              int32_t d_s, int32_t d_a, const float* new_obs,
+                              const float* new_act, const int32_t* new_traj, int32_t U,
+                              int64_t* count, void* stream) {
+  if (!obs || !traj || !new_obs || !new_traj || !count)
+    return fail(CRL_EINVAL, "NULL buffer argument");
+  if (d_a > 0 && (!act || !new_act)) return fail(CRL_EINVAL, "act is NULL");
+  if (E < 1 || C < 2) return fail(CRL_EINVAL, "need num_envs >= 1 and capacity >= 2");
+  if (d_s < 1 || d_a < 0) return fail(CRL_EINVAL, "bad row widths %d, %d", d_s, d_a);
+  if (U < 1 || U > C) return fail(CRL_EINVAL, "steps %d outside [1, capacity %d]", U, C);
+  if ((int64_t)U * E > INT32_MAX / 4 || (int64_t)E * C > INT32_MAX)
+    return fail(CRL_EINVAL, "chunk or ring too large");
+  CRL_HIP(launch_replay_insert(obs, act, traj, E, C, d_s, d_a, new_obs, new_act, new_traj, U,
+                               count, (hipStream_t)stream),
+          "replay insert launch");
+  return CRL_OK;
+}
+
+CRL_API int crl_ring_sample_relabel(crl_ctx* x, const float* obs, const float* act,
+                                    const int32_t* traj, int32_t E, int32_t C,
+                                    const int64_t* count, uint64_t seed, const int64_t* step,
+                                    int32_t* idx, void* x_sa, void* x_g, void* x_sg,
+                                    void* stream) {
+  if (!x) return fail(CRL_EINVAL, "NULL context");
+  if (!obs || !traj || !count || !step || !idx || !x_sa || !x_g)
+    return fail(CRL_EINVAL, "NULL buffer argument");
+  if (!act && x->cfg.act_dim > 0) return fail(CRL_EINVAL, "act is NULL");
+  if (E < 1 || C < 2) return fail(CRL_EINVAL, "need num_envs >= 1 and capacity >= 2");
+  if ((int64_t)E * C > INT32_MAX) return fail(CRL_EINVAL, "ring too large");
+  CRL_TRY(check_device(x));
+  CRL_HIP(launch_ring_relabel(obs, act, traj, E, C, count, x->cfg.obs_dim, x->cfg.act_dim,
+                              x->cfg.goal_dim, x->cfg.goal_lo, seed, step, x->d_thr,
+                              x->cfg.max_episode_len - 2, x->B, idx, x_sa, x->net[0].ld_in, x_g,
+                              x->net[1].ld_in, x_sg, x->ld_sg, x->bf16, (hipStream_t)stream),
+          "ring relabel launch");
+  return CRL_OK;
+}
+
 CRL_API int crl_critic_fwd(crl_ctx* x, const float* params, const uint16_t* params_bf16,
                            const void* x_sa, const void* x_g, void* ws, float* loss_out,
                            void* stream) {
@@ -1273,6 +1323,14 @@ CRL_API int crl_actor_step(crl_ctx* x, const float* params, const uint16_t* para
   float* dact = WF(ws, x->dact);
   const float* pout = WF(ws, x->sl[2].out);
 
+  // random goals: the policy and psi see the mixed goals
+  if (x->mix_thr > 0) {
+    CRL_HIP(launch_goal_mix(x_g, x->net[1].ld_in, x_sg, x->ld_sg, x->cfg.obs_dim,
+                            x->cfg.goal_dim, seed, step, x->mix_thr, B, W(ws, x->xg_mix),
+                            W(ws, x->xsg_mix), x->bf16, s), "random-goal mix");
+    x_g = W(ws, x->xg_mix);
+    x_sg = W(ws, x->xsg_mix);
+  }
   // policy MLP on [s, g], then the sampled action and log pi
   NetCall pol = {2, x_sg, x->ld_sg, actor_params, apb, actor_grads, nullptr, 0, 0, 0};
   CRL_TRY(mlp_forward(x, &pol, 1, ws, s));

@@ -53,6 +53,17 @@ hipError_t launch_relabel(const float* obs, const float* act, int E, int T,
                           int32_t* idx, void* x_sa, int ld_sa, void* x_g, int ld_g,
                           void* x_sg, int ld_sg, bool bf16, hipStream_t s);
 
+// replay.hip: the ring buffer
+hipError_t launch_replay_insert(float* obs, float* act, int32_t* traj, int E, int C, int d_s,
+                                int d_a, const float* nobs, const float* nact,
+                                const int32_t* ntraj, int U, int64_t* count, hipStream_t s);
+hipError_t launch_ring_relabel(const float* obs, const float* act, const int32_t* traj, int E,
+                               int C, const int64_t* count, int d_s, int d_a, int d_g,
+                               int goal_lo, uint64_t seed, const int64_t* step,
+                               const uint64_t* thr, int n_thr, int B, int32_t* idx, void* x_sa,
+                               int ld_sa, void* x_g, int ld_g, void* x_sg, int ld_sg, bool bf16,
+                               hipStream_t s);
+
 struct LnArgs {
   const void* Z[2];     // [B][N] pre-LN values
   void* H[2];           // [B][N] Swish(LN(z)) out
@@ -212,6 +223,11 @@ hipError_t launch_actor_energy(const float* phi, const float* psi, int D, int en
 hipError_t launch_actor_head_bwd(const float* out, int ldo, int A, const float* eps,
                                  const float* da, int ldd, const float* log_alpha, float* dout,
                                  void* dout_t, int B, bool bf16, hipStream_t s);
+// random goals: xg_out[b] = x_g[j], xsg_out[b] = [x_sg[b][0:d_s], x_g[j], 0...]
+// with j the partner drawn for b (j = b when b is not mixed)
+hipError_t launch_goal_mix(const void* x_g, int ld_g, const void* x_sg, int ld_sg, int d_s,
+                           int d_g, uint64_t seed, const int64_t* step, uint64_t thr53, int B,
+                           void* xg_out, void* xsg_out, bool bf16, hipStream_t s);
 hipError_t launch_actor_loss(const float* logpi, const float* f, int B, const float* log_alpha,
                              float target_entropy, float* loss_out, float* alpha_grad,
                              hipStream_t s);

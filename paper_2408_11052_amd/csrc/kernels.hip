@@ -1,6 +1,7 @@
 // Relabel/gather, LayerNorm+Swish, column reductions, materialised InfoNCE,
 // Adam and small utility kernels (gfx950, wave64).
 #include "internal.hpp"
+#include "relabel.hpp"
 
 namespace crl {
 
@@ -15,45 +16,13 @@ __global__ __launch_bounds__(256) void relabel_kernel(
   const int lane = threadIdx.x & 63;
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (b >= B) return;
-  // the first level of the threshold search probes the same 64 entries for
-  // every sample: fetch them while the counter is read and Philox runs
-  const int n_thr = T_ - 2;
-  const int step0 = (n_thr + 63) >> 6;
-  const int q0 = lane * step0;
-  const uint64_t thr0 = (n_thr > 64 && q0 < n_thr) ? thr[q0] : 0ull;
+  const GeomProbe probe = geom_prefetch(thr, T_ - 2, lane);
   uint64_t x[4] = {(uint64_t)b, (uint64_t)(*step), 0ull, 0ull};
   philox4x64_10(x, seed, 0ull);
   const int e = (int)__umul64hi(x[0], (uint64_t)E);
   const int t = (int)__umul64hi(x[1], (uint64_t)(T_ - 1));
-  // k = 1 + #{m in [1, T-2] : w2 < thr[m]}; the table is non-increasing, so
-  // the count is the length p of its prefix that exceeds w2.  64-way search:
-  // the lanes probe 64 evenly spaced entries of [lo, hi) at once, and the
-  // number of probes above w2 narrows p to one gap between probes.
-  const uint64_t w2 = x[2];
-  int lo = 0, hi = n_thr;  // p in [lo, hi]
-  if (hi - lo > 64) {  // first level from the prefetched probes
-    const bool above = q0 < hi && thr0 > w2;
-    const int c = __popcll(__ballot(above));
-    const int nlo = c > 0 ? (c - 1) * step0 + 1 : 0;
-    hi = min(hi, c * step0);
-    lo = nlo;
-  }
-  while (hi - lo > 64) {
-    const int step = (hi - lo + 63) >> 6;
-    const int q = lo + lane * step;
-    const bool above = q < hi && thr[q] > w2;
-    const int c = __popcll(__ballot(above));  // probes 0..c-1 are above w2
-    const int nlo = c > 0 ? lo + (c - 1) * step + 1 : lo;
-    const int qc = lo + c * step;             // first probe not above (or past hi)
-    hi = min(hi, qc);
-    lo = nlo;
-  }
-  {
-    const int q = lo + lane;
-    const bool above = q < hi && thr[q] > w2;
-    lo += __popcll(__ballot(above));
-  }
-  const int tg = min(t + 1 + lo, T_ - 1);
+  const int km1 = geom_count(thr, probe, x[2], lane);  // k - 1
+  const int tg = min(t + 1 + km1, T_ - 1);
   if (lane == 0) {
     idx[3 * b + 0] = e;
     idx[3 * b + 1] = t;
@@ -62,18 +31,8 @@ __global__ __launch_bounds__(256) void relabel_kernel(
   const float* s_row = obs + ((int64_t)e * T_ + t) * d_s;
   const float* a_row = act + ((int64_t)e * T_ + t) * d_a;
   const float* g_row = obs + ((int64_t)e * T_ + tg) * d_s + goal_lo;
-  for (int c = lane; c < ld_sa; c += 64) {
-    float v = c < d_s ? s_row[c] : (c < d_s + d_a ? a_row[c - d_s] : 0.f);
-    x_sa[(int64_t)b * ld_sa + c] = Store<T>::from_f(v);
-  }
-  for (int c = lane; c < ld_g; c += 64)
-    x_g[(int64_t)b * ld_g + c] = Store<T>::from_f(c < d_g ? g_row[c] : 0.f);
-  if (x_sg) {
-    for (int c = lane; c < ld_sg; c += 64) {
-      float v = c < d_s ? s_row[c] : (c < d_s + d_g ? g_row[c - d_s] : 0.f);
-      x_sg[(int64_t)b * ld_sg + c] = Store<T>::from_f(v);
-    }
-  }
+  write_inputs<T>(s_row, a_row, g_row, d_s, d_a, d_g, b, lane, x_sa, ld_sa, x_g, ld_g, x_sg,
+                  ld_sg);
 }
 
 hipError_t launch_relabel(const float* obs, const float* act, int E, int T, int d_s,

@@ -9,25 +9,37 @@ advanced by the library on the stream, so the same enqueued sequence can be
 captured once into a HIP graph and replayed for consecutive updates.  In the
 critic-only update t is n itself: n is advanced once the relabelling has read
 it, so the Adam step of update k sees k + 1, as a separate step counter would.
+
+The batch comes either from a static buffer of one episode per environment
+row, or from a ReplayRing; with a ring, ``capture_iteration`` records one
+training iteration of Algorithm 1's outer loop as a graph: the append of a
+freshly unrolled chunk of every environment's steps followed by a given
+number of updates on the grown buffer (the update-to-data ratio).
 """
 from __future__ import annotations
 
 import torch
 
 from .critic import Critic, crl_adam_step, crl_cast_bf16, crl_counter_add
+from .replay import ReplayRing
 
 
 class CriticUpdate:
     """Device state of the critic update: parameters, Adam moments, batch."""
 
-    def __init__(self, w, obs: torch.Tensor, act: torch.Tensor, phi_layers, psi_layers,
+    def __init__(self, w, obs, act, phi_layers, psi_layers,
                  seed: int = 2, lr: float | None = None, device="cuda:0"):
+        """obs, act: the static buffer [E][T][d] (one episode per row), or
+        obs a ReplayRing and act None (goals clipped to the longest episode
+        w.episode_len and to the end of the drawn step's trajectory)."""
         self.w = w
         self.dev = torch.device(device)
-        self.obs, self.act = obs, act
+        self.ring = obs if isinstance(obs, ReplayRing) else None
+        self.obs, self.act = (None, None) if self.ring is not None else (obs, act)
         self.seed = int(seed)
         self.lr = float(w.critic_lr if lr is None else lr)
-        self.crit = Critic(w, max_episode_len=obs.shape[1])
+        max_len = w.episode_len if self.ring is not None else obs.shape[1]
+        self.crit = Critic(w, max_episode_len=max_len)
         c = self.crit
         self.params = torch.from_numpy(c.pack(phi_layers, psi_layers)).to(self.dev)
         self.pbf = None
@@ -46,8 +58,11 @@ class CriticUpdate:
 
     def _critic_grads(self, x_sg):
         c = self.crit
-        c.crl_sample_relabel(self.obs, self.act, self.seed, self.n, self.idx, self.x_sa,
-                             self.x_g, x_sg)
+        if self.ring is not None:
+            self.ring.sample_relabel(c, self.seed, self.n, self.idx, self.x_sa, self.x_g, x_sg)
+        else:
+            c.crl_sample_relabel(self.obs, self.act, self.seed, self.n, self.idx, self.x_sa,
+                                 self.x_g, x_sg)
         c.crl_critic_fwd(self.params, self.pbf, self.x_sa, self.x_g, self.ws, self.loss)
         c.crl_critic_bwd(self.params, self.pbf, self.x_sa, self.x_g, self.ws, self.grads)
 
@@ -72,6 +87,31 @@ class CriticUpdate:
         torch.cuda.current_stream().wait_stream(s)
         return g
 
+    def enqueue_iteration(self, new_obs, new_act, new_traj, updates: int):
+        """Append one chunk ([U][E][...], time-major) to the ring, then
+        `updates` consecutive updates on the grown buffer."""
+        if self.ring is None:
+            raise ValueError("iterations need a ReplayRing buffer")
+        self.ring.insert(new_obs, new_act, new_traj)
+        for _ in range(updates):
+            self.enqueue()
+
+    def capture_iteration(self, new_obs, new_act, new_traj, updates: int,
+                          iterations: int = 1) -> torch.cuda.CUDAGraph:
+        """A HIP graph of `iterations` x (append the chunk held in new_*,
+        then `updates` updates).  The chunk buffers are read at replay time,
+        so the caller refills them between replays as the environments
+        produce steps; the ring's count, n and t advance on the device."""
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(iterations):
+                    self.enqueue_iteration(new_obs, new_act, new_traj, updates)
+        torch.cuda.current_stream().wait_stream(s)
+        return g
+
     def close(self):
         self.crit.close()
 
@@ -84,8 +124,7 @@ class FullUpdate(CriticUpdate):
     have zero gradient and stay 0).
     """
 
-    def __init__(self, w, obs: torch.Tensor, act: torch.Tensor, phi_layers, psi_layers,
-                 actor_layers, seed: int = 2, log_alpha: float = 0.0, device="cuda:0"):
+    def __init__(self, w, obs, act, phi_layers, psi_layers, actor_layers, seed: int = 2, log_alpha: float = 0.0, device="cuda:0"):
         super().__init__(w, obs, act, phi_layers, psi_layers, seed=seed, device=device)
         c = self.crit
         if not c.has_actor:

@@ -152,7 +152,7 @@ def test_enums_follow_the_header():
 def test_reserved_fields_must_be_zero():
     from paper_2408_11052_amd.critic import make_config
     cfg = make_config(WL.SMALL_RELU)
-    cfg.reserved[3] = 1
+    cfg.reserved[1] = 1
     ctx = C.c_void_p()
     assert _lib.lib().crl_create(C.byref(cfg), C.byref(ctx)) == _lib.CRL_EINVAL
 

@@ -71,6 +71,9 @@ def _oracle_actor_step(w, obs, act, phi, psi, actor, log_alpha, step):
     _, x_sa, x_g, x_sg = orelabel.sample_relabel(obs, act, w.batch_size, w.discounting,
                                                  SEED_PHILOX, step, w.goal_lo, w.goal_dim)
     eps = oactor.box_muller_noise(SEED_PHILOX, step, w.batch_size, w.act_dim)
+    if w.random_goal_ratio > 0:
+        x_sg, x_g, _, _ = oactor.random_goal_mix(x_sg, x_g, w.obs_dim, w.random_goal_ratio,
+                                                 SEED_PHILOX, step)
     out = oactor.actor_loss_and_grads(_to64(actor), _to64(phi), _to64(psi), x_sg, x_g,
                                       x_sa[:, :w.obs_dim], eps, log_alpha, w)
     out["eps"] = eps
@@ -92,6 +95,14 @@ CASES = {
     "bf16_l2_ln_ragged": SMALL.with_(name="actor_bf16_ragged", precision="bf16", logits="fused",
                                      energy_function="l2", batch_size=264, hidden=(128, 128),
                                      actor_hidden=(96, 96, 96)),
+    # random goals (Appendix C): half, and all, of the policy's goals taken
+    # from other samples of the batch
+    "fp32_dot_ln_random_goals_half": SMALL.with_(name="actor_rg_half", random_goal_ratio=0.5),
+    "fp32_l2_relu_random_goals_all": SMALL.with_(name="actor_rg_all", energy_function="l2",
+                                                 activation="relu", random_goal_ratio=1.0),
+    "bf16_dot_ln_random_goals": SMALL.with_(name="actor_rg_bf16", precision="bf16",
+                                            logits="fused", batch_size=256, hidden=(128, 128),
+                                            actor_hidden=(128,) * 3, random_goal_ratio=0.3),
 }
 
 
@@ -176,6 +187,13 @@ def _trajectory(w, steps, tol_c, tol_a, perturb=0.1):
 def test_full_update_trajectory_fp32():
     """20 full updates at small shapes, FP32 GPU path against the FP64 oracle."""
     _trajectory(SMALL.with_(name="full_small_fp32", batch_size=160), 20, 1e-4, 1e-4)
+
+
+def test_full_update_trajectory_fp32_random_goals():
+    """10 full updates with half of the policy's goals taken from other
+    samples (Appendix C), FP32 GPU path against the FP64 oracle."""
+    _trajectory(SMALL.with_(name="full_small_fp32_rg", batch_size=160, random_goal_ratio=0.5),
+                10, 1e-4, 1e-4)
 
 
 def _oracle_from_gpu(ou, gu):
