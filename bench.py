@@ -16,6 +16,9 @@ from captured HIP graphs.  Beside it:
     from captured graphs;
   - the B=16384, D=256 L2-energy update (fused: its B x B logits are never
     stored) with its peak HBM use;
+  - training iterations on a ring replay buffer: append a freshly unrolled
+    chunk of every environment's steps, then a given number of updates (the
+    update-to-data ratio), each iteration one captured graph;
   - the FP64 oracle on the host cores, on a bounded sample.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
@@ -63,6 +66,15 @@ def parse():
                     help="updates timed on the large-batch fused workload (never materialises "
                          "the B x B logits)")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--others", default="b256_relu2x256_l2_sym,b1024_lnswish4x1024_l2_fwd",
+                    help="further workloads timed from graphs ('' = none)")
+    ap.add_argument("--no-rates", action="store_true")
+    ap.add_argument("--no-single-thread", action="store_true")
+    ap.add_argument("--utd", default="1,16",
+                    help="updates per appended chunk timed on the ring buffer ('' = none)")
+    ap.add_argument("--utd-iterations", type=int, default=24)
+    ap.add_argument("--ring-capacity", type=int, default=1000)
+    ap.add_argument("--unroll", type=int, default=62, help="steps per env per append")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -111,6 +123,39 @@ def kernel_table(upd, steps):
     return rows
 
 
+def host_description():
+    """CPU model and the BLAS behind numpy (threadpoolctl's view)."""
+    from threadpoolctl import threadpool_info
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = [f"{d.get('internal_api')} {d.get('version')} ({d.get('threading_layer', '?')} "
+            f"threads, {d.get('num_threads')} threads)"
+            for d in threadpool_info() if d.get("user_api") == "blas"]
+    return {"cpu_model": model, "blas": blas, "os_cpu_count": os.cpu_count()}
+
+
+def oracle_single_thread(w, obs, act, phi, psi):
+    """One FP64 oracle update with the BLAS limited to one thread (seconds)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import critic as ocritic
+    from oracle import relabel as orelabel
+    phi = [{k: a.astype(np.float64) for k, a in L.items()} for L in phi]
+    psi = [{k: a.astype(np.float64) for k, a in L.items()} for L in psi]
+    with threadpool_limits(limits=1, user_api="blas"):
+        t0 = time.perf_counter()
+        _, x_sa, x_g, _ = orelabel.sample_relabel(obs, act, w.batch_size, w.discounting, 2, 0,
+                                                  w.goal_lo, w.goal_dim)
+        ocritic.critic_loss_and_grads(phi, psi, x_sa, x_g, w)
+        return time.perf_counter() - t0
+
+
 def cpu_baseline(w, obs, act, phi, psi, budget_s):
     """The FP64 oracle's update on the host cores, on a bounded sample."""
     import numpy as np
@@ -144,6 +189,102 @@ def cpu_baseline(w, obs, act, phi, psi, budget_s):
             "kind": "oracle",
             "sample": f"{steps} full FP64 updates (relabel, critic fwd+bwd, Adam) of the "
                       f"same workload in {dt:.1f} s"}
+
+
+def other_workloads(names, dev, steps=100):
+    """Updates/s of further workloads (their own buffers), from graphs of 10."""
+    import torch
+    from paper_2408_11052_amd.update import CriticUpdate, critic_step_flops
+    from synthetic import WORKLOADS, buffer_for, critic_params_for
+    out = []
+    for name in names:
+        wo = WORKLOADS[name]
+        obs, act = buffer_for(wo, seed=0)
+        p, q = critic_params_for(wo, seed=1)
+        d_obs, d_act = torch.from_numpy(obs).to(dev), torch.from_numpy(act).to(dev)
+        u = CriticUpdate(wo, d_obs, d_act, p, q, seed=2)
+        dt, n = time_steps(u, steps, 5, 10)
+        fl = critic_step_flops(wo)["total"]
+        peak = PEAK_BF16_TFLOPS if wo.precision == "bf16" else PEAK_FP32_TFLOPS
+        out.append({"workload": name, "precision": wo.precision, "logits": wo.logits,
+                    "steps_per_s": round(n / dt, 2), "ms_per_step": round(1e3 * dt / n, 4),
+                    "tflops": round(fl * n / dt / 1e12, 3),
+                    "frac_of_peak": round(fl * n / dt / 1e12 / peak, 4)})
+        log(f"[bench] {name}: {n / dt:.1f} steps/s ({wo.precision})")
+        u.close()
+        del u, d_obs, d_act
+        torch.cuda.empty_cache()
+    return out
+
+
+def training_iterations(w, phi, psi, args, dev):
+    """Iterations of (append U steps of every env to the ring, then k updates)
+    on a ring of the headline workload's buffer size.  A pool of P chunks
+    (one continuous synthetic unroll, time-major) is resident in HBM; graph p
+    appends chunk p, so replaying the P graphs in turn cycles through the
+    pool.  The ring is filled to capacity before timing."""
+    import torch
+    from paper_2408_11052_amd import ReplayRing, crl_timing_enable, crl_timing_read, \
+        crl_timing_reset
+    from paper_2408_11052_amd.update import CriticUpdate, critic_step_flops
+    from synthetic.trajectories import unroll_stream
+    E, C, U, P = w.num_envs, args.ring_capacity, args.unroll, 4
+    log(f"[utd] ring {E} envs x {C} steps, chunks of {U} steps (pool of {P})")
+    t0 = time.perf_counter()
+    obs, act, traj = unroll_stream(E, P * U, w.obs_dim, w.act_dim, w.episode_len, seed=11)
+    pool = [(torch.from_numpy(obs[p * U:(p + 1) * U]).to(dev),
+             torch.from_numpy(act[p * U:(p + 1) * U]).to(dev),
+             torch.from_numpy(traj[p * U:(p + 1) * U]).to(dev)) for p in range(P)]
+    del obs, act, traj
+    log(f"[utd] chunk pool ready in {time.perf_counter() - t0:.1f} s")
+    ring = ReplayRing(E, C, w.obs_dim, w.act_dim, device=dev)
+    for i in range((C + U - 1) // U):
+        ring.insert(*pool[i % P])
+    torch.cuda.synchronize()
+    # the append alone, HIP-event timed
+    crl_timing_reset()
+    crl_timing_enable(True)
+    for i in range(P):
+        ring.insert(*pool[i])
+    torch.cuda.synchronize()
+    crl_timing_enable(False)
+    ins = [r for r in crl_timing_read() if r[0] == "replay_insert_kernel"]
+    crl_timing_reset()
+    out = {"workload": w.name, "num_envs": E, "ring_capacity": C, "unroll": U}
+    if ins:
+        _, la, kms, _, kby = ins[0]
+        out["insert_us"] = round(1e3 * kms / la, 2)
+        out["insert_gbs"] = round(kby / (kms * 1e-3) / 1e9, 1)
+        out["insert_mb"] = round(kby / la / 1e6, 1)
+    fl = critic_step_flops(w)["total"]
+    runs = []
+    for k in [int(x) for x in args.utd.split(",") if x]:
+        upd = CriticUpdate(w, ring, None, phi, psi, seed=2)
+        graphs = [upd.capture_iteration(*pool[p], updates=k) for p in range(P)]
+        for g in graphs:  # untimed
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.utd_iterations):
+            graphs[i % P].replay()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        its = args.utd_iterations / dt
+        runs.append({"updates_per_append": k, "iterations_per_s": round(its, 2),
+                     "updates_per_s": round(its * k, 2),
+                     "env_steps_per_s": round(its * E * U, 1),
+                     "ms_per_iteration": round(1e3 * dt / args.utd_iterations, 4),
+                     "tflops": round(fl * k * its / 1e12, 2),
+                     "loss": round(float(upd.loss[0]), 5)})
+        log(f"[utd] {k} updates per append: {its:.1f} iterations/s, {its * k:.1f} updates/s")
+        del graphs
+        upd.close()
+        del upd
+        torch.cuda.empty_cache()
+    out["runs"] = runs
+    del ring, pool
+    torch.cuda.empty_cache()
+    return out
 
 
 def source_digest(files) -> str:
@@ -354,11 +495,48 @@ def main():
         del lu, ld_obs, ld_act
         torch.cuda.empty_cache()
 
+    utd = None
+    if args.utd:
+        utd = training_iterations(w, phi, psi, args, dev)
+
+    others = None
+    if args.others:
+        others = other_workloads(args.others.split(","), dev)
+
+    rates = None
+    if not args.no_rates:
+        from paper_2408_11052_amd import crl_peak_rate
+        exp_rate = crl_peak_rate("exp")
+        fma_rate = crl_peak_rate("fma32")
+        rates = {"exp_per_s": exp_rate, "fma32_per_s": fma_rate,
+                 "fp32_vector_tflops_unpacked": round(2 * fma_rate / 1e12, 2)}
+        # the D = 64 InfoNCE kernels: two exponentials per critic-matrix entry
+        # (row and column log-sum-exp in the forward; P^r and P^c in the
+        # backward), so the exponential issue rate bounds them
+        exps = 2.0 * w.batch_size * w.batch_size
+        rk = []
+        for k in kernels:
+            if k["kernel"].startswith("infonce_"):
+                per = k["us_avg"] * 1e-6
+                rk.append({"kernel": k["kernel"], "exps_per_launch": exps,
+                           "us_per_launch": k["us_avg"],
+                           "achieved_exp_per_s": exps / per,
+                           "frac_of_exp_rate": round(exps / per / exp_rate, 4)})
+        rates["exp_bound_kernels"] = rk
+        log(f"[bench] measured rates: {exp_rate / 1e12:.2f} T exp/s, {fma_rate / 1e12:.2f} T "
+            f"FP32 FMA/s; " + ", ".join(f"{r['kernel']} {r['frac_of_exp_rate']:.1%} of the exp "
+                                         f"rate" for r in rk))
+
     cpu = None
     if not args.no_cpu:
         log(f"[bench] FP64 oracle on the host cores (~{args.cpu_seconds:.0f} s)")
         cpu = cpu_baseline(w, obs, act, phi, psi, args.cpu_seconds)
         log(f"[bench] oracle: {cpu['value']:.3f} steps/s on {cpu['cores']} threads")
+        cpu["host"] = host_description()
+        if not args.no_single_thread:
+            st = oracle_single_thread(w, obs, act, phi, psi)
+            cpu["single_thread_steps_per_s"] = round(1.0 / st, 4)
+            log(f"[bench] oracle, one BLAS thread: {st:.1f} s per update")
 
     out = {
         "metric": METRIC,
@@ -390,6 +568,9 @@ def main():
         "workspace_gib": round(ws_gib, 3),
         "full_update": full,
         "large_batch": large,
+        "training_iterations": utd,
+        "other_workloads": others,
+        "issue_rates": rates,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

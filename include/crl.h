@@ -412,6 +412,19 @@ CRL_API int crl_timing_read(int32_t index, char* name, int32_t name_len,
                             int64_t* launches, double* ms, double* flops,
                             double* bytes);
 
+/* Measured issue rate of one instruction kind on the current device, for
+ * the rooflines of kernels bound by it rather than by MFMA or HBM:
+ * CRL_RATE_EXP counts v_exp_f32 (the exponential of the log-sum-exp and
+ * softmax terms) per second, CRL_RATE_FMA32 FP32 fused multiply-adds per
+ * second (unpacked, as this library's vector code issues them).  Runs
+ * CRL_RATE_PROBE_BLOCKS workgroups of 256 lanes, each lane 8 independent
+ * chains of 4096 instructions, three times on `stream`, and reports the
+ * fastest; waits for the stream (not graph-capturable).  scratch: device
+ * FP32 [CRL_RATE_PROBE_BLOCKS * 256], overwritten. */
+enum { CRL_RATE_EXP = 0, CRL_RATE_FMA32 = 1 };
+#define CRL_RATE_PROBE_BLOCKS 8192
+CRL_API int crl_peak_rate(int32_t which, float* scratch, double* per_second, void* stream);
+
 /* Message for the last non-OK status returned on this thread. */
 CRL_API const char* crl_last_error(void);
 

@@ -7,6 +7,6 @@ call does, and fails loudly if it has not been built.
 """
 from ._lib import lib, CRLError, LIB_PATH  # noqa: F401
 from .critic import (Critic, CriticLoss, crl_adam_step, crl_cast_bf16,  # noqa: F401
-                     crl_check_finite, crl_counter_add, crl_replay_insert,
+                     crl_check_finite, crl_counter_add, crl_peak_rate, crl_replay_insert,
                      crl_timing_enable, crl_timing_read, crl_timing_reset, make_config)
 from .replay import ReplayRing  # noqa: F401

@@ -76,6 +76,7 @@ SIGNATURES = {
     "crl_timing_read": (C.c_int, [I32, C.c_char_p, I32, C.POINTER(I64),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]),
+    "crl_peak_rate": (C.c_int, [I32, P, C.POINTER(C.c_double), P]),
     "crl_last_error": (C.c_char_p, []),
 }
 

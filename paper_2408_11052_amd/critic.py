@@ -272,6 +272,16 @@ def crl_cast_bf16(src, dst, stream=None):
     check(lib().crl_cast_bf16(_ptr(src), _ptr(dst), src.numel(), _stream(stream)))
 
 
+def crl_peak_rate(which: str, stream=None) -> float:
+    """Measured instructions per second on the current device: "exp"
+    (v_exp_f32) or "fma32" (unpacked FP32 FMA).  Synchronises."""
+    kind = {"exp": 0, "fma32": 1}[which]
+    scratch = torch.empty(8192 * 256, dtype=torch.float32, device="cuda")
+    out = C.c_double()
+    check(lib().crl_peak_rate(kind, _ptr(scratch), C.byref(out), _stream(stream)))
+    return out.value
+
+
 def crl_timing_enable(enable: bool = True):
     check(lib().crl_timing_enable(1 if enable else 0))
 

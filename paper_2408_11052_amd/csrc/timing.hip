@@ -99,9 +99,59 @@ void timing_end(KTimer& t) {
   t.on = false;
 }
 
+// Issue-rate probes: every lane runs 8 independent chains of one instruction
+// (v_exp_f32 with a negated operand, which keeps the value in (1/2, 1), or an
+// FP32 fused multiply-add) so that latency is hidden by the other chains and
+// the other wavefronts; the sum of the chains is stored so nothing is elided.
+template <int KIND>
+__global__ __launch_bounds__(256) void rate_probe_kernel(float* __restrict__ out, int iters) {
+  float x[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) x[c] = 0.5f + 0.01f * (float)((threadIdx.x + c) & 7);
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (KIND == 0) x[c] = __builtin_amdgcn_exp2f(-x[c]);
+      else x[c] = __builtin_fmaf(x[c], 0.999f, 0.0005f);
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s += x[c];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace crl
 
 extern "C" {
+
+CRL_API int crl_peak_rate(int32_t which, float* scratch, double* per_second, void* stream) {
+  if (!scratch || !per_second || (which != CRL_RATE_EXP && which != CRL_RATE_FMA32))
+    return CRL_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int blocks = CRL_RATE_PROBE_BLOCKS, iters = 4096;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return CRL_EHIP;
+  int rc = CRL_OK;
+  float best = 0.f;
+  for (int rep = 0; rep < 3 && rc == CRL_OK; ++rep) {
+    if (hipEventRecord(a, s) != hipSuccess) { rc = CRL_EHIP; break; }
+    if (which == CRL_RATE_EXP)
+      crl::rate_probe_kernel<0><<<blocks, 256, 0, s>>>(scratch, iters);
+    else
+      crl::rate_probe_kernel<1><<<blocks, 256, 0, s>>>(scratch, iters);
+    if (hipGetLastError() != hipSuccess || hipEventRecord(b, s) != hipSuccess ||
+        hipEventSynchronize(b) != hipSuccess) { rc = CRL_EHIP; break; }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) { rc = CRL_EHIP; break; }
+    if (rep == 0 || ms < best) best = ms;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc != CRL_OK) return rc;
+  *per_second = (double)blocks * 256.0 * iters * 8.0 / (best * 1e-3);
+  return CRL_OK;
+}
 
 CRL_API int crl_timing_enable(int32_t enable) {
   std::lock_guard<std::mutex> lk(crl::g_mu);
