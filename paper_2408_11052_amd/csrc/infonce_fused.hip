@@ -21,6 +21,8 @@
 // unit rows; the reduction then projects out the row's own direction and
 // divides by its norm.  Each split writes its own partial, summed in a fixed
 // order afterwards (no atomics).
+#include <cmath>
+
 #include "internal.hpp"
 
 namespace crl {
@@ -140,20 +142,64 @@ __device__ __forceinline__ void tile_store_rows(bf16_t* __restrict__ Ys, const T
   }
 }
 
+// Exponentials are one v_exp_f32 (2^x) of a scaled argument: exp(x - m) is
+// exp2((x - m) * log2(e)) in the forward, where x = m must give exactly 1
+// (B = 1 gives r_i = F_ii exactly), and exp2(x * log2(e) - s) with the
+// shift s = lse * log2(e) + log2(B) formed once per row or column in the
+// backward.
+constexpr float kL2E = 1.4426950408889634f;  // log2(e)
+
+// Tile entry of the energy from v = <x_i, y_j> (norms nx, ny for the
+// distances), and for L2 the distance d (0 below the norm-expansion noise,
+// as l2_dist; the hardware square root, whose 1-ulp error is far below the
+// BF16 rounding of the operands).  A NaN operand stays NaN in f and d.
+template <int EN>
+__device__ __forceinline__ float energy_f(float v, float nx, float ny, float& d) {
+  if (EN == kEnL2) {
+    const float t = nx + ny;
+    const float d2 = __builtin_fmaf(-2.f, v, t);
+    d = d2 <= kL2Floor * t ? 0.f : __builtin_amdgcn_sqrtf(d2);
+    return -d;
+  }
+  if (EN == kEnL2sq) {
+    const float d2 = __builtin_fmaf(-2.f, v, nx + ny);
+    d = d2 < 0.f ? 0.f : d2;
+    return -d;
+  }
+  d = 0.f;
+  return v;
+}
+__device__ __forceinline__ float exp_diff(float x, float m) {
+  return __builtin_amdgcn_exp2f((x - m) * kL2E);
+}
+
+// Per workgroup: 64 rows (wave w: rows 16w + 4g + r of lane (r16, g), r < 4)
+// against the 64-column tiles of one column split.  Tiles inside the batch
+// on every side skip the masking, and only the tile that holds a wave's
+// diagonal entries looks for them (both are wave-uniform branches).
+// Occupancy targets (wavefronts per SIMD) that the register allocation must
+// meet: the forward's LDS holds three workgroups per CU at D = 256, the
+// backward passes need about 256 registers per lane there.
+template <int KS> constexpr int fwd_waves() { return KS >= 8 ? 3 : 4; }
+template <int KS> constexpr int bwd_waves() { return KS >= 4 ? 2 : 4; }
+
 template <int KS, int EN>
-__global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, int cps) {
+__global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(FusedArgs a, int B, int cps) {
   constexpr bool L2 = EN != kEnDot;
   constexpr int D = KS * 32;
   constexpr int LDY = D + 8;
+  constexpr int LDC = kFCols + 16;  // column-partial rows: 64 lanes over 32 banks, 2 per bank
   __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDY];
   // column (max, sum) of each (wave, 4-row group) for the current tile
-  __shared__ float cm_s[16][kFCols], cs_s[16][kFCols];
+  __shared__ float cm_s[16][LDC], cs_s[16][LDC];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   const int rb = blockIdx.x;
   const int row_base = rb * kFRows + wave * 16;
   const int c0 = blockIdx.y * cps, c1 = min(B, c0 + cps);
+  const bool rows_full = row_base + 16 <= B;
 
   bf16x8 xa[KS];
   {
@@ -175,22 +221,24 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
     rsum[r] = 0.f;
   }
 
-  // column (max, sum) partials of the previous tile, merged over the 16
+  // column (max, sum) partials of a finished tile, merged over the 16
   // (wave, row group) entries: their max first, then the rescaled sums in a
-  // fixed order (independent exponentials instead of a chain of merges)
+  // fixed order.  The tiles' merges rotate over the four waves.
   auto flush_cols = [&](int jp) {
-    if (tid < kFCols && jp + tid < c1) {
+    const int col = jp + lane;
+    if (col < c1) {
       float mv[16], sv[16];
 #pragma unroll
-      for (int w = 0; w < 16; ++w) { mv[w] = cm_s[w][tid]; sv[w] = cs_s[w][tid]; }
+      for (int w = 0; w < 16; ++w) { mv[w] = cm_s[w][lane]; sv[w] = cs_s[w][lane]; }
       float cm = mv[0];
 #pragma unroll
       for (int w = 1; w < 16; ++w) cm = fmaxf(cm, mv[w]);
       float cs = 0.f;
 #pragma unroll
-      for (int w = 0; w < 16; ++w) cs += sv[w] == 0.f ? 0.f : sv[w] * __expf(mv[w] - cm);
-      a.col_m[(int64_t)rb * B + jp + tid] = cm;
-      a.col_s[(int64_t)rb * B + jp + tid] = cs;
+      for (int w = 0; w < 16; ++w)
+        cs += sv[w] == 0.f ? 0.f : sv[w] * exp_diff(mv[w], cm);
+      a.col_m[(int64_t)rb * B + col] = cm;
+      a.col_s[(int64_t)rb * B + col] = cs;
     }
   };
   // the prefetch is unconditional (clamped to the last tile) so the wait
@@ -206,9 +254,10 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
     }
   };
   if (c0 < c1) { tile_load<D>(pf, a.psi_b, c0, B, tid); ny_load(c0); }
-  for (int j0 = c0; j0 < c1; j0 += kFCols) {
+  int t = 0;
+  for (int j0 = c0; j0 < c1; j0 += kFCols, ++t) {
     __syncthreads();
-    if (j0 > c0) flush_cols(j0 - kFCols);
+    if (j0 > c0 && wave == ((t - 1) & 3)) flush_cols(j0 - kFCols);
     tile_store_rows<D, LDY>(Ys, pf, tid);
     float nyv[4];
 #pragma unroll
@@ -226,53 +275,60 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
         acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b, acc[jb], 0, 0, 0);
       }
     }
-    // energies; invalid rows/columns become -inf
     float f[4][4];
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      const int col = j0 + jb * 16 + r16;
-      const bool cv = col < c1;
-      const float ny = nyv[jb];
+    for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float v = acc[jb][r];
-        if (EN == kEnL2) v = -l2_dist(nx[r], ny, v);
-        if (EN == kEnL2sq) v = -l2sq_dist(nx[r], ny, v);
-        f[jb][r] = (cv && rvalid[r]) ? v : -INFINITY;
-        const int row = row_base + 4 * g + r;
-        if (cv && rvalid[r] && row == col) a.diag[row] = v;
+        float d;
+        f[jb][r] = energy_f<EN>(acc[jb][r], nx[r], nyv[jb], d);
+      }
+    if (j0 <= row_base && row_base < j0 + kFCols) {  // this wave's diagonal entries
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row_base + 4 * g + r;
+          if (row == j0 + jb * 16 + r16 && row < c1 && rvalid[r]) a.diag[row] = f[jb][r];
+        }
+    }
+    const bool edge = !rows_full || j0 + kFCols > c1;
+    if (edge) {  // entries outside the batch or the split become -inf
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        const bool cv = j0 + jb * 16 + r16 < c1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) f[jb][r] = (cv && rvalid[r]) ? f[jb][r] : -INFINITY;
       }
     }
     // rows: online (max, sum)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      float ml = fmaxf(fmaxf(f[0][r], f[1][r]), fmaxf(f[2][r], f[3][r]));
-      if (ml > rm[r]) {
-        rsum[r] = (rm[r] == -INFINITY) ? 0.f : rsum[r] * __expf(rm[r] - ml);
-        rm[r] = ml;
-      }
-      if (rm[r] != -INFINITY) {
+      const float ml = fmaxf(__builtin_fmaxf(f[0][r], f[1][r]), __builtin_fmaxf(f[2][r], f[3][r]));
+      const float nm = fmaxf(rm[r], ml);
+      float sr = rsum[r] * exp_diff(rm[r], nm);
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) rsum[r] += __expf(f[jb][r] - rm[r]);
-      }
+      for (int jb = 0; jb < 4; ++jb) sr += exp_diff(f[jb][r], nm);
+      if (edge) sr = nm == -INFINITY ? 0.f : sr;  // nothing of this row seen yet
+      rsum[r] = sr;
+      rm[r] = nm;
     }
     // columns: (max, sum) over this lane's 4 rows, one entry per (wave, row
-    // group); flush_cols merges the 16 entries after the next barrier
+    // group); the merge runs after the next barrier
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
-      float cm = fmaxf(fmaxf(f[jb][0], f[jb][1]), fmaxf(f[jb][2], f[jb][3]));
+      const float cm = fmaxf(__builtin_fmaxf(f[jb][0], f[jb][1]), __builtin_fmaxf(f[jb][2], f[jb][3]));
       float cs = 0.f;
-      if (cm != -INFINITY) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) cs += __expf(f[jb][r] - cm);
-      }
+      for (int r = 0; r < 4; ++r) cs += exp_diff(f[jb][r], cm);
+      if (edge) cs = cm == -INFINITY ? 0.f : cs;
       cm_s[wave * 4 + g][jb * 16 + r16] = cm;
       cs_s[wave * 4 + g][jb * 16 + r16] = cs;
     }
   }
   if (c0 < c1) {
     __syncthreads();
-    flush_cols(c0 + ((c1 - c0 - 1) / kFCols) * kFCols);
+    if (wave == ((t - 1) & 3)) flush_cols(jlast);
   }
   // merge the row states across the 16 lanes that share each row: the max
   // by a butterfly, then the sums rescaled to it by a butterfly (every lane
@@ -286,7 +342,7 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
     for (int r = 0; r < 4; ++r) mrow[r] = fmaxf(mrow[r], __shfl_xor(mrow[r], o, 64));
 #pragma unroll
   for (int r = 0; r < 4; ++r)
-    srow[r] = rsum[r] == 0.f ? 0.f : rsum[r] * __expf(rm[r] - mrow[r]);
+    srow[r] = rsum[r] == 0.f ? 0.f : rsum[r] * exp_diff(rm[r], mrow[r]);
 #pragma unroll
   for (int o = 1; o <= 8; o <<= 1)
 #pragma unroll
@@ -307,20 +363,31 @@ __global__ __launch_bounds__(256) void infonce_fwd_kernel(FusedArgs a, int B, in
 // Per 64-column tile: F (MFMA), G (or H) into the wave's own LDS strip, then
 // dX += G . Y with the Y operand read from the row-major tile by the 16-bit
 // transpose read (no transposed copy of the tile is kept).  The tile's
-// column values (the other side's LSE, its penalty factor, |y|^2) are
-// fetched together with the tile, one tile ahead.
+// column values (the other side's LSE, |y|^2) are fetched together with the
+// tile, one tile ahead.
+//
+// Entry (i, j) of G (rows pass; the columns pass exchanges the roles) is
+//   P^r_ij (wf + 2 beta r_i) / B + wb P^c_ij / B - (wf + wb) delta_ij / B,
+// and each P / B is one exp2 of f log2(e) - (lse log2(e) + log2 B), the shifts
+// formed once per row and per column: the weight wb (0 or 1) of the other
+// direction is folded into its shift (+inf when it is 0).  The strip is kept
+// transposed, [column][row], so that each lane stores its four rows of a
+// column as one 8-byte write; the transpose read gives back the row-major A
+// operand of the product.
 template <int KS, int EN, int TRANS>
-__global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, int cps,
-                                                          float beta, float wf, float wb) {
+__global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(FusedArgs a, int B, int cps,
+                                                          float beta, float wf, float wb,
+                                                          float log2b) {
   constexpr bool L2 = EN != kEnDot;
   constexpr int D = KS * 32;
   constexpr int LDY = D + 8;
-  constexpr int LDT = kFCols + 8;
+  constexpr int LDG = 16;     // transposed G strip: [64 columns][16 rows]
   constexpr int NB = D / 16;  // 16-wide output blocks of dX
   typedef short v4s __attribute__((ext_vector_type(4)));
   typedef short v8s __attribute__((ext_vector_type(8)));
+  typedef __attribute__((address_space(3))) v4s lds_v4s;
   __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDY];
-  __shared__ __attribute__((aligned(16))) bf16_t Gs[4][16 * LDT];
+  __shared__ __attribute__((aligned(16))) bf16_t Gt[4][kFCols * LDG];
 
   const bf16_t* Xb = TRANS ? a.psi_b : a.phi_b;
   const bf16_t* Yb = TRANS ? a.phi_b : a.psi_b;
@@ -330,12 +397,21 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
   const float* lseX = TRANS ? a.c : a.r;
   const float* lseY = TRANS ? a.r : a.c;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   const int rb = blockIdx.x;
   const int row_base = rb * kFRows + wave * 16;
   const int c0 = blockIdx.y * cps, c1 = min(B, c0 + cps);
-  const float inv = 1.f / (float)B;
+  const bool rows_full = row_base + 16 <= B;
+  const float beta2 = 2.f * beta;
+  const float dgv = (wf + wb) / (float)B;  // the diagonal's -delta_ij terms
+  // shift and weight of the row direction (the penalty rides on the rows'
+  // own LSE r_i) and the shift of the column direction, folded with wb
+  auto main_shift = [&](float lse) { return __builtin_fmaf(lse, kL2E, log2b); };
+  auto other_shift = [&](float lse) {
+    return wb != 0.f ? __builtin_fmaf(lse, kL2E, log2b) : INFINITY;
+  };
 
   bf16x8 xa[KS];
   {
@@ -346,18 +422,16 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
       else xa[ks] = bf16x8{};
     }
   }
-  // the penalty factor 2 beta r_i is formed from the row LSE where it is
-  // used (lse_a for the rows pass, the column values for the columns pass):
-  // fewer live registers keep the D = 256 kernels at two waves per SIMD
-  const float beta2 = 2.f * beta;
-  float nx[4], lse_a[4], hsum[4];
+  float nx[4], sh_a[4], k_a[4], hsum[4];
   bool rvalid[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = row_base + 4 * g + r;
     rvalid[r] = row < B;
     nx[r] = (L2 && rvalid[r]) ? nX[row] : 0.f;
-    lse_a[r] = rvalid[r] ? lseX[row] : 0.f;
+    const float l = rvalid[r] ? lseX[row] : 0.f;
+    sh_a[r] = TRANS ? other_shift(l) : main_shift(l);
+    k_a[r] = wf + beta2 * l;  // used by the rows pass only
     hsum[r] = 0.f;
   }
   floatx4 acc_dx[NB];
@@ -397,56 +471,74 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
         acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b, acc[jb], 0, 0, 0);
       }
     }
-    // G (or H = G/d for L2) for this tile, into the wave's own LDS strip
+    float sh_b[4], k_b[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
-      const int col = j0 + jb * 16 + r16;
-      const bool cv = col < c1;
+      sh_b[jb] = TRANS ? main_shift(cvals.lse[jb]) : other_shift(cvals.lse[jb]);
+      k_b[jb] = wf + beta2 * cvals.lse[jb];  // used by the columns pass only
+    }
+    const bool edge = !rows_full || j0 + kFCols > c1;
+    const bool diag = j0 <= row_base && row_base < j0 + kFCols;
+    // one 16-column block at a time: its four rows' G, the diagonal and edge
+    // terms, H, the rows' sums and the strip store
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      float h[4], dd[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row_base + 4 * g + r;
-        float v = acc[jb][r];
-        float d = 0.f;
-        if (EN == kEnL2) { d = l2_dist(nx[r], cvals.ny[jb], v); v = -d; }
-        if (EN == kEnL2sq) v = -l2sq_dist(nx[r], cvals.ny[jb], v);
-        float gv = 0.f;
-        if (cv && rvalid[r]) {
-          const float dl = (row == col) ? 1.f : 0.f;
-          // the softmax over this pass's own rows (pa) and over its columns (pb)
-          const float pa = __expf(v - lse_a[r]);
-          const float pb = __expf(v - cvals.lse[jb]);
-          if (TRANS == 0) {
-            gv = pa * (wf + beta2 * lse_a[r]) - wf * dl + wb * (pb - dl);
-          } else {
-            gv = pb * (wf + beta2 * cvals.lse[jb]) - wf * dl + wb * (pa - dl);
-          }
-          gv *= inv;
-          if (EN == kEnL2) gv = d > 0.f ? gv * __builtin_amdgcn_rcpf(d) : 0.f;
-          if (EN == kEnL2sq) gv *= 2.f;
-        }
-        hsum[r] += gv;
-        Gs[wave][(4 * g + r) * LDT + jb * 16 + r16] = f2bf(gv);
+        const float fv = energy_f<EN>(acc[jb][r], nx[r], cvals.ny[jb], dd[r]);
+        const float pa = __builtin_amdgcn_exp2f(__builtin_fmaf(fv, kL2E, -sh_a[r]));
+        const float pb = __builtin_amdgcn_exp2f(__builtin_fmaf(fv, kL2E, -sh_b[jb]));
+        h[r] = TRANS ? __builtin_fmaf(pb, k_b[jb], pa) : __builtin_fmaf(pa, k_a[r], pb);
       }
+      if (diag) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (row_base + 4 * g + r == j0 + jb * 16 + r16) h[r] -= dgv;
+      }
+      if (edge) {
+        const bool cv = j0 + jb * 16 + r16 < c1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[r] = (cv && rvalid[r]) ? h[r] : 0.f;
+      }
+      // H = G / d (L2; 0 where d = 0) or 2 G (L2 without the root)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (EN == kEnL2) h[r] = dd[r] > 0.f ? h[r] * __builtin_amdgcn_rcpf(dd[r]) : 0.f;
+        if (EN == kEnL2sq) h[r] *= 2.f;
+        hsum[r] += h[r];
+      }
+      uint2 w;
+      w.x = pack2bf(h[0], h[1]);
+      w.y = pack2bf(h[2], h[3]);
+      *reinterpret_cast<uint2*>(&Gt[wave][(jb * 16 + r16) * LDG + 4 * g]) = w;
     }
     // only this wave reads its strip back: a wave-local LDS wait suffices
     __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
     __builtin_amdgcn_wave_barrier();
-    // dX[16 rows][D] += G[16][64] . Y[64][D]; lane (g, j) needs Y[8g + 0..7][d]
-    // of column d = nb*16 + j: two transpose reads of 4 rows each
+    // dX[16 rows][D] += G[16][64] . Y[64][D]; lane (g, j) needs G[j][8g + 0..7]
+    // and Y[8g + 0..7][d] of column d = nb*16 + j: transpose reads of 4 rows
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      bf16x8 ga = *reinterpret_cast<const bf16x8*>(&Gs[wave][r16 * LDT + kk * 32 + g * 8]);
+      v4s gq[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+        gq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (lds_v4s*)(&Gt[wave][krow * LDG + 4 * (r16 & 3)]));
+      }
+      v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
+      const bf16x8 ga = __builtin_bit_cast(bf16x8, gv8);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        v4s h[2];
+        v4s hq[2];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const int jrow = kk * 32 + 8 * g + 4 * t + (r16 >> 2);
+        for (int q = 0; q < 2; ++q) {
+          const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
           const int dcol = nb * 16 + 4 * (r16 & 3);
-          h[t] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-              (__attribute__((address_space(3))) v4s*)(Ys + jrow * LDY + dcol));
+          hq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + jrow * LDY + dcol));
         }
-        v8s yv = {h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+        v8s yv = {hq[0][0], hq[0][1], hq[0][2], hq[0][3], hq[1][0], hq[1][1], hq[1][2], hq[1][3]};
         acc_dx[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, __builtin_bit_cast(bf16x8, yv),
                                                              acc_dx[nb], 0, 0, 0);
       }
@@ -478,33 +570,39 @@ __global__ __launch_bounds__(256) void infonce_bwd_kernel(FusedArgs a, int B, in
 // G once, and uses it twice:
 //   dphi[rows] += G . psi[tile]        (wave w: its 16 rows, as in the row pass)
 //   dpsi[tile]  = G^T . phi[rows]      (wave w: 16 columns x 16 features, K = 256)
-// phi's 256 rows and the G tile stay in LDS; both MFMA operands of the second
-// product come from 16-bit transpose reads.  dphi partials go to split
-// blockIdx.y (the column block), dpsi partials to split blockIdx.x (the row
-// block); for L2 the row and column sums of H go with them.
+// phi's 256 rows and the G tile stay in LDS, the tile transposed
+// ([column][row]: each lane stores its four rows of a column as one 8-byte
+// write); G^T rows are then plain 16-byte reads and the G strip of the first
+// product a transpose read, as is phi in the second.  dphi partials go to
+// split blockIdx.y (the column block), dpsi partials to split blockIdx.x (the
+// row block); for L2 the row and column sums of H go with them.  The entries
+// of G are formed as in infonce_bwd_kernel.
 constexpr int kBRows = 256;  // rows (and columns) per workgroup of the one-pass backward
 int fused_bwd_splits(int B) { return (B + kBRows - 1) / kBRows; }
 
 template <int EN>
 __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int B, float beta,
-                                                               float wf, float wb) {
+                                                               float wf, float wb, float log2b) {
   constexpr bool L2 = EN != kEnDot;
   constexpr int D = 64, KS = 2, NB = 4;
-  constexpr int LDX = D + 8;       // phi / psi rows in LDS (144 B)
-  constexpr int LDG = kFCols + 8;  // G rows in LDS
+  constexpr int LDX = D + 8;           // phi / psi rows in LDS (144 B)
+  constexpr int LDGT = kBRows + 8;     // transposed G rows (one per column of the tile)
   typedef short v4s __attribute__((ext_vector_type(4)));
   typedef short v8s __attribute__((ext_vector_type(8)));
   typedef __attribute__((address_space(3))) v4s lds_v4s;
   __shared__ __attribute__((aligned(16))) bf16_t Xs[kBRows * LDX];
   __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDX];
-  __shared__ __attribute__((aligned(16))) bf16_t Gs[kBRows * LDG];
+  __shared__ __attribute__((aligned(16))) bf16_t Gt[kFCols * LDGT];
   __shared__ float csum[16][kFCols];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   const int r0 = blockIdx.x * kBRows, cb0 = blockIdx.y * kBRows;
   const int row_base = r0 + wave * 16;
-  const float inv = 1.f / (float)B;
+  const bool rows_full = row_base + 16 <= B;
+  const float beta2 = 2.f * beta;
+  const float dgv = (wf + wb) / (float)B;
 
   // phi rows of the block -> LDS (rows past B are zero)
 #pragma unroll
@@ -524,15 +622,16 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
       else xa[ks] = bf16x8{};
     }
   }
-  float nx[4], lse_r[4], pen_r[4], hrow[4];
+  float nx[4], sh_r[4], k_r[4], hrow[4];
   bool rvalid[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = row_base + 4 * g + r;
     rvalid[r] = row < B;
     nx[r] = (L2 && rvalid[r]) ? a.nphi[row] : 0.f;
-    lse_r[r] = rvalid[r] ? a.r[row] : 0.f;
-    pen_r[r] = rvalid[r] ? 2.f * beta * a.r[row] : 0.f;
+    const float lr = rvalid[r] ? a.r[row] : 0.f;
+    sh_r[r] = __builtin_fmaf(lr, kL2E, log2b);
+    k_r[r] = wf + beta2 * lr;
     hrow[r] = 0.f;
   }
   floatx4 acc_dx[NB];
@@ -550,16 +649,15 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
   u32x4 ypf = y_load(cb0);
   for (int t = 0; t < ntiles; ++t) {
     const int j0 = cb0 + t * kFCols;
-    __syncthreads();  // previous tile's Ys and Gs reads are done (and Xs is written)
+    __syncthreads();  // previous tile's Ys and Gt reads are done (and Xs is written)
     if (tid < 512) *reinterpret_cast<u32x4*>(Ys + ((tid >> 3) * LDX) + (tid & 7) * 8) = ypf;
     if (t + 1 < ntiles) ypf = y_load(j0 + kFCols);
-    float cl[4], cp[4], ny[4];
+    float sh_c[4], ny[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
       const int col = j0 + jb * 16 + r16;
       const bool cv = col < B;
-      cl[jb] = cv ? a.c[col] : 0.f;
-      cp[jb] = cv ? 1.f : 0.f;
+      sh_c[jb] = (wb != 0.f && cv) ? __builtin_fmaf(a.c[col], kL2E, log2b) : INFINITY;
       ny[jb] = (L2 && cv) ? a.npsi[col] : 0.f;
     }
     __syncthreads();
@@ -573,57 +671,77 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
         acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b, acc[jb], 0, 0, 0);
       }
     }
-    // G (or H = G / d) of the wave's 16 rows; column sums of H for L2
+    // G (or H = G / d) of the wave's 16 rows, one 16-column block at a time;
+    // row and column sums of H for L2
+    const bool edge = !rows_full || j0 + kFCols > B;
+    const bool diag = j0 <= row_base && row_base < j0 + kFCols;
     float hcol[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
-      const int col = j0 + jb * 16 + r16;
+      float h[4], dd[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row_base + 4 * g + r;
-        float v = acc[jb][r];
-        float d = 0.f;
-        if (EN == kEnL2) { d = l2_dist(nx[r], ny[jb], v); v = -d; }
-        if (EN == kEnL2sq) v = -l2sq_dist(nx[r], ny[jb], v);
-        float gv = 0.f;
-        if (cp[jb] != 0.f && rvalid[r]) {
-          const float dl = (row == col) ? 1.f : 0.f;
-          gv = __expf(v - lse_r[r]) * (wf + pen_r[r]) - wf * dl;
-          if (wb != 0.f) gv += __expf(v - cl[jb]) - dl;
-          gv *= inv;
-          if (EN == kEnL2) gv = d > 0.f ? gv * __builtin_amdgcn_rcpf(d) : 0.f;
-          if (EN == kEnL2sq) gv *= 2.f;
-        }
-        hrow[r] += gv;
-        hcol[jb] += gv;
-        Gs[(wave * 16 + 4 * g + r) * LDG + jb * 16 + r16] = f2bf(gv);
+        const float fv = energy_f<EN>(acc[jb][r], nx[r], ny[jb], dd[r]);
+        const float pa = __builtin_amdgcn_exp2f(__builtin_fmaf(fv, kL2E, -sh_r[r]));
+        const float pb = __builtin_amdgcn_exp2f(__builtin_fmaf(fv, kL2E, -sh_c[jb]));
+        h[r] = __builtin_fmaf(pa, k_r[r], pb);
       }
+      if (diag) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (row_base + 4 * g + r == j0 + jb * 16 + r16) h[r] -= dgv;
+      }
+      if (edge) {
+        const bool cv = j0 + jb * 16 + r16 < B;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[r] = (cv && rvalid[r]) ? h[r] : 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (EN == kEnL2) h[r] = dd[r] > 0.f ? h[r] * __builtin_amdgcn_rcpf(dd[r]) : 0.f;
+        if (EN == kEnL2sq) h[r] *= 2.f;
+        hrow[r] += h[r];
+        hcol[jb] += h[r];
+      }
+      uint2 w;
+      w.x = pack2bf(h[0], h[1]);
+      w.y = pack2bf(h[2], h[3]);
+      *reinterpret_cast<uint2*>(&Gt[(jb * 16 + r16) * LDGT + wave * 16 + 4 * g]) = w;
     }
     if (L2) {
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb) {
-        float h = hcol[jb];
-        h += __shfl_xor(h, 16, 64);
-        h += __shfl_xor(h, 32, 64);
-        if (g == 0) csum[wave][jb * 16 + r16] = h;
+        float hc = hcol[jb];
+        hc += __shfl_xor(hc, 16, 64);
+        hc += __shfl_xor(hc, 32, 64);
+        if (g == 0) csum[wave][jb * 16 + r16] = hc;
       }
     }
-    // dphi[16 rows][D] += G[16][64] . Y[64][D] from the wave's own G strip
+    // dphi[16 rows][D] += G[16][64] . Y[64][D] from the wave's own rows of
+    // the tile (only this wave wrote them: a wave-local LDS wait suffices)
     __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      bf16x8 ga = *reinterpret_cast<const bf16x8*>(&Gs[(wave * 16 + r16) * LDG + kk * 32 + g * 8]);
+      v4s gq[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+        gq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (lds_v4s*)(&Gt[krow * LDGT + wave * 16 + 4 * (r16 & 3)]));
+      }
+      v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
+      const bf16x8 ga = __builtin_bit_cast(bf16x8, gv8);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        v4s h[2];
+        v4s hq[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
           const int dcol = nb * 16 + 4 * (r16 & 3);
-          h[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + jrow * LDX + dcol));
+          hq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + jrow * LDX + dcol));
         }
-        v8s yv = {h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+        v8s yv = {hq[0][0], hq[0][1], hq[0][2], hq[0][3], hq[1][0], hq[1][1], hq[1][2], hq[1][3]};
         acc_dx[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, __builtin_bit_cast(bf16x8, yv),
                                                              acc_dx[nb], 0, 0, 0);
       }
@@ -631,25 +749,25 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
     __syncthreads();  // the whole G tile (and csum) is in LDS
     {
       // dpsi[16 columns cb16][16 features nb] = G^T . phi over the 256 rows:
-      // A = G^T (lane (g, j): rows 32kk + 8g..+7 of column j), B = phi
-      // (rows 32kk + 8g..+7 of feature j), both by transpose reads
+      // A = G^T (lane (g, j): rows 32kk + 8g..+7 of column j, one 16-byte
+      // read of the transposed tile), B = phi (rows 32kk + 8g..+7 of feature
+      // j, transpose reads)
       const int cb16 = wave >> 2, nb = wave & 3;
       floatx4 acc_dy = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kk = 0; kk < kBRows / 32; ++kk) {
-        v4s ha[2], hb[2];
+        const bf16x8 av =
+            *reinterpret_cast<const bf16x8*>(&Gt[(cb16 * 16 + r16) * LDGT + kk * 32 + 8 * g]);
+        v4s hb[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
-          ha[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-              (lds_v4s*)(Gs + krow * LDG + cb16 * 16 + 4 * (r16 & 3)));
           hb[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
               (lds_v4s*)(Xs + krow * LDX + nb * 16 + 4 * (r16 & 3)));
         }
-        v8s av = {ha[0][0], ha[0][1], ha[0][2], ha[0][3], ha[1][0], ha[1][1], ha[1][2], ha[1][3]};
         v8s bv = {hb[0][0], hb[0][1], hb[0][2], hb[0][3], hb[1][0], hb[1][1], hb[1][2], hb[1][3]};
-        acc_dy = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                         __builtin_bit_cast(bf16x8, bv), acc_dy, 0, 0, 0);
+        acc_dy = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, bv),
+                                                         acc_dy, 0, 0, 0);
       }
       float* dst = a.dX_part + ((int64_t)gridDim.y + blockIdx.x) * B * D;
 #pragma unroll
@@ -658,10 +776,10 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
         if (col < B) dst[(int64_t)col * D + nb * 16 + r16] = acc_dy[r];
       }
       if (L2 && tid < kFCols && j0 + tid < B) {
-        float h = 0.f;
+        float hs = 0.f;
 #pragma unroll
-        for (int w = 0; w < 16; ++w) h += csum[w][tid];
-        a.rs_part[((int64_t)gridDim.y + blockIdx.x) * B + j0 + tid] = h;
+        for (int w = 0; w < 16; ++w) hs += csum[w][tid];
+        a.rs_part[((int64_t)gridDim.y + blockIdx.x) * B + j0 + tid] = hs;
       }
     }
   }
@@ -677,11 +795,11 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
   if (L2) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      float h = hrow[r];
+      float hr = hrow[r];
 #pragma unroll
-      for (int o = 1; o <= 8; o <<= 1) h += __shfl_xor(h, o, 64);
+      for (int o = 1; o <= 8; o <<= 1) hr += __shfl_xor(hr, o, 64);
       const int row = row_base + 4 * g + r;
-      if (r16 == 0 && row < B) a.rs_part[(int64_t)blockIdx.y * B + row] = h;
+      if (r16 == 0 && row < B) a.rs_part[(int64_t)blockIdx.y * B + row] = hr;
     }
   }
 }
@@ -850,6 +968,7 @@ hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int energy, int lo
   const float wf = (loss == CRL_LOSS_FWD || loss == CRL_LOSS_SYM || loss == CRL_LOSS_FLATNCE_FWD) ? 1.f : 0.f;
   const float wb = (loss == CRL_LOSS_SYM || loss == CRL_LOSS_BWD || loss == CRL_LOSS_FLATNCE_BWD) ? 1.f : 0.f;
   const int64_t n = (int64_t)B * D;
+  const float l2b = (float)std::log2((double)B);
   const bool one = fused_bwd_one_pass(B, D);
   int S = fused_splits(B);
   if (one) {  // one pass for both gradients
@@ -861,7 +980,7 @@ hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int energy, int lo
                                          "infonce_bwd_both_kernel<l2>",
                                          "infonce_bwd_both_kernel<l2sq>"};
     KTimer t = timing_begin(fused_name(names, en), flops, bytes, s);
-    CRL_EN_DISPATCH(EN, (infonce_bwd_both_kernel<EN><<<grid, 1024, 0, s>>>(a, B, beta, wf, wb)))
+    CRL_EN_DISPATCH(EN, (infonce_bwd_both_kernel<EN><<<grid, 1024, 0, s>>>(a, B, beta, wf, wb, l2b)))
     timing_end(t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -875,9 +994,9 @@ hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int energy, int lo
     KTimer t = timing_begin(pass ? "infonce_bwd_kernel<cols>" : "infonce_bwd_kernel<rows>",
                             bw_flops, bw_bytes, s);
     if (pass == 0) {
-      CRL_EN_DISPATCH(EN, CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, EN, 0><<<grid, 256, 0, s>>>(a, B, cps, beta, wf, wb))))
+      CRL_EN_DISPATCH(EN, CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, EN, 0><<<grid, 256, 0, s>>>(a, B, cps, beta, wf, wb, l2b))))
     } else {
-      CRL_EN_DISPATCH(EN, CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, EN, 1><<<grid, 256, 0, s>>>(a, B, cps, beta, wf, wb))))
+      CRL_EN_DISPATCH(EN, CRL_FUSED_DISPATCH(KS, (infonce_bwd_kernel<KS, EN, 1><<<grid, 256, 0, s>>>(a, B, cps, beta, wf, wb, l2b))))
     }
     timing_end(t);
     hipError_t e = hipGetLastError();
