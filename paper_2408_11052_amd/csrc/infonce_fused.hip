@@ -177,6 +177,26 @@ __device__ __forceinline__ float exp_diff(float x, float m) {
 // against the 64-column tiles of one column split.  Tiles inside the batch
 // on every side skip the masking, and only the tile that holds a wave's
 // diagonal entries looks for them (both are wave-uniform branches).
+// The 16 x 64 tile F = X[16 rows] . Y[64 columns]^T of one wave: four
+// 16-column accumulators, the K loop outside, so that the four products of
+// a K step are independent and their B fragments can be read together.
+template <int KS, int LDY>
+__device__ __forceinline__ void tile_product(floatx4 (&acc)[4], const bf16x8 (&xa)[KS],
+                                             const bf16_t* __restrict__ Ys, int r16, int g) {
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) acc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    bf16x8 b[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+      b[jb] = *reinterpret_cast<const bf16x8*>(Ys + (jb * 16 + r16) * LDY + ks * 32 + g * 8);
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+      acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b[jb], acc[jb], 0, 0, 0);
+  }
+}
+
 // Occupancy targets (wavefronts per SIMD) that the register allocation must
 // meet: the forward's LDS holds three workgroups per CU at D = 256, the
 // backward passes need about 256 registers per lane there.
@@ -266,15 +286,7 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
     ny_load(min(j0 + kFCols, jlast));
     __syncthreads();
     floatx4 acc[4];
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      acc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        bf16x8 b = *reinterpret_cast<const bf16x8*>(Ys + (jb * 16 + r16) * LDY + ks * 32 + g * 8);
-        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b, acc[jb], 0, 0, 0);
-      }
-    }
+    tile_product<KS, LDY>(acc, xa, Ys, r16, g);
     float f[4][4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
@@ -462,15 +474,7 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
     col_load(cpf, min(j0 + kFCols, jlast));
     __syncthreads();
     floatx4 acc[4];
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      acc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        bf16x8 b = *reinterpret_cast<const bf16x8*>(Ys + (jb * 16 + r16) * LDY + ks * 32 + g * 8);
-        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b, acc[jb], 0, 0, 0);
-      }
-    }
+    tile_product<KS, LDY>(acc, xa, Ys, r16, g);
     float sh_b[4], k_b[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
@@ -529,18 +533,26 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
       }
       v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
       const bf16x8 ga = __builtin_bit_cast(bf16x8, gv8);
+      // up to four output blocks at a time: their B fragments read together
+      constexpr int NU = NB < 4 ? NB : 4;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        v4s hq[2];
+      for (int nb0 = 0; nb0 < NB; nb0 += NU) {
+        v4s hq[NU][2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
-          const int dcol = nb * 16 + 4 * (r16 & 3);
-          hq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + jrow * LDY + dcol));
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+            const int dcol = (nb0 + u) * 16 + 4 * (r16 & 3);
+            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + jrow * LDY + dcol));
+          }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          v8s yv = {hq[u][0][0], hq[u][0][1], hq[u][0][2], hq[u][0][3],
+                    hq[u][1][0], hq[u][1][1], hq[u][1][2], hq[u][1][3]};
+          acc_dx[nb0 + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              ga, __builtin_bit_cast(bf16x8, yv), acc_dx[nb0 + u], 0, 0, 0);
         }
-        v8s yv = {hq[0][0], hq[0][1], hq[0][2], hq[0][3], hq[1][0], hq[1][1], hq[1][2], hq[1][3]};
-        acc_dx[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, __builtin_bit_cast(bf16x8, yv),
-                                                             acc_dx[nb], 0, 0, 0);
       }
     }
   }
@@ -662,15 +674,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
     }
     __syncthreads();
     floatx4 acc[4];
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      acc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        bf16x8 b = *reinterpret_cast<const bf16x8*>(Ys + (jb * 16 + r16) * LDX + ks * 32 + g * 8);
-        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b, acc[jb], 0, 0, 0);
-      }
-    }
+    tile_product<KS, LDX>(acc, xa, Ys, r16, g);
     // G (or H = G / d) of the wave's 16 rows, one 16-column block at a time;
     // row and column sums of H for L2
     const bool edge = !rows_full || j0 + kFCols > B;
@@ -732,18 +736,26 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
       }
       v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
       const bf16x8 ga = __builtin_bit_cast(bf16x8, gv8);
+      // up to four output blocks at a time: their B fragments read together
+      constexpr int NU = NB < 4 ? NB : 4;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        v4s hq[2];
+      for (int nb0 = 0; nb0 < NB; nb0 += NU) {
+        v4s hq[NU][2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
-          const int dcol = nb * 16 + 4 * (r16 & 3);
-          hq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + jrow * LDX + dcol));
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+            const int dcol = (nb0 + u) * 16 + 4 * (r16 & 3);
+            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + jrow * LDX + dcol));
+          }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          v8s yv = {hq[u][0][0], hq[u][0][1], hq[u][0][2], hq[u][0][3],
+                    hq[u][1][0], hq[u][1][1], hq[u][1][2], hq[u][1][3]};
+          acc_dx[nb0 + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              ga, __builtin_bit_cast(bf16x8, yv), acc_dx[nb0 + u], 0, 0, 0);
         }
-        v8s yv = {hq[0][0], hq[0][1], hq[0][2], hq[0][3], hq[1][0], hq[1][1], hq[1][2], hq[1][3]};
-        acc_dx[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, __builtin_bit_cast(bf16x8, yv),
-                                                             acc_dx[nb], 0, 0, 0);
       }
     }
     __syncthreads();  // the whole G tile (and csum) is in LDS
