@@ -129,7 +129,26 @@ __device__ __forceinline__ void tile_load(TileRegs<D>& t, const bf16_t* __restri
   }
 }
 
-// rows layout Ys[r][d] (stride LDY)
+// LDS rows of D BF16 values are padded to D + 8 (a row stride of 4 mod 64
+// banks of 4 bytes) and stored in a permuted order: inside each group of 16
+// rows, row 8a + 4b + t (t < 4) sits at 8a + 2t + b.  Two reads then find
+// distinct banks: the MFMA's row operand (a ds_read_b128 pass of 16 lanes,
+// rows r0..r0+15, one 16-byte chunk each: 16 distinct positions, 4 banks
+// apart) and the transpose read (a half-wave: rows 4b + t and 8 + 4b + t,
+// 32 contiguous bytes of each, whose positions 2t + b and 8 + 2t + b lie an
+// even number of rows apart, 8 banks).  The padding alone would give the
+// second pattern 2-way conflicts; a chunk swizzle would cost an address
+// register per column block.  With b a compile-time offset of both reads,
+// every address is one per-lane base plus an immediate.
+__device__ __forceinline__ int lds_row(int r) {
+  return (r & ~7) | ((r & 3) << 1) | ((r >> 2) & 1);
+}
+template <int D>
+__device__ __forceinline__ int lds_at(int r, int d) {
+  return lds_row(r) * (D + 8) + d;
+}
+
+// rows layout Ys[r][d] (row order and stride as above)
 template <int D, int LDY>
 __device__ __forceinline__ void tile_store_rows(bf16_t* __restrict__ Ys, const TileRegs<D>& t,
                                                 int tid) {
@@ -138,7 +157,7 @@ __device__ __forceinline__ void tile_store_rows(bf16_t* __restrict__ Ys, const T
   for (int i = 0; i < D / 32; ++i) {
     const int v = tid + i * 256;
     const int r = v / VPR, c = v % VPR;
-    *reinterpret_cast<u32x4*>(Ys + r * LDY + c * 8) = t.v[i];
+    *reinterpret_cast<u32x4*>(Ys + lds_at<D>(r, c * 8)) = t.v[i];
   }
 }
 
@@ -180,7 +199,7 @@ __device__ __forceinline__ float exp_diff(float x, float m) {
 // The 16 x 64 tile F = X[16 rows] . Y[64 columns]^T of one wave: four
 // 16-column accumulators, the K loop outside, so that the four products of
 // a K step are independent and their B fragments can be read together.
-template <int KS, int LDY>
+template <int KS>
 __device__ __forceinline__ void tile_product(floatx4 (&acc)[4], const bf16x8 (&xa)[KS],
                                              const bf16_t* __restrict__ Ys, int r16, int g) {
 #pragma unroll
@@ -190,7 +209,7 @@ __device__ __forceinline__ void tile_product(floatx4 (&acc)[4], const bf16x8 (&x
     bf16x8 b[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
-      b[jb] = *reinterpret_cast<const bf16x8*>(Ys + (jb * 16 + r16) * LDY + ks * 32 + g * 8);
+      b[jb] = *reinterpret_cast<const bf16x8*>(Ys + lds_at<KS * 32>(jb * 16 + r16, ks * 32 + g * 8));
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
       acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b[jb], acc[jb], 0, 0, 0);
@@ -286,7 +305,7 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
     ny_load(min(j0 + kFCols, jlast));
     __syncthreads();
     floatx4 acc[4];
-    tile_product<KS, LDY>(acc, xa, Ys, r16, g);
+    tile_product<KS>(acc, xa, Ys, r16, g);
     float f[4][4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
@@ -474,7 +493,7 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
     col_load(cpf, min(j0 + kFCols, jlast));
     __syncthreads();
     floatx4 acc[4];
-    tile_product<KS, LDY>(acc, xa, Ys, r16, g);
+    tile_product<KS>(acc, xa, Ys, r16, g);
     float sh_b[4], k_b[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
@@ -544,7 +563,7 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
           for (int q = 0; q < 2; ++q) {
             const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
             const int dcol = (nb0 + u) * 16 + 4 * (r16 & 3);
-            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + jrow * LDY + dcol));
+            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_at<D>(jrow, dcol)));
           }
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
@@ -597,7 +616,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
                                                                float wf, float wb, float log2b) {
   constexpr bool L2 = EN != kEnDot;
   constexpr int D = 64, KS = 2, NB = 4;
-  constexpr int LDX = D + 8;           // phi / psi rows in LDS (144 B)
+  constexpr int LDX = D + 8;           // phi / psi rows in LDS (144 B, lds_at order)
   constexpr int LDGT = kBRows + 8;     // transposed G rows (one per column of the tile)
   typedef short v4s __attribute__((ext_vector_type(4)));
   typedef short v8s __attribute__((ext_vector_type(8)));
@@ -623,7 +642,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
     const int r = v >> 3, c = v & 7;
     u32x4 val = {0u, 0u, 0u, 0u};
     if (r0 + r < B) val = *reinterpret_cast<const u32x4*>(a.phi_b + (int64_t)(r0 + r) * D + c * 8);
-    *reinterpret_cast<u32x4*>(Xs + r * LDX + c * 8) = val;
+    *reinterpret_cast<u32x4*>(Xs + lds_at<D>(r, c * 8)) = val;
   }
   bf16x8 xa[KS];
   {
@@ -662,7 +681,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
   for (int t = 0; t < ntiles; ++t) {
     const int j0 = cb0 + t * kFCols;
     __syncthreads();  // previous tile's Ys and Gt reads are done (and Xs is written)
-    if (tid < 512) *reinterpret_cast<u32x4*>(Ys + ((tid >> 3) * LDX) + (tid & 7) * 8) = ypf;
+    if (tid < 512) *reinterpret_cast<u32x4*>(Ys + lds_at<D>(tid >> 3, (tid & 7) * 8)) = ypf;
     if (t + 1 < ntiles) ypf = y_load(j0 + kFCols);
     float sh_c[4], ny[4];
 #pragma unroll
@@ -674,7 +693,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
     }
     __syncthreads();
     floatx4 acc[4];
-    tile_product<KS, LDX>(acc, xa, Ys, r16, g);
+    tile_product<KS>(acc, xa, Ys, r16, g);
     // G (or H = G / d) of the wave's 16 rows, one 16-column block at a time;
     // row and column sums of H for L2
     const bool edge = !rows_full || j0 + kFCols > B;
@@ -747,7 +766,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
           for (int q = 0; q < 2; ++q) {
             const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
             const int dcol = (nb0 + u) * 16 + 4 * (r16 & 3);
-            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + jrow * LDX + dcol));
+            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_at<D>(jrow, dcol)));
           }
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
@@ -775,7 +794,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
         for (int q = 0; q < 2; ++q) {
           const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
           hb[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-              (lds_v4s*)(Xs + krow * LDX + nb * 16 + 4 * (r16 & 3)));
+              (lds_v4s*)(Xs + lds_at<D>(krow, nb * 16 + 4 * (r16 & 3))));
         }
         v8s bv = {hb[0][0], hb[0][1], hb[0][2], hb[0][3], hb[1][0], hb[1][1], hb[1][2], hb[1][3]};
         acc_dy = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, bv),

@@ -9,7 +9,9 @@ namespace crl {
 // One wavefront per (step u, env e) row of the chunk: the row's obs and act
 // words go to ring row (count + u) mod C of env e, its trajectory id beside
 // them.  The chunk is read in order (rows of one step are contiguous), the
-// ring is written in whole rows.
+// ring is written in whole rows; with V4 (d_s a multiple of 4, both obs
+// buffers 16-byte aligned) the obs row moves in 16-byte pieces.
+template <bool V4>
 __global__ __launch_bounds__(256) void replay_insert_kernel(
     float* __restrict__ obs, float* __restrict__ act, int32_t* __restrict__ traj, int E, int C,
     int d_s, int d_a, const float* __restrict__ nobs, const float* __restrict__ nact,
@@ -22,9 +24,15 @@ __global__ __launch_bounds__(256) void replay_insert_kernel(
   int row = (int)(*count % C) + u;  // u < C, so one wrap at most
   if (row >= C) row -= C;
   const int64_t dst = (int64_t)e * C + row;
-  float* __restrict__ so = obs + dst * d_s;
-  const float* __restrict__ no = nobs + (int64_t)r * d_s;
-  for (int c = lane; c < d_s; c += 64) so[c] = no[c];
+  if (V4) {
+    float4* __restrict__ so = reinterpret_cast<float4*>(obs + dst * d_s);
+    const float4* __restrict__ no = reinterpret_cast<const float4*>(nobs + (int64_t)r * d_s);
+    for (int c = lane; c < (d_s >> 2); c += 64) so[c] = no[c];
+  } else {
+    float* __restrict__ so = obs + dst * d_s;
+    const float* __restrict__ no = nobs + (int64_t)r * d_s;
+    for (int c = lane; c < d_s; c += 64) so[c] = no[c];
+  }
   float* __restrict__ sa = act + dst * d_a;
   const float* __restrict__ na = nact + (int64_t)r * d_a;
   for (int c = lane; c < d_a; c += 64) sa[c] = na[c];
@@ -100,9 +108,16 @@ hipError_t launch_replay_insert(float* obs, float* act, int32_t* traj, int E, in
   const int64_t rows = (int64_t)U * E;
   dim3 grid((unsigned)((rows + 3) / 4)), block(256);
   const double bytes = 2.0 * (double)rows * (4.0 * (d_s + d_a) + 4.0);
-  CRL_TIMED("replay_insert_kernel", 0.0, bytes, s,
-    replay_insert_kernel<<<grid, block, 0, s>>>(obs, act, traj, E, C, d_s, d_a, nobs, nact,
-                                                ntraj, U, count));
+  const bool v4 = (d_s & 3) == 0 && ((reinterpret_cast<uintptr_t>(obs) |
+                                       reinterpret_cast<uintptr_t>(nobs)) & 15u) == 0;
+  if (v4)
+    CRL_TIMED("replay_insert_kernel", 0.0, bytes, s,
+      replay_insert_kernel<true><<<grid, block, 0, s>>>(obs, act, traj, E, C, d_s, d_a, nobs,
+                                                        nact, ntraj, U, count));
+  else
+    CRL_TIMED("replay_insert_kernel", 0.0, bytes, s,
+      replay_insert_kernel<false><<<grid, block, 0, s>>>(obs, act, traj, E, C, d_s, d_a, nobs,
+                                                         nact, ntraj, U, count));
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   return launch_counter_add(count, U, s);
