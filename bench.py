@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--full-workload", default="b4096_full_update_actor4x1024")
     ap.add_argument("--full-steps", type=int, default=1000,
                     help="consecutive full updates (critic, policy, alpha) timed")
-    ap.add_argument("--full-graph-steps", type=int, default=100)
+    ap.add_argument("--full-graph-steps", type=int, default=1000)
     ap.add_argument("--no-full", action="store_true")
     ap.add_argument("--large-workload", default="b16384_lnswish2x1024_d256_l2_sym")
     ap.add_argument("--large-steps", type=int, default=100,
