@@ -115,16 +115,26 @@ __global__ void fused_prep_reduce_kernel(FusedArgs a, GemmParams P, int B, int D
 template <int D>
 struct TileRegs { u32x4 v[D / 32]; };
 
+// A tile inside the batch (the common case) loads without bounds checks from
+// one tile base and per-lane 32-bit offsets; only the last tile of the batch
+// checks its rows.
 template <int D>
 __device__ __forceinline__ void tile_load(TileRegs<D>& t, const bf16_t* __restrict__ Y, int j0,
                                           int B, int tid) {
   constexpr int VPR = D / 8;  // 16-byte vectors per row
+  const bf16_t* __restrict__ base = Y + (int64_t)j0 * D;
+  if (j0 + kFCols <= B) {
+#pragma unroll
+    for (int i = 0; i < D / 32; ++i)
+      t.v[i] = *reinterpret_cast<const u32x4*>(base + (tid + i * 256) * 8);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < D / 32; ++i) {
     const int v = tid + i * 256;
-    const int r = v / VPR, c = v % VPR;
+    const int r = v / VPR;
     u32x4 val = {0u, 0u, 0u, 0u};
-    if (j0 + r < B) val = *reinterpret_cast<const u32x4*>(Y + (int64_t)(j0 + r) * D + c * 8);
+    if (j0 + r < B) val = *reinterpret_cast<const u32x4*>(base + v * 8);
     t.v[i] = val;
   }
 }
@@ -284,13 +294,17 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
   // before each LDS store covers exactly the previous fetch
   const int jlast = c0 + ((c1 - c0 - 1) / kFCols) * kFCols;
   TileRegs<D> pf;
-  float nypf[4];
+  float nypf[4] = {0.f, 0.f, 0.f, 0.f};
   auto ny_load = [&](int j0) {
+    if (!L2) return;
+    const float* __restrict__ base = a.npsi + j0;
+    if (j0 + kFCols <= c1) {
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      const int col = j0 + jb * 16 + r16;
-      nypf[jb] = (L2 && col < c1) ? a.npsi[col] : 0.f;
+      for (int jb = 0; jb < 4; ++jb) nypf[jb] = base[jb * 16 + r16];
+      return;
     }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) nypf[jb] = j0 + jb * 16 + r16 < c1 ? base[jb * 16 + r16] : 0.f;
   };
   if (c0 < c1) { tile_load<D>(pf, a.psi_b, c0, B, tid); ny_load(c0); }
   int t = 0;
@@ -472,6 +486,14 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
   // per-lane column values of a tile (columns j0 + jb*16 + r16)
   struct ColVals { float lse[4], ny[4]; };
   auto col_load = [&](ColVals& cvv, int j0) {
+    if (j0 + kFCols <= c1) {
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        cvv.lse[jb] = lseY[j0 + jb * 16 + r16];
+        cvv.ny[jb] = L2 ? nY[j0 + jb * 16 + r16] : 0.f;
+      }
+      return;
+    }
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
       const int col = j0 + jb * 16 + r16;
