@@ -202,7 +202,7 @@ def other_workloads(names, dev, steps=100):
         obs, act = buffer_for(wo, seed=0)
         p, q = critic_params_for(wo, seed=1)
         d_obs, d_act = torch.from_numpy(obs).to(dev), torch.from_numpy(act).to(dev)
-        u = CriticUpdate(wo, d_obs, d_act, p, q, seed=2)
+        u = CriticUpdate(wo, d_obs, d_act, p, q, seed=2, keep_grads=False)
         dt, n = time_steps(u, steps, 5, 10)
         fl = critic_step_flops(wo)["total"]
         peak = PEAK_BF16_TFLOPS if wo.precision == "bf16" else PEAK_FP32_TFLOPS
@@ -259,7 +259,7 @@ def training_iterations(w, phi, psi, args, dev):
     fl = critic_step_flops(w)["total"]
     runs = []
     for k in [int(x) for x in args.utd.split(",") if x]:
-        upd = CriticUpdate(w, ring, None, phi, psi, seed=2)
+        upd = CriticUpdate(w, ring, None, phi, psi, seed=2, keep_grads=False)
         graphs = [upd.capture_iteration(*pool[p], updates=k) for p in range(P)]
         for g in graphs:  # untimed
             g.replay()
@@ -367,7 +367,7 @@ def main():
     torch.cuda.synchronize()
 
     flops = critic_step_flops(w)
-    upd = CriticUpdate(w, d_obs, d_act, phi, psi, seed=2)
+    upd = CriticUpdate(w, d_obs, d_act, phi, psi, seed=2, keep_grads=False)
     nparam = upd.crit.nparam
     ws_gib = upd.crit.ws_bytes / 2**30
     log(f"[bench] {w.precision}/{w.logits}: {upd.crit.nparam} params, workspace "
@@ -422,7 +422,7 @@ def main():
     fp32 = None
     if not args.no_fp32:
         wf = w.with_(precision="fp32", logits="materialised")
-        upf = CriticUpdate(wf, d_obs, d_act, phi, psi, seed=2)
+        upf = CriticUpdate(wf, d_obs, d_act, phi, psi, seed=2, keep_grads=False)
         log(f"[bench] plain FP32 path (materialised logits, eager): {args.fp32_steps} steps")
         dtf, nf = time_steps(upf, args.fp32_steps, 2, 0)
         dtg, ng = time_steps(upf, args.fp32_steps, 0, 5)
@@ -444,7 +444,7 @@ def main():
         pa, qa = critic_params_for(wa, seed=1)
         actor = actor_params(wa.in_sg, wa.actor_hidden, wa.act_dim,
                              wa.activation == "ln_swish", seed=3)
-        fu = FullUpdate(wa, d_obs, d_act, pa, qa, actor, seed=2)
+        fu = FullUpdate(wa, d_obs, d_act, pa, qa, actor, seed=2, keep_grads=False)
         fl = critic_step_flops(wa)["total"] + actor_step_flops(wa)["total"]
         log(f"[bench] full update {wa.name}: {fu.crit.nparam_actor} policy params; "
             f"{args.full_steps} steps from graphs of {args.full_graph_steps}")
@@ -474,7 +474,7 @@ def main():
         ld_act = torch.from_numpy(lact).to(dev)
         del lobs, lact
         torch.cuda.reset_peak_memory_stats()
-        lu = CriticUpdate(wl, ld_obs, ld_act, lp, lq, seed=2)
+        lu = CriticUpdate(wl, ld_obs, ld_act, lp, lq, seed=2, keep_grads=False)
         lfl = critic_step_flops(wl)["total"]
         dtl, nl = time_steps(lu, args.large_steps, 5, 10)
         peak_l = torch.cuda.max_memory_allocated() / 2**30

@@ -255,6 +255,23 @@ CRL_API int crl_critic_bwd(crl_ctx* ctx, const float* params,
                            const void* x_g, void* ws, float* grads,
                            void* stream);
 
+/* Steps 3 and 4 in one call (Algorithm 1, the critic's gradient step): the
+ * gradient of crl_critic_bwd, each element fed to the Adam step of
+ * crl_adam_step as it is formed (the gradient vector is not read back).
+ *   params, params_bf16  updated in place (params_bf16 may be NULL for FP32)
+ *   grads                device FP32 [crl_param_count] out, or NULL: then
+ *                        the gradient is not kept
+ *   m, v, step, lr, b1, b2, eps   as for crl_adam_step, over the whole vector
+ * Other arguments as for crl_critic_bwd.  params, m, v and params_bf16 come
+ * out bit-identical to crl_critic_bwd followed by crl_adam_step (grads equal
+ * as values); the same alignment rules apply. */
+CRL_API int crl_critic_bwd_adam(crl_ctx* ctx, float* params,
+                                uint16_t* params_bf16, const void* x_sa,
+                                const void* x_g, void* ws, float* grads,
+                                float* m, float* v, const int64_t* step,
+                                double lr, double b1, double b2, double eps,
+                                void* stream);
+
 /* The critic matrix and the loss alone, from given representations: the
  * energy and objective steps of crl_critic_fwd / crl_critic_bwd (Section 3.1
  * objective; Appendix A.2 energies and objectives; the logsumexp penalty of

@@ -60,6 +60,8 @@ SIGNATURES = {
     "crl_ring_sample_relabel": (C.c_int, [P, P, P, P, I32, I32, P, U64, P, P, P, P, P, P]),
     "crl_critic_fwd": (C.c_int, [P, P, P, P, P, P, P, P]),
     "crl_critic_bwd": (C.c_int, [P, P, P, P, P, P, P, P]),
+    "crl_critic_bwd_adam": (C.c_int, [P, P, P, P, P, P, P, P, P, P, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, P]),
     "crl_infonce_fwd": (C.c_int, [P, P, P, P, P, P]),
     "crl_infonce_bwd": (C.c_int, [P, P, P, P, P, P, P]),
     "crl_infonce_fwd_noalloc": (C.c_int, [P, P, P, P, P, P, P, P]),

@@ -215,6 +215,15 @@ class Critic:
         check(lib().crl_critic_bwd(self.ctx, _ptr(params), _ptr(params_bf16), _ptr(x_sa),
                                    _ptr(x_g), _ptr(ws), _ptr(grads), _stream(stream)))
 
+    def crl_critic_bwd_adam(self, params, params_bf16, x_sa, x_g, ws, grads, m, v, step,
+                            lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8,
+                            stream=None):
+        """The gradient of crl_critic_bwd fed straight into the Adam step
+        (params, params_bf16, m, v updated in place; grads may be None)."""
+        check(lib().crl_critic_bwd_adam(self.ctx, _ptr(params), _ptr(params_bf16), _ptr(x_sa),
+                                        _ptr(x_g), _ptr(ws), _ptr(grads), _ptr(m), _ptr(v),
+                                        _ptr(step), lr, b1, b2, eps, _stream(stream)))
+
     def crl_infonce_fwd(self, phi, psi, ws, loss_out, stream=None):
         check(lib().crl_infonce_fwd(self.ctx, _ptr(phi), _ptr(psi), _ptr(ws), _ptr(loss_out),
                                     _stream(stream)))

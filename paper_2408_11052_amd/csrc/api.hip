@@ -94,9 +94,16 @@ struct Group {
   int nets[2], count;
   std::vector<int64_t> dwp;              // per layer: dW split-K partials, -1 if unsplit
   std::vector<int> dwbn;                 // per layer: column tile of the LDS kernel (0: dense partials)
-  std::vector<RedJob> few, many;         // reduction jobs (few / many parts)
+  std::vector<int64_t> dwu;              // per layer: with the Adam epilogue, where an
+                                         // unsplit dW goes (-1 if split)
+  std::vector<RedJob> few, many;         // reduction jobs (few / many parts); the few
+                                         // list ends with the unsplit dW copies, which
+                                         // only the Adam epilogue runs
   RedJob* d_few = nullptr;
   RedJob* d_many = nullptr;
+  int nfew_plain = 0;                    // few jobs of the plain reduction
+  int64_t total4_plain = 0;
+  int64_t chunks = 0;                    // blocks of the few jobs with the Adam epilogue
   int64_t total4 = 0, nblocks = 0;
   double few_bytes = 0, many_bytes = 0;
 };
@@ -399,7 +406,9 @@ void plan_group(crl_ctx* x, int gi, int64_t& off) {
   const int L = x->net[G.nets[0]].L;
   const int nrb = colsum_chunks(x->B);
   G.dwp.assign(L + 1, -1);
+  G.dwu.assign(L + 1, -1);
   G.dwbn.assign(L + 1, 0);
+  std::vector<RedJob> unsplit;  // dW blocks that the GEMM writes whole
   G.few.clear();
   G.many.clear();
   auto add = [](std::vector<RedJob>& v, int64_t src, int64_t stride, int64_t dst, int nparts,
@@ -433,6 +442,22 @@ void plan_group(crl_ctx* x, int gi, int64_t& off) {
         j.M = P.d[e].M; j.N = P.d[e].N; j.tiles_n = P.tiles_n[e]; j.bn = bn;
         G.few.push_back(j);
       }
+    } else {
+      // the Adam epilogue needs every element in a job: the unsplit dW is
+      // written to the workspace and taken as a one-part job
+      int64_t mn = 0;
+      for (int e = 0; e < G.count; ++e) mn = std::max(mn, (int64_t)P.d[e].M * P.d[e].N);
+      G.dwu[l] = take_bytes(x, off, (int64_t)G.count * mn * 4);
+      for (int e = 0; e < G.count; ++e) {
+        RedJob j{};
+        j.src = G.dwu[l] + (int64_t)e * mn * 4;
+        j.stride = (int64_t)P.d[e].M * P.d[e].N;
+        j.dst = x->net[G.nets[e]].lay[l].w;
+        j.nparts = 1;
+        j.n = (int32_t)j.stride;
+        j.M = P.d[e].M; j.N = P.d[e].N; j.tiles_n = 0; j.bn = 0;
+        unsplit.push_back(j);
+      }
     }
     const bool top = l == L;
     for (int e = 0; e < G.count; ++e) {
@@ -461,11 +486,20 @@ void plan_group(crl_ctx* x, int gi, int64_t& off) {
   for (size_t k = 0; k + 1 < gaps.size(); k += 2) add(G.many, 0, 0, gaps[k], 0, (int)gaps[k + 1]);
   G.total4 = 0;
   G.few_bytes = 0;
-  for (RedJob& j : G.few) {
+  G.nfew_plain = (int)G.few.size();
+  for (const RedJob& j : unsplit) G.few.push_back(j);
+  G.chunks = 0;
+  for (size_t k = 0; k < G.few.size(); ++k) {
+    RedJob& j = G.few[k];
+    if ((int)k == G.nfew_plain) G.total4_plain = G.total4;
     j.first = G.total4;
     G.total4 += j.n / 4;
-    G.few_bytes += 4.0 * j.M * j.N * (j.nparts + 1.0);
+    // fragment-order jobs are whole tiles: whole chunks
+    j.first_chunk = G.chunks;
+    G.chunks += (j.n / 4 + kRedChunk4 - 1) / kRedChunk4;
+    if ((int)k < G.nfew_plain) G.few_bytes += 4.0 * j.M * j.N * (j.nparts + 1.0);
   }
+  if (G.nfew_plain == (int)G.few.size()) G.total4_plain = G.total4;
   G.nblocks = 0;
   G.many_bytes = 0;
   for (RedJob& j : G.many) {
@@ -582,6 +616,20 @@ LossWs loss_ws(const crl_ctx* x) {
   return o;
 }
 
+// Adam hyperparameters for the device: 1 - b and log b formed in double
+AdamCoef adam_coef(double lr, double b1, double b2, double eps) {
+  AdamCoef c;
+  c.lr = (float)lr;
+  c.b1 = (float)b1;
+  c.b2 = (float)b2;
+  c.omb1 = (float)(1.0 - b1);
+  c.omb2 = (float)(1.0 - b2);
+  c.log_b1 = (float)std::log(b1);
+  c.log_b2 = (float)std::log(b2);
+  c.eps = (float)eps;
+  return c;
+}
+
 inline char* W(void* ws, int64_t off) { return static_cast<char*>(ws) + off; }
 inline float* WF(void* ws, int64_t off) { return reinterpret_cast<float*>(W(ws, off)); }
 
@@ -679,10 +727,12 @@ int mlp_forward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t 
 // parameter gradients of every layer.  A net with dx set (count must be 1)
 // also gets the gradient of the chosen input columns.
 int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t s,
-                 bool top_bias_ready = false) {
+                 bool top_bias_ready = false, const AdamArgs* adam = nullptr) {
   const Net& N0 = x->net[nc[0].net];
   const int B = x->B, H = N0.H, L = N0.L;
-  const bool grads = nc[0].g != nullptr;
+  // adam: the parameter gradients go into the Adam step of the vector as
+  // they are reduced (nc[0].g, if not NULL, receives them too)
+  const bool grads = nc[0].g != nullptr || adam != nullptr;
   const Group& G = x->grp[nc[0].net == 2 ? 1 : 0];
   if (grads && G.count != count) return fail(CRL_EINVAL, "internal: backward group mismatch");
   float* splitk = WF(ws, x->splitk);
@@ -728,9 +778,17 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
         d.A = l == 0 ? nc[e].x : (const void*)W(ws, S.Hh[l - 1]);
         d.lda = l == 0 ? nc[e].ld : N.H;
         d.B = dZ[e]; d.ldb = lo.fan_out;
-        d.C = nc[e].g + lo.w; d.ldc = lo.fan_out;
+        d.ldc = lo.fan_out;
         d.alpha = 1.f;
         d.epi = EPI_NONE;
+        if (G.dwu[l] >= 0 && (adam || !nc[e].g)) {  // unsplit: a one-part reduction job
+          const GemmDesc& d0 = Pw.d[0];
+          const GemmDesc& d1 = Pw.d[count - 1];
+          const int64_t mn = std::max((int64_t)d0.M * d0.N, (int64_t)d1.M * d1.N);
+          d.C = WF(ws, G.dwu[l]) + (int64_t)e * mn;
+        } else {
+          d.C = nc[e].g ? nc[e].g + lo.w : WF(ws, G.dwp[l]);  // split: C is not written
+        }
       }
       Pw.defer_reduce = Pw.splits > 1;
       paired = dw_dx_paired(x, G, l);
@@ -806,9 +864,21 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
   }
   if (grads) {
     const char* wsc = static_cast<const char*>(ws);
-    CRL_HIP(launch_grad_reduce(wsc, nc[0].g, G.d_few, (int)G.few.size(), G.total4, G.d_many,
-                               (int)G.many.size(), G.nblocks, G.few_bytes + G.many_bytes, s),
-            "gradient reductions");
+    if (adam) {
+      // every element of the vector (unsplit dW blocks included) is reduced
+      // once, then stepped: the gradient read, the parameter, m, v read and written
+      double bytes = G.few_bytes + G.many_bytes;
+      for (size_t k = G.nfew_plain; k < G.few.size(); ++k) bytes += 8.0 * G.few[k].n;
+      const int64_t n = nc[0].net == 2 ? x->nparam_actor : x->nparam;
+      bytes += (24.0 + (adam->pb ? 2.0 : 0.0)) * n - (nc[0].g ? 0.0 : 4.0 * n);
+      CRL_HIP(launch_grad_reduce(wsc, nc[0].g, G.d_few, (int)G.few.size(), G.chunks, G.d_many,
+                                 (int)G.many.size(), G.nblocks, bytes, s, adam),
+              "gradient reductions with the Adam step");
+    } else {
+      CRL_HIP(launch_grad_reduce(wsc, nc[0].g, G.d_few, G.nfew_plain, G.total4_plain, G.d_many,
+                                 (int)G.many.size(), G.nblocks, G.few_bytes + G.many_bytes, s),
+              "gradient reductions");
+    }
   }
   return CRL_OK;
 }
@@ -1227,6 +1297,39 @@ CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* para
   return mlp_backward(x, nc, 2, ws, s, x->fused);
 }
 
+CRL_API int crl_critic_bwd_adam(crl_ctx* x, float* params, uint16_t* params_bf16,
+                                const void* x_sa, const void* x_g, void* ws, float* grads,
+                                float* m, float* v, const int64_t* step, double lr, double b1,
+                                double b2, double eps, void* stream) {
+  if (!x) return fail(CRL_EINVAL, "NULL context");
+  if (!params || !x_sa || !x_g || !ws || !m || !v || !step)
+    return fail(CRL_EINVAL, "NULL buffer argument");
+  if (x->bf16 && !params_bf16) return fail(CRL_EINVAL, "BF16 precision needs params_bf16");
+  if (!aligned16(params) || !aligned16(ws) || (grads && !aligned16(grads)) || !aligned16(x_sa) ||
+      !aligned16(x_g) || !aligned16(m) || !aligned16(v) ||
+      (params_bf16 && !aligned16(params_bf16)))
+    return fail(CRL_EINVAL, "buffers must be 16-byte aligned");
+  if (!(b1 > 0.0 && b1 < 1.0 && b2 > 0.0 && b2 < 1.0 && eps >= 0.0 && std::isfinite(lr)))
+    return fail(CRL_EINVAL, "Adam hyperparameters out of range");
+  CRL_TRY(check_device(x));
+  hipStream_t s = (hipStream_t)stream;
+  AdamArgs A{};
+  A.p = params;
+  A.m = m;
+  A.v = v;
+  A.pb = reinterpret_cast<bf16_t*>(params_bf16);
+  A.step = step;
+  A.c = adam_coef(lr, b1, b2, eps);
+  const bf16_t* pb = reinterpret_cast<const bf16_t*>(params_bf16);
+  const float* phi = WF(ws, x->sl[0].out);
+  const float* psi = WF(ws, x->sl[1].out);
+  CRL_TRY(contrastive_bwd(x, phi, psi, ws, WF(ws, x->sl[0].dout), WF(ws, x->sl[1].dout),
+                          W(ws, x->sl[0].dout_t), W(ws, x->sl[1].dout_t), true, s));
+  NetCall nc[2] = {{0, x_sa, x->net[0].ld_in, params, pb, grads, nullptr, 0, 0, 0},
+                   {1, x_g, x->net[1].ld_in, params, pb, grads, nullptr, 0, 0, 0}};
+  return mlp_backward(x, nc, 2, ws, s, x->fused, &A);
+}
+
 CRL_API int crl_infonce_fwd(crl_ctx* x, const float* phi, const float* psi, void* ws,
                             float* loss_out, void* stream) {
   if (!x) return fail(CRL_EINVAL, "NULL context");
@@ -1365,15 +1468,7 @@ CRL_API int crl_adam_step(float* p, const float* g, float* m, float* v, uint16_t
   if (!(b1 > 0.0 && b1 < 1.0 && b2 > 0.0 && b2 < 1.0 && eps >= 0.0 && std::isfinite(lr)))
     return fail(CRL_EINVAL, "Adam hyperparameters out of range");
   if (n == 0) return CRL_OK;
-  AdamCoef c;
-  c.lr = (float)lr;
-  c.b1 = (float)b1;
-  c.b2 = (float)b2;
-  c.omb1 = (float)(1.0 - b1);
-  c.omb2 = (float)(1.0 - b2);
-  c.log_b1 = (float)std::log(b1);
-  c.log_b2 = (float)std::log(b2);
-  c.eps = (float)eps;
+  const AdamCoef c = adam_coef(lr, b1, b2, eps);
   CRL_HIP(launch_adam(p, g, m, v, reinterpret_cast<bf16_t*>(p_bf16), n, step, c,
                       (hipStream_t)stream), "Adam launch");
   return CRL_OK;

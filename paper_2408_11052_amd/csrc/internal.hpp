@@ -118,14 +118,21 @@ struct RedJob {
   int64_t stride;
   int64_t dst;
   int64_t first;
+  int64_t first_chunk;  // few-part jobs with the Adam epilogue: first block, in
+                        // chunks of kRedChunk4 float4 outputs
   int32_t nparts, n;
   int32_t M, N, tiles_n, bn;
 };
+// float4 outputs per block of the reduction with the Adam epilogue: half of a
+// 128 x 128 fragment-order tile (64 rows), or one 128 x 64 tile
+constexpr int kRedChunk4 = 2048;
+struct AdamArgs;
 // few-part jobs (total4 float4 outputs) and many-part jobs (nblocks blocks of
-// 16 outputs) in one launch
+// 16 outputs) in one launch.  With A, each gradient element goes straight
+// into the Adam step of its parameter (g, if not NULL, still receives it).
 hipError_t launch_grad_reduce(const char* ws, float* g, const RedJob* few, int nfew,
                               int64_t total4, const RedJob* many, int nmany, int64_t nblocks,
-                              double bytes, hipStream_t s);
+                              double bytes, hipStream_t s, const AdamArgs* A = nullptr);
 
 hipError_t launch_sqnorm(const float* X, float* out, int B, int D, hipStream_t s);
 hipError_t launch_cast_bf16(const float* src, bf16_t* dst, int64_t n, hipStream_t s);
@@ -135,6 +142,15 @@ struct AdamCoef {
 };
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, bf16_t* pb,
                        int64_t n, const int64_t* step, const AdamCoef& c, hipStream_t s);
+// The optimiser state of a flat vector, for the reduction's Adam epilogue.
+struct AdamArgs {
+  float* p;
+  float* m;
+  float* v;
+  bf16_t* pb;            // BF16 copy of p, or NULL
+  const int64_t* step;   // t (device, read)
+  AdamCoef c;
+};
 hipError_t launch_counter_add(int64_t* c, int64_t inc, hipStream_t s);
 
 // materialised critic matrix (FP32 B x B in the workspace, row stride ld)

@@ -431,6 +431,56 @@ hipError_t launch_colsum(const ColSumArgs& a, int count, int B, int N, int ld, b
 // ---------------------------------------------------------------------------
 // small utilities
 // ---------------------------------------------------------------------------
+// One Adam update, written with explicit fused multiply-adds so that every
+// kernel that applies it rounds the same way:
+//   m = b1 m + (1-b1) g,  v = b2 v + (1-b2) g^2,
+//   p -= lr (m c1) / (sqrt(v c2) + eps),  c1 = 1/(1 - b1^t), c2 = 1/(1 - b2^t).
+__device__ __forceinline__ float adam_update(float& p, float g, float& m, float& v, float c1,
+                                             float c2, const AdamCoef& c) {
+  m = __builtin_fmaf(c.b1, m, c.omb1 * g);
+  v = __builtin_fmaf(c.b2, v, (c.omb2 * g) * g);
+  p = p - (c.lr * (m * c1)) / (sqrtf(v * c2) + c.eps);
+  return p;
+}
+// bias-correction factors 1 / (1 - b^t) = -1 / expm1(t log b): full FP32
+// relative accuracy (no cancellation in 1 - b^t)
+__device__ __forceinline__ void adam_factors(const AdamCoef& c, const int64_t* step, float& c1,
+                                             float& c2) {
+  const float t = (float)(*step);
+  c1 = 1.f / (-expm1f(t * c.log_b1));
+  c2 = 1.f / (-expm1f(t * c.log_b2));
+}
+// Adam on parameter k with gradient gk
+__device__ __forceinline__ void adam_at(const AdamArgs& A, float c1, float c2, int64_t k,
+                                        float gk) {
+  float pk = A.p[k], mk = A.m[k], vk = A.v[k];
+  adam_update(pk, gk, mk, vk, c1, c2, A.c);
+  A.p[k] = pk;
+  A.m[k] = mk;
+  A.v[k] = vk;
+  if (A.pb) A.pb[k] = f2bf(pk);
+}
+// ... on the four parameters k4 * 4 + 0..3 (16-byte aligned)
+__device__ __forceinline__ void adam_at4(const AdamArgs& A, float c1, float c2, int64_t k4,
+                                         float4 gg) {
+  float4 pp = reinterpret_cast<float4*>(A.p)[k4];
+  float4 mm = reinterpret_cast<float4*>(A.m)[k4];
+  float4 vv = reinterpret_cast<float4*>(A.v)[k4];
+  adam_update(pp.x, gg.x, mm.x, vv.x, c1, c2, A.c);
+  adam_update(pp.y, gg.y, mm.y, vv.y, c1, c2, A.c);
+  adam_update(pp.z, gg.z, mm.z, vv.z, c1, c2, A.c);
+  adam_update(pp.w, gg.w, mm.w, vv.w, c1, c2, A.c);
+  reinterpret_cast<float4*>(A.p)[k4] = pp;
+  reinterpret_cast<float4*>(A.m)[k4] = mm;
+  reinterpret_cast<float4*>(A.v)[k4] = vv;
+  if (A.pb) {
+    uint2 u;
+    u.x = pack2bf(pp.x, pp.y);
+    u.y = pack2bf(pp.z, pp.w);
+    reinterpret_cast<uint2*>(A.pb)[k4] = u;
+  }
+}
+
 // last job whose `first` is <= v (jobs sorted by `first`)
 __device__ inline int find_job(const RedJob* __restrict__ jobs, int njobs, int64_t v) {
   int lo = 0, hi = njobs - 1;
@@ -441,10 +491,112 @@ __device__ inline int find_job(const RedJob* __restrict__ jobs, int njobs, int64
   return lo;
 }
 
+// sum of a float4 over the job's parts, in part order (four running sums)
+__device__ __forceinline__ float4 sum_parts(const float4* __restrict__ p, int64_t st,
+                                            int nparts) {
+  float4 s[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) s[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  int k = 0;
+  for (; k + 3 < nparts; k += 4) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 t = p[(k + q) * st];
+      s[q].x += t.x; s[q].y += t.y; s[q].z += t.z; s[q].w += t.w;
+    }
+  }
+  for (; k < nparts; ++k) {
+    const float4 t = p[k * st];
+    s[0].x += t.x; s[0].y += t.y; s[0].z += t.z; s[0].w += t.w;
+  }
+  float4 r;
+  r.x = (s[0].x + s[1].x) + (s[2].x + s[3].x);
+  r.y = (s[0].y + s[1].y) + (s[2].y + s[3].y);
+  r.z = (s[0].z + s[1].z) + (s[2].z + s[3].z);
+  r.w = (s[0].w + s[1].w) + (s[2].w + s[3].w);
+  return r;
+}
+
+// last job whose first_chunk is <= v
+__device__ inline int find_job_chunk(const RedJob* __restrict__ jobs, int njobs, int64_t v) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].first_chunk <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Few parts with the Adam epilogue: block blk takes chunk c of one job
+// (kRedChunk4 float4 outputs, 8 per thread).  Dense jobs step their float4s
+// in place.  Fragment-order jobs sum their partials into an LDS copy of the
+// chunk's rows (64 rows of a 128-wide tile, or a whole 64-wide tile) and then
+// step the parameters row by row, so that p, m, v move in whole rows.
+constexpr int kRedLdsFloats = 128 * (64 + 4);  // >= 64 * (128 + 4)
+__device__ __forceinline__ void reduce_few_adam(const char* __restrict__ ws,
+                                                float* __restrict__ g,
+                                                const RedJob* __restrict__ jobs, int njobs,
+                                                int64_t blk, const AdamArgs& A, float c1,
+                                                float c2, float* __restrict__ T) {
+  const RedJob J = jobs[find_job_chunk(jobs, njobs, blk)];
+  const int64_t c = blk - J.first_chunk;
+  const float4* src = reinterpret_cast<const float4*>(ws + J.src);
+  const int64_t st = J.stride / 4, n4 = J.n / 4;
+  const int tid = threadIdx.x;
+  if (J.bn == 0) {
+#pragma unroll
+    for (int k = 0; k < kRedChunk4 / 256; ++k) {
+      const int64_t i4 = c * kRedChunk4 + k * 256 + tid;
+      if (i4 < n4) {
+        const float4 r = sum_parts(src + i4, st, J.nparts);
+        if (g) reinterpret_cast<float4*>(g + J.dst)[i4] = r;
+        adam_at4(A, c1, c2, J.dst / 4 + i4, r);
+      }
+    }
+    return;
+  }
+  // the chunk: tile t, rows [r0, r0 + R) of it (R = 64 for bn = 128, else 128)
+  const int bn = J.bn, ld = bn + 4, wpr = bn / 32;
+  const int64_t tsz4 = 32 * (int64_t)bn;  // float4s per tile
+  const int t = (int)((c * kRedChunk4) / tsz4);
+  const int r0 = 64 * ((int)((c * kRedChunk4) % tsz4) / (16 * bn));  // 0 or 64
+#pragma unroll
+  for (int k = 0; k < kRedChunk4 / 256; ++k) {
+    const int64_t i4 = c * kRedChunk4 + k * 256 + tid;
+    const float4 r = sum_parts(src + i4, st, J.nparts);
+    // float4 i4 = lane's 4 accumulator rows of fragment f of wave w of tile t
+    const int rem = (int)(i4 * 4 - (int64_t)t * tsz4 * 4);
+    const int w = rem >> 11, f = (rem >> 8) & 7, lane = (rem >> 2) & 63;
+    const int rl = (w / wpr) * 64 + (f >> 1) * 16 + (lane >> 4) * 4 - r0;
+    const int cl = (w % wpr) * 32 + (f & 1) * 16 + (lane & 15);
+    T[rl * ld + cl] = r.x;
+    T[(rl + 1) * ld + cl] = r.y;
+    T[(rl + 2) * ld + cl] = r.z;
+    T[(rl + 3) * ld + cl] = r.w;
+  }
+  __syncthreads();
+  const int q4 = bn / 4;  // float4s per chunk row
+  const int row0 = (t / J.tiles_n) * 128 + r0, col0 = (t % J.tiles_n) * bn;
+#pragma unroll
+  for (int k = 0; k < kRedChunk4 / 256; ++k) {
+    const int v = k * 256 + tid;
+    const int rl = v / q4, cq = v % q4;
+    const int row = row0 + rl, col = col0 + 4 * cq;
+    if (row < J.M && col < J.N) {  // N is a multiple of 8: whole float4s
+      const float4 r = *reinterpret_cast<const float4*>(T + rl * ld + 4 * cq);
+      const int64_t k0 = J.dst + (int64_t)row * J.N + col;
+      if (g) *reinterpret_cast<float4*>(g + k0) = r;
+      adam_at4(A, c1, c2, k0 / 4, r);
+    }
+  }
+}
+
 // few parts (split-K partials): one float4 of one job per thread
+template <bool ADAM>
 __device__ __forceinline__ void reduce_few(const char* __restrict__ ws, float* __restrict__ g,
                                            const RedJob* __restrict__ jobs, int njobs,
-                                           int64_t total4, int64_t blk) {
+                                           int64_t total4, int64_t blk, const AdamArgs& A,
+                                           float c1, float c2) {
   const int64_t v = blk * 256ll + threadIdx.x;
   if (v >= total4) return;
   const RedJob J = jobs[find_job(jobs, njobs, v)];
@@ -487,23 +639,34 @@ __device__ __forceinline__ void reduce_few(const char* __restrict__ ws, float* _
   r.z = (s[0].z + s[1].z) + (s[2].z + s[3].z);
   r.w = (s[0].w + s[1].w) + (s[2].w + s[3].w);
   if (o0 < 0) {
-    reinterpret_cast<float4*>(g + J.dst)[i4] = r;
+    if (!ADAM || g) reinterpret_cast<float4*>(g + J.dst)[i4] = r;
+    if (ADAM) adam_at4(A, c1, c2, J.dst / 4 + i4, r);
   } else {  // rows past M inside the last tile are not stored
-    float* q = g + J.dst + o0;
+    const int64_t k = J.dst + o0;
     const int nrow = min(4, J.M - (int)(o0 / J.N));
-    q[0] = r.x;
-    if (nrow > 1) q[J.N] = r.y;
-    if (nrow > 2) q[2 * (int64_t)J.N] = r.z;
-    if (nrow > 3) q[3 * (int64_t)J.N] = r.w;
+    if (!ADAM || g) {
+      float* q = g + k;
+      q[0] = r.x;
+      if (nrow > 1) q[J.N] = r.y;
+      if (nrow > 2) q[2 * (int64_t)J.N] = r.z;
+      if (nrow > 3) q[3 * (int64_t)J.N] = r.w;
+    }
+    if (ADAM) {
+      adam_at(A, c1, c2, k, r.x);
+      if (nrow > 1) adam_at(A, c1, c2, k + J.N, r.y);
+      if (nrow > 2) adam_at(A, c1, c2, k + 2 * (int64_t)J.N, r.z);
+      if (nrow > 3) adam_at(A, c1, c2, k + 3 * (int64_t)J.N, r.w);
+    }
   }
 }
 
 // many parts (per-chunk column partials): 16 outputs per workgroup, the parts
 // over 16 groups, then a fixed-order tree in LDS.  A job with no parts writes
 // zeros (the padding between parameter tensors).
+template <bool ADAM>
 __device__ __forceinline__ void reduce_many(const char* __restrict__ ws, float* __restrict__ g,
                                             const RedJob* __restrict__ jobs, int njobs,
-                                            int64_t blk) {
+                                            int64_t blk, const AdamArgs& A, float c1, float c2) {
   __shared__ float red[16][17];
   const RedJob J = jobs[find_job(jobs, njobs, blk)];
   const int col = threadIdx.x & 15, grp = threadIdx.x >> 4;
@@ -527,30 +690,51 @@ __device__ __forceinline__ void reduce_many(const char* __restrict__ ws, float* 
     if (grp < h) red[grp][col] += red[grp + h][col];
     __syncthreads();
   }
-  if (grp == 0 && i < J.n) g[J.dst + i] = red[0][col];
+  if (grp == 0 && i < J.n) {
+    const float r = red[0][col];
+    if (!ADAM || g) g[J.dst + i] = r;
+    if (ADAM) adam_at(A, c1, c2, J.dst + i, r);
+  }
 }
 
 // Both reductions in one launch: blocks [0, nbf) take the few-part jobs,
-// the rest the many-part jobs.
+// the rest the many-part jobs.  ADAM: each reduced element goes into the
+// Adam step of its parameter (the jobs then cover the whole vector).
+template <bool ADAM>
 __global__ __launch_bounds__(256) void grad_reduce_kernel(const char* __restrict__ ws,
                                                           float* __restrict__ g,
                                                           const RedJob* __restrict__ few,
                                                           int nfew, int64_t total4,
                                                           const RedJob* __restrict__ many,
-                                                          int nmany, int64_t nbf) {
-  if (blockIdx.x < nbf) reduce_few(ws, g, few, nfew, total4, blockIdx.x);
-  else reduce_many(ws, g, many, nmany, blockIdx.x - nbf);
+                                                          int nmany, int64_t nbf, AdamArgs A) {
+  if constexpr (ADAM) {
+    __shared__ __attribute__((aligned(16))) float T[kRedLdsFloats];
+    float c1, c2;
+    adam_factors(A.c, A.step, c1, c2);
+    if (blockIdx.x < nbf) reduce_few_adam(ws, g, few, nfew, blockIdx.x, A, c1, c2, T);
+    else reduce_many<true>(ws, g, many, nmany, blockIdx.x - nbf, A, c1, c2);
+  } else {
+    if (blockIdx.x < nbf) reduce_few<false>(ws, g, few, nfew, total4, blockIdx.x, A, 0.f, 0.f);
+    else reduce_many<false>(ws, g, many, nmany, blockIdx.x - nbf, A, 0.f, 0.f);
+  }
 }
 
 hipError_t launch_grad_reduce(const char* ws, float* g, const RedJob* few, int nfew,
                               int64_t total4, const RedJob* many, int nmany, int64_t nblocks,
-                              double bytes, hipStream_t s) {
-  const int64_t nbf = nfew > 0 ? (total4 + 255) / 256 : 0;
+                              double bytes, hipStream_t s, const AdamArgs* A) {
+  // with Adam, total4 counts chunks of kRedChunk4 float4s
+  const int64_t nbf = nfew > 0 ? (A ? total4 : (total4 + 255) / 256) : 0;
   const int64_t nbm = nmany > 0 ? nblocks : 0;
   if (nbf + nbm == 0) return hipSuccess;
-  CRL_TIMED("grad_reduce_kernel", 0.0, bytes, s,
-            grad_reduce_kernel<<<(unsigned)(nbf + nbm), 256, 0, s>>>(ws, g, few, nfew, total4,
-                                                                      many, nmany, nbf));
+  const dim3 grid((unsigned)(nbf + nbm));
+  if (A)
+    CRL_TIMED("grad_reduce_adam_kernel", 0.0, bytes, s,
+              grad_reduce_kernel<true><<<grid, 256, 0, s>>>(ws, g, few, nfew, total4, many,
+                                                            nmany, nbf, *A));
+  else
+    CRL_TIMED("grad_reduce_kernel", 0.0, bytes, s,
+              grad_reduce_kernel<false><<<grid, 256, 0, s>>>(ws, g, few, nfew, total4, many,
+                                                             nmany, nbf, AdamArgs{}));
   return hipGetLastError();
 }
 
@@ -592,46 +776,21 @@ hipError_t launch_cast_bf16(const float* src, bf16_t* dst, int64_t n, hipStream_
   return hipGetLastError();
 }
 
-// Adam on a flat vector.  Bias corrections 1 - b^t = -expm1(t log b) keep
-// full FP32 relative accuracy (no cancellation in 1 - b^t).
+// Adam on a flat vector (adam_update on every element).
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v,
                                                    bf16_t* __restrict__ pb, int64_t n,
                                                    const int64_t* __restrict__ step, AdamCoef c) {
-  const float t = (float)(*step);
-  const float c1 = 1.f / (-expm1f(t * c.log_b1));
-  const float c2 = 1.f / (-expm1f(t * c.log_b2));
+  float c1, c2;
+  adam_factors(c, step, c1, c2);
+  const AdamArgs A{p, m, v, pb, step, c};
   const int64_t n4 = n >> 2;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    float4 pp = reinterpret_cast<float4*>(p)[i];
-    float4 gg = reinterpret_cast<const float4*>(g)[i];
-    float4 mm = reinterpret_cast<float4*>(m)[i];
-    float4 vv = reinterpret_cast<float4*>(v)[i];
-    float* pa = &pp.x; float* ga = &gg.x; float* ma = &mm.x; float* va = &vv.x;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      ma[k] = c.b1 * ma[k] + c.omb1 * ga[k];
-      va[k] = c.b2 * va[k] + c.omb2 * ga[k] * ga[k];
-      pa[k] -= c.lr * (ma[k] * c1) / (sqrtf(va[k] * c2) + c.eps);
-    }
-    reinterpret_cast<float4*>(p)[i] = pp;
-    reinterpret_cast<float4*>(m)[i] = mm;
-    reinterpret_cast<float4*>(v)[i] = vv;
-    if (pb) {
-      uint2 u;
-      u.x = pack2bf(pp.x, pp.y);
-      u.y = pack2bf(pp.z, pp.w);
-      reinterpret_cast<uint2*>(pb)[i] = u;
-    }
-  }
+       i += (int64_t)gridDim.x * blockDim.x)
+    adam_at4(A, c1, c2, i, reinterpret_cast<const float4*>(g)[i]);
   if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
-    int64_t k = n4 * 4 + threadIdx.x;
-    float mk = c.b1 * m[k] + c.omb1 * g[k];
-    float vk = c.b2 * v[k] + c.omb2 * g[k] * g[k];
-    m[k] = mk; v[k] = vk;
-    p[k] -= c.lr * (mk * c1) / (sqrtf(vk * c2) + c.eps);
-    if (pb) pb[k] = f2bf(p[k]);
+    const int64_t k = n4 * 4 + threadIdx.x;
+    adam_at(A, c1, c2, k, g[k]);
   }
 }
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, bf16_t* pb, int64_t n,

@@ -28,11 +28,15 @@ class CriticUpdate:
     """Device state of the critic update: parameters, Adam moments, batch."""
 
     def __init__(self, w, obs, act, phi_layers, psi_layers,
-                 seed: int = 2, lr: float | None = None, device="cuda:0"):
+                 seed: int = 2, lr: float | None = None, device="cuda:0",
+                 keep_grads: bool = True):
         """obs, act: the static buffer [E][T][d] (one episode per row), or
         obs a ReplayRing and act None (goals clipped to the longest episode
-        w.episode_len and to the end of the drawn step's trajectory)."""
+        w.episode_len and to the end of the drawn step's trajectory).
+        keep_grads: also store each update's critic gradient in self.grads
+        (the Adam step takes it as it is formed either way)."""
         self.w = w
+        self.keep_grads = bool(keep_grads)
         self.dev = torch.device(device)
         self.ring = obs if isinstance(obs, ReplayRing) else None
         self.obs, self.act = (None, None) if self.ring is not None else (obs, act)
@@ -56,7 +60,7 @@ class CriticUpdate:
         self.n = torch.zeros(1, dtype=torch.int64, device=self.dev)  # batch counter
         self.t = self.n  # Adam step (the full update keeps its own)
 
-    def _critic_grads(self, x_sg):
+    def _critic_fwd(self, x_sg):
         c = self.crit
         if self.ring is not None:
             self.ring.sample_relabel(c, self.seed, self.n, self.idx, self.x_sa, self.x_g, x_sg)
@@ -64,16 +68,18 @@ class CriticUpdate:
             c.crl_sample_relabel(self.obs, self.act, self.seed, self.n, self.idx, self.x_sa,
                                  self.x_g, x_sg)
         c.crl_critic_fwd(self.params, self.pbf, self.x_sa, self.x_g, self.ws, self.loss)
-        c.crl_critic_bwd(self.params, self.pbf, self.x_sa, self.x_g, self.ws, self.grads)
 
-    def _critic_adam(self):
-        crl_adam_step(self.params, self.grads, self.m, self.v, self.pbf, self.t, self.lr)
+    def _critic_step(self):
+        """The critic gradient fed into its Adam step (step t)."""
+        self.crit.crl_critic_bwd_adam(self.params, self.pbf, self.x_sa, self.x_g, self.ws,
+                                      self.grads if self.keep_grads else None, self.m, self.v,
+                                      self.t, self.lr)
 
     def enqueue(self):
         """Enqueue one critic update on the current stream (no host sync)."""
-        self._critic_grads(None)
+        self._critic_fwd(None)
         crl_counter_add(self.n, 1)  # also the Adam step
-        self._critic_adam()
+        self._critic_step()
 
     def capture(self, steps: int = 1) -> torch.cuda.CUDAGraph:
         """A HIP graph of `steps` consecutive updates (replay advances n, t)."""
@@ -124,8 +130,10 @@ class FullUpdate(CriticUpdate):
     have zero gradient and stay 0).
     """
 
-    def __init__(self, w, obs, act, phi_layers, psi_layers, actor_layers, seed: int = 2, log_alpha: float = 0.0, device="cuda:0"):
-        super().__init__(w, obs, act, phi_layers, psi_layers, seed=seed, device=device)
+    def __init__(self, w, obs, act, phi_layers, psi_layers, actor_layers, seed: int = 2,
+                 log_alpha: float = 0.0, device="cuda:0", keep_grads: bool = True):
+        super().__init__(w, obs, act, phi_layers, psi_layers, seed=seed, device=device,
+                         keep_grads=keep_grads)
         c = self.crit
         if not c.has_actor:
             raise ValueError("the workload has no policy (actor_hidden is empty)")
@@ -151,9 +159,9 @@ class FullUpdate(CriticUpdate):
     def enqueue(self):
         """Enqueue one full update (critic, policy, alpha) on the current stream."""
         c = self.crit
-        self._critic_grads(self.x_sg)
+        self._critic_fwd(self.x_sg)
         crl_counter_add(self.t, 1)
-        self._critic_adam()
+        self._critic_step()
         c.crl_actor_step(self.params, self.pbf, self.aparams, self.apbf, self.log_alpha,
                          self.x_sa, self.x_g, self.x_sg, self.seed, self.n, self.ws,
                          self.agrads, self.alpha_grad, self.actor_loss)

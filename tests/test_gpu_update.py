@@ -179,3 +179,73 @@ def test_autograd_function_matches_oracle_finite_differences():
         assert err <= tol, (side, l, k, j, g[flat], fd)
     log(f"[fd] 64 coordinates, worst relative deviation {worst:.2e}")
     crit.close()
+
+
+def _bwd_adam_case(case):
+    if case == "bf16_unsplit":   # B < 1024: every dW is one whole-K launch
+        return _small_bf16()
+    if case == "bf16_split":
+        return WL.DOT_B4096_BF16.with_(name="bwdadam_bf16", batch_size=2048,
+                                       hidden=(256,) * 2, num_envs=64, episode_len=64)
+    if case == "bf16_materialised_relu":
+        return WL.DOT_B4096_BF16.with_(name="bwdadam_relu", batch_size=520, hidden=(128,) * 3,
+                                       activation="relu", logits="materialised",
+                                       num_envs=32, episode_len=64)
+    if case == "fp32_unsplit":
+        return WL.LN_FWD_FP32.with_(name="bwdadam_fp32", batch_size=200, hidden=(96,) * 2,
+                                    num_envs=16, episode_len=40)
+    return WL.LN_FWD_FP32.with_(name="bwdadam_fp32s", batch_size=1024, hidden=(128,) * 2,
+                                num_envs=32, episode_len=64)
+
+
+@pytest.mark.parametrize("case", ["bf16_unsplit", "bf16_split", "bf16_materialised_relu",
+                                  "fp32_unsplit", "fp32_split"])
+def test_bwd_adam_equals_bwd_then_adam(case):
+    """crl_critic_bwd_adam against crl_critic_bwd followed by crl_adam_step on
+    the same batch: parameters, BF16 copy, m and v bit for bit over three
+    steps, the gradient (when kept) equal as values."""
+    from paper_2408_11052_amd import Critic, crl_adam_step, crl_cast_bf16
+    w = _bwd_adam_case(case)
+    obs, act, phi, psi = setup(w, perturb=0.1)
+    log(f"[bwd_adam] {case}: B={w.batch_size} hidden={w.hidden} prec={w.precision}")
+    crit = Critic(w, max_episode_len=obs.shape[1])
+    d_obs, d_act = torch.from_numpy(obs).to(DEV), torch.from_numpy(act).to(DEV)
+    packed = torch.from_numpy(crit.pack(phi, psi)).to(DEV)
+
+    def state():
+        s = {"p": packed.clone(), "pb": None, "m": torch.zeros_like(packed),
+             "v": torch.zeros_like(packed),
+             "g": torch.full_like(packed, float("nan"))}
+        if w.precision == "bf16":
+            s["pb"] = torch.empty(crit.nparam, dtype=torch.bfloat16, device=DEV)
+            crl_cast_bf16(s["p"], s["pb"])
+        return s
+
+    a, b = state(), state()
+    x_sa, x_g, x_sg = crit.inputs(DEV)
+    ws = crit.workspace(DEV)
+    idx = torch.zeros(w.batch_size, 3, dtype=torch.int32, device=DEV)
+    loss = torch.zeros(8, dtype=torch.float32, device=DEV)
+    t = torch.zeros(1, dtype=torch.int64, device=DEV)
+    lr = 3e-4
+    bits = lambda x: x.view(torch.int32) if x.dtype == torch.float32 else x.view(torch.int16)
+    for step in range(3):
+        d_step = torch.tensor([step], dtype=torch.int64, device=DEV)
+        t.fill_(step + 1)
+        keep = step != 1
+        crit.crl_sample_relabel(d_obs, d_act, 2, d_step, idx, x_sa, x_g, x_sg)
+        crit.crl_critic_fwd(a["p"], a["pb"], x_sa, x_g, ws, loss)
+        crit.crl_critic_bwd(a["p"], a["pb"], x_sa, x_g, ws, a["g"])
+        crl_adam_step(a["p"], a["g"], a["m"], a["v"], a["pb"], t, lr)
+        crit.crl_sample_relabel(d_obs, d_act, 2, d_step, idx, x_sa, x_g, x_sg)
+        crit.crl_critic_fwd(b["p"], b["pb"], x_sa, x_g, ws, loss)
+        crit.crl_critic_bwd_adam(b["p"], b["pb"], x_sa, x_g, ws, b["g"] if keep else None,
+                                 b["m"], b["v"], t, lr)
+        torch.cuda.synchronize()
+        if keep:
+            assert torch.equal(a["g"], b["g"]), step
+        for k in ("p", "m", "v", "pb"):
+            if a[k] is not None:
+                assert torch.equal(bits(a[k]), bits(b[k])), (step, k)
+    assert float(a["m"].abs().max()) > 0.0
+    crit.close()
