@@ -18,10 +18,14 @@ constexpr int kWave = 64;
 __device__ inline bf16_t f2bf(float f) {
   return __builtin_bit_cast(bf16_t, (__bf16)f);
 }
-// Two values packed low/high into one 32-bit word (one conversion instruction).
+// Two values packed low/high into one 32-bit word: one v_cvt_pk_bf16_f32 (the
+// two-element vector conversion; two scalar conversions would take four
+// instructions with the shift and the merge).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ inline uint32_t pack2bf(float lo, float hi) {
-  return (uint32_t)__builtin_bit_cast(bf16_t, (__bf16)lo) |
-         ((uint32_t)__builtin_bit_cast(bf16_t, (__bf16)hi) << 16);
+  const f32x2_t f = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
 }
 __device__ inline float bf2f(bf16_t h) {
   return __builtin_bit_cast(float, (uint32_t)h << 16);

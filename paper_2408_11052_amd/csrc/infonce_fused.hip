@@ -198,6 +198,28 @@ __device__ __forceinline__ float energy_f(float v, float nx, float ny, float& d)
   d = 0.f;
   return v;
 }
+// The same for the backward, with the factor w that turns the gradient of the
+// energy's argument into the tile entry: for L2, 1 / d (0 where d is 0) from
+// one reciprocal square root, d = d2 / sqrt(d2) (a NaN operand stays NaN in
+// both); 2 for the squared distance; 1 for the product.
+template <int EN>
+__device__ __forceinline__ float energy_fw(float v, float nx, float ny, float& w) {
+  if (EN == kEnL2) {
+    const float t = nx + ny;
+    const float d2 = __builtin_fmaf(-2.f, v, t);
+    const bool zero = d2 <= kL2Floor * t;
+    const float r = __builtin_amdgcn_rsqf(d2);
+    w = zero ? 0.f : r;
+    return zero ? -0.f : -(d2 * r);
+  }
+  if (EN == kEnL2sq) {
+    const float d2 = __builtin_fmaf(-2.f, v, nx + ny);
+    w = 2.f;
+    return d2 < 0.f ? -0.f : -d2;
+  }
+  w = 1.f;
+  return v;
+}
 __device__ __forceinline__ float exp_diff(float x, float m) {
   return __builtin_amdgcn_exp2f((x - m) * kL2E);
 }
@@ -528,10 +550,10 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
     // terms, H, the rows' sums and the strip store
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
-      float h[4], dd[4];
+      float h[4], wv[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float fv = energy_f<EN>(acc[jb][r], nx[r], cvals.ny[jb], dd[r]);
+        const float fv = energy_fw<EN>(acc[jb][r], nx[r], cvals.ny[jb], wv[r]);
         const float pa = __builtin_amdgcn_exp2f(__builtin_fmaf(fv, kL2E, -sh_a[r]));
         const float pb = __builtin_amdgcn_exp2f(__builtin_fmaf(fv, kL2E, -sh_b[jb]));
         h[r] = TRANS ? __builtin_fmaf(pb, k_b[jb], pa) : __builtin_fmaf(pa, k_a[r], pb);
@@ -549,8 +571,7 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
       // H = G / d (L2; 0 where d = 0) or 2 G (L2 without the root)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (EN == kEnL2) h[r] = dd[r] > 0.f ? h[r] * __builtin_amdgcn_rcpf(dd[r]) : 0.f;
-        if (EN == kEnL2sq) h[r] *= 2.f;
+        if (EN != kEnDot) h[r] *= wv[r];
         hsum[r] += h[r];
       }
       uint2 w;
@@ -723,10 +744,10 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
     float hcol[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
-      float h[4], dd[4];
+      float h[4], wv[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float fv = energy_f<EN>(acc[jb][r], nx[r], ny[jb], dd[r]);
+        const float fv = energy_fw<EN>(acc[jb][r], nx[r], ny[jb], wv[r]);
         const float pa = __builtin_amdgcn_exp2f(__builtin_fmaf(fv, kL2E, -sh_r[r]));
         const float pb = __builtin_amdgcn_exp2f(__builtin_fmaf(fv, kL2E, -sh_c[jb]));
         h[r] = __builtin_fmaf(pa, k_r[r], pb);
@@ -743,8 +764,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (EN == kEnL2) h[r] = dd[r] > 0.f ? h[r] * __builtin_amdgcn_rcpf(dd[r]) : 0.f;
-        if (EN == kEnL2sq) h[r] *= 2.f;
+        if (EN != kEnDot) h[r] *= wv[r];
         hrow[r] += h[r];
         hcol[jb] += h[r];
       }
