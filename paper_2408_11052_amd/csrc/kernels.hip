@@ -147,15 +147,16 @@ __global__ __launch_bounds__(256) void ln_swish_fwd_kernel(LnArgs a, int B, int 
     if (lane + 64 * c < nch)
 #pragma unroll
       for (int i = 0; i < 8; ++i) s += v[c][i];
-  const float mean = wave_sum(s) / (float)N;
+  const float inv_n = 1.f / (float)N;  // exact for the power-of-two widths
+  const float mean = wave_sum(s) * inv_n;
   float q = 0.f;
 #pragma unroll
   for (int c = 0; c < CH; ++c)
     if (lane + 64 * c < nch)
 #pragma unroll
       for (int i = 0; i < 8; ++i) { float d = v[c][i] - mean; q += d * d; }
-  const float var = wave_sum(q) / (float)N;
-  const float rstd = 1.f / sqrtf(var + eps);
+  const float var = wave_sum(q) * inv_n;
+  const float rstd = __builtin_amdgcn_rsqf(var + eps);  // hardware 1/sqrt (1 ulp)
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     const int ch = lane + 64 * c;
@@ -234,6 +235,7 @@ __global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int 
     for (int i = 0; i < 8; ++i) { cg[c][i] = cb[c][i] = cz[c][i] = gv[c][i] = bv[c][i] = 0.f; }
     if (ch < nch) { load8(a.g[e] + ch * 8, gv[c]); load8(a.b[e] + ch * 8, bv[c]); }
   }
+  const float inv_n = 1.f / (float)N;
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     if (j >= nr) break;
@@ -250,9 +252,11 @@ __global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int 
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const float xh = (z[i] - mu[j]) * rs[j];
-          const float y = gv[c][i] * xh + bv[c][i];
+          const float y = __builtin_fmaf(gv[c][i], xh, bv[c][i]);
           const float sg = sigmoidf_(y);
-          const float dy = dh[i] * (sg * (1.f + y * (1.f - sg)));
+          // Swish'(y) = sg (1 + y (1 - sg)) = sg + y sg (1 - sg)
+          const float q = __builtin_fmaf(-sg, sg, sg);
+          const float dy = dh[i] * __builtin_fmaf(y, q, sg);
           cg[c][i] += dy * xh;
           cb[c][i] += dy;
           const float d = dy * gv[c][i];
@@ -263,8 +267,10 @@ __global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int 
         }
       }
     }
-    const float m1 = wave_sum(s1) / (float)N;
-    const float m2 = wave_sum(s2) / (float)N;
+    // dz = rstd (dzhat - m1 - zhat m2) = rstd dzhat + (e zhat + k),
+    // e = -rstd m2, k = -rstd m1
+    const float k = -rs[j] * (wave_sum(s1) * inv_n);
+    const float e = -rs[j] * (wave_sum(s2) * inv_n);
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int ch = lane + 64 * c;
@@ -272,7 +278,7 @@ __global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int 
         float o[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          o[i] = rs[j] * (dzh[c][i] - m1 - zh[c][i] * m2);
+          o[i] = __builtin_fmaf(rs[j], dzh[c][i], __builtin_fmaf(e, zh[c][i], k));
           cz[c][i] += o[i];
         }
         store8(dZb + (int64_t)row * N + ch * 8, o);
