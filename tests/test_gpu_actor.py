@@ -196,6 +196,17 @@ def test_full_update_trajectory_fp32_random_goals():
                 10, 1e-4, 1e-4)
 
 
+@pytest.mark.slow
+def test_full_update_trajectory_b4096_fp32():
+    """Five free-running full updates at the B=4096 full-update shapes (4x1024
+    LN+Swish critic, 4x1024 policy) on the FP32 GPU path (FP32 tiles,
+    materialised logits) against the FP64 oracle: every step's critic and
+    policy losses and log alpha, with no state copied between the two."""
+    w = WL.FULL_UPDATE_B4096.with_(name="full_b4096_fp32", precision="fp32",
+                                   logits="materialised")
+    _trajectory(w, 5, 1e-4, 1e-4, perturb=0.0)
+
+
 def _oracle_from_gpu(ou, gu):
     """Copy the GPU's whole update state (parameters, Adam moments, log alpha,
     step) into the oracle, in FP64."""
