@@ -138,7 +138,7 @@ CRL_API int crl_param_count(const crl_ctx* ctx, int64_t* n);
 CRL_API int crl_actor_param_count(const crl_ctx* ctx, int64_t* n);
 /* Offsets of layer `layer` (0 = first) of net 0 (phi) or 1 (psi), in the
  * critic vector, or of net 2 (the policy), in the policy vector.  The policy's
- * output layer has fan_out = 2 act_dim rounded up to a multiple of 8: columns
+ * output layer has fan_out = 2 act_dim rounded up to a multiple of 64: columns
  * [0, act_dim) are the mean, [act_dim, 2 act_dim) the scale pre-activation,
  * the rest padding whose gradient is 0 (zero-initialised, it stays 0). */
 CRL_API int crl_layer_layout(const crl_ctx* ctx, int32_t net, int32_t layer,

@@ -1071,7 +1071,9 @@ CRL_API int crl_create(const crl_config* cfg, crl_ctx** out) {
   x->D = cfg->repr_dim;
   x->L = cfg->n_hidden;
   x->A = cfg->act_dim;
-  x->P = (int)align_up(2 * cfg->act_dim, 8);
+  // the policy head's width, padded to whole 64-deep K steps so that its
+  // input gradient (K = P) runs on the direct-to-LDS GEMM, paired with its dW
+  x->P = (int)align_up(2 * cfg->act_dim, 64);
   x->esz = x->bf16 ? 2 : 4;
   const int fan_in0[3] = {cfg->obs_dim + cfg->act_dim, cfg->goal_dim, cfg->obs_dim + cfg->goal_dim};
   for (int e = 0; e < 3; ++e) {

@@ -54,15 +54,18 @@ static const char* lds_kernel_name() {
 }
 
 // The direct-to-LDS kernel takes a launch whose K ranges are all whole 64-deep
-// steps, with 16-byte rows and N a multiple of 8 (ragged M and N are handled
-// by clamped loads and guarded stores).  Its column tile is 128 wide, as the
+// steps, with 16-byte rows (ragged M and N are handled by clamped loads and
+// guarded stores).  N not a multiple of 8 is taken only where the results are
+// stored plainly (no mask epilogue, no fragment-order partials): those column
+// tails are stored element by element.  Its column tile is 128 wide, as the
 // planned grid; or 64 wide when no problem is wider than 64 (one column tile
 // either way).
 static int lds_path_bn(const GemmParams& P) {
   int nmax = 0;
   for (int g = 0; g < P.count; ++g) {
     const GemmDesc& d = P.d[g];
-    if (d.K % lds::BK || P.k_chunk % lds::BK || d.N % 8) return 0;
+    if (d.K % lds::BK || P.k_chunk % lds::BK) return 0;
+    if (d.N % 8 && (P.defer_reduce || (d.epi != EPI_NONE && d.epi != EPI_BIAS))) return 0;
     if (d.lda % 8 || d.ldb % 8 || d.ldc % 8) return 0;
     if (d.epi == EPI_L2 || d.epi == EPI_L2SQ || d.accumulate) return 0;
     if ((reinterpret_cast<uintptr_t>(d.A) | reinterpret_cast<uintptr_t>(d.B) |

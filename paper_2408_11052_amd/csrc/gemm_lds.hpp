@@ -8,7 +8,8 @@
 // 128 or 64, computed by BN/16 waves of 64 x 32 each (eight or four waves: more
 // resident waves hide more of the load and barrier latency than larger
 // per-wave blocks save in LDS reads).  M and N may be ragged (loads past the edge are clamped into the
-// operand and the results they feed are not stored); every K range must be a
+// operand and the results they feed are not stored; an N that is not a multiple of 8 is stored
+// element by element); every K range must be a
 // whole number of 64-deep steps, otherwise gemm_kernel takes the launch.
 #pragma once
 #include "gemm.hpp"
@@ -228,11 +229,20 @@ __device__ __forceinline__ void gemm_lds_tile(const GemmParams& P, const WorkIte
   const int col0 = n0 + ch * 8;
   const int rows = min(BM, D.M - m0);
   if (col0 >= D.N) return;
+  // N not a multiple of 8 (a few output columns, no mask epilogue): element stores
+  const int nc = min(8, D.N - col0);
+  const bool ragged = (D.N & 7) != 0;
   if (split) {
     float* out = P.partial + (int64_t)gi * P.partial_len + (int64_t)wi.split * D.M * D.N;
     for (int rl = tid / TPR; rl < rows; rl += RSTEP) {
       const float* src = Cs + rl * kLdc + ch * 8;
       float* dst = out + (int64_t)(m0 + rl) * D.N + col0;
+      if (ragged) {  // unrolled with constant indices: no private-memory array
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k < nc) dst[k] = src[k];
+        continue;
+      }
       *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(src);
       *reinterpret_cast<float4*>(dst + 4) = *reinterpret_cast<const float4*>(src + 4);
     }
@@ -251,6 +261,12 @@ __device__ __forceinline__ void gemm_lds_tile(const GemmParams& P, const WorkIte
       load8_any(aux + o, a8);
 #pragma unroll
       for (int k = 0; k < 8; ++k) v[k] = a8[k] > 0.f ? v[k] : 0.f;
+    }
+    if (ragged) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < nc) C[o + k] = Store<OutT>::from_f(v[k]);
+      continue;
     }
     store8_any(C + o, v);
   }
