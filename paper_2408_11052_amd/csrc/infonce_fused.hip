@@ -293,21 +293,26 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
   }
 
   // column (max, sum) partials of a finished tile, merged over the 16
-  // (wave, row group) entries: their max first, then the rescaled sums in a
-  // fixed order.  The tiles' merges rotate over the four waves.
+  // (wave, row group) entries: their max first, then the rescaled sums.  Each
+  // wave takes 16 of the tile's columns, four lanes per column, each lane four
+  // of the entries; the lanes' maxima and sums then meet by butterflies over
+  // the lane groups (a fixed order).  Every wave does its share every tile, so
+  // no wave arrives at the next barrier with the whole merge.
   auto flush_cols = [&](int jp) {
-    const int col = jp + lane;
-    if (col < c1) {
-      float mv[16], sv[16];
+    const int cl = wave * 16 + r16;
+    float mv[4], sv[4];
 #pragma unroll
-      for (int w = 0; w < 16; ++w) { mv[w] = cm_s[w][lane]; sv[w] = cs_s[w][lane]; }
-      float cm = mv[0];
+    for (int i = 0; i < 4; ++i) { mv[i] = cm_s[4 * g + i][cl]; sv[i] = cs_s[4 * g + i][cl]; }
+    float cm = fmaxf(__builtin_fmaxf(mv[0], mv[1]), __builtin_fmaxf(mv[2], mv[3]));
+    cm = fmaxf(cm, __shfl_xor(cm, 16, 64));
+    cm = fmaxf(cm, __shfl_xor(cm, 32, 64));
+    float cs = 0.f;
 #pragma unroll
-      for (int w = 1; w < 16; ++w) cm = fmaxf(cm, mv[w]);
-      float cs = 0.f;
-#pragma unroll
-      for (int w = 0; w < 16; ++w)
-        cs += sv[w] == 0.f ? 0.f : sv[w] * exp_diff(mv[w], cm);
+    for (int i = 0; i < 4; ++i) cs += sv[i] == 0.f ? 0.f : sv[i] * exp_diff(mv[i], cm);
+    cs += __shfl_xor(cs, 16, 64);
+    cs += __shfl_xor(cs, 32, 64);
+    const int col = jp + cl;
+    if (g == 0 && col < c1) {
       a.col_m[(int64_t)rb * B + col] = cm;
       a.col_s[(int64_t)rb * B + col] = cs;
     }
@@ -329,10 +334,9 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
     for (int jb = 0; jb < 4; ++jb) nypf[jb] = j0 + jb * 16 + r16 < c1 ? base[jb * 16 + r16] : 0.f;
   };
   if (c0 < c1) { tile_load<D>(pf, a.psi_b, c0, B, tid); ny_load(c0); }
-  int t = 0;
-  for (int j0 = c0; j0 < c1; j0 += kFCols, ++t) {
+  for (int j0 = c0; j0 < c1; j0 += kFCols) {
     __syncthreads();
-    if (j0 > c0 && wave == ((t - 1) & 3)) flush_cols(j0 - kFCols);
+    if (j0 > c0) flush_cols(j0 - kFCols);
     tile_store_rows<D, LDY>(Ys, pf, tid);
     float nyv[4];
 #pragma unroll
@@ -395,7 +399,7 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
   }
   if (c0 < c1) {
     __syncthreads();
-    if (wave == ((t - 1) & 3)) flush_cols(jlast);
+    flush_cols(jlast);
   }
   // merge the row states across the 16 lanes that share each row: the max
   // by a butterfly, then the sums rescaled to it by a butterfly (every lane
