@@ -103,6 +103,11 @@ CASES = {
     "bf16_dot_ln_random_goals": SMALL.with_(name="actor_rg_bf16", precision="bf16",
                                             logits="fused", batch_size=256, hidden=(128, 128),
                                             actor_hidden=(128,) * 3, random_goal_ratio=0.3),
+    # a wide action: the input gradient over the action columns has N = 70, a
+    # 128-wide tile with a ragged tail, and the head 192 columns
+    "bf16_dot_ln_wide_action": SMALL.with_(name="actor_wide_action", precision="bf16",
+                                           logits="fused", act_dim=70, batch_size=256,
+                                           hidden=(128, 128), actor_hidden=(128, 128)),
 }
 
 
@@ -119,7 +124,9 @@ def test_actor_step_matches_oracle(case):
     err_eps = np.max(np.abs(g["eps"] - o["eps"]) / np.maximum(1.0, np.abs(o["eps"])))
     log(f"[actor] eps max rel err {err_eps:.2e}")
     assert err_eps < 1e-5
-    tol_loss = 1e-2 if bf16 else 1e-4
+    # log pi sums act_dim terms, each carrying the BF16 rounding of the head's
+    # outputs: the BF16 bar grows with the action width beyond 17
+    tol_loss = 1e-2 * max(1.0, w.act_dim / 17) if bf16 else 1e-4
     scale = abs(math.exp(la) * o["mean_log_pi"]) + abs(np.mean(o["f"]))
     d_loss = abs(g["loss"][0] - o["loss"])
     d_lp = abs(g["loss"][1] - o["mean_log_pi"])
@@ -129,7 +136,7 @@ def test_actor_step_matches_oracle(case):
     assert d_loss <= tol_loss * scale
     assert d_lp <= tol_loss * max(1.0, abs(o["mean_log_pi"]))
     assert d_ag <= tol_loss * max(1.0, abs(o["d_log_alpha"]))
-    assert rel_l2(g["log_pi"], o["log_pi"]) < (2e-2 if bf16 else 1e-5)
+    assert rel_l2(g["log_pi"], o["log_pi"]) < (2 * tol_loss if bf16 else 1e-5)
     assert rel_l2(g["f"], o["f"]) < (2e-2 if bf16 else 1e-5)
     cos_min = 0.999 if bf16 else 0.99999
     for l, (gl, ol) in enumerate(zip(g["g"], o["g_actor"])):
