@@ -433,7 +433,11 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
 // TRANS = 1: rows are psi, streamed operand phi -> partials of dpsi.
 // Per 64-column tile: F (MFMA), G (or H) into the wave's own LDS strip, then
 // dX += G . Y with the Y operand read from the row-major tile by the 16-bit
-// transpose read (no transposed copy of the tile is kept).  The tile's
+// transpose read (no transposed copy of the tile is kept).  For D >= 128 the
+// product is split over D instead of rows: after a workgroup barrier each
+// wave multiplies all four strips (64 rows) by its quarter of the tile's
+// columns, so the tile is read once per workgroup in that product rather
+// than once per wave; for D <= 64 a wave reads its own strip back.  The tile's
 // column values (the other side's LSE, |y|^2) are fetched together with the
 // tile, one tile ahead.
 //
@@ -454,6 +458,9 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
   constexpr int LDY = D + 8;
   constexpr int LDG = 16;     // transposed G strip: [64 columns][16 rows]
   constexpr int NB = D / 16;  // 16-wide output blocks of dX
+  // D >= 128: wave w owns columns [w D/4, (w+1) D/4) of dX for all 64 rows
+  constexpr bool DSPLIT = NB >= 8;
+  constexpr int NW = NB / 4;  // 16-wide output blocks per wave when split
   typedef short v4s __attribute__((ext_vector_type(4)));
   typedef short v8s __attribute__((ext_vector_type(8)));
   typedef __attribute__((address_space(3))) v4s lds_v4s;
@@ -583,54 +590,104 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
       w.y = pack2bf(h[2], h[3]);
       *reinterpret_cast<uint2*>(&Gt[wave][(jb * 16 + r16) * LDG + 4 * g]) = w;
     }
-    // only this wave reads its strip back: a wave-local LDS wait suffices
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-    __builtin_amdgcn_wave_barrier();
-    // dX[16 rows][D] += G[16][64] . Y[64][D]; lane (g, j) needs G[j][8g + 0..7]
-    // and Y[8g + 0..7][d] of column d = nb*16 + j: transpose reads of 4 rows
+    if constexpr (DSPLIT) {
+      // every wave reads all four strips: a workgroup barrier
+      __syncthreads();
+      // dX[64 rows][this wave's D/4 columns] += G[64][64] . Y[64][D/4 columns];
+      // the A fragments of the four strips are read once and each used NW times
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      v4s gq[2];
+      for (int kk = 0; kk < 2; ++kk) {
+        bf16x8 ga[4];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
-        gq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-            (lds_v4s*)(&Gt[wave][krow * LDG + 4 * (r16 & 3)]));
-      }
-      v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
-      const bf16x8 ga = __builtin_bit_cast(bf16x8, gv8);
-      // up to four output blocks at a time: their B fragments read together
-      constexpr int NU = NB < 4 ? NB : 4;
+        for (int st = 0; st < 4; ++st) {
+          v4s gq[2];
 #pragma unroll
-      for (int nb0 = 0; nb0 < NB; nb0 += NU) {
-        v4s hq[NU][2];
+          for (int q = 0; q < 2; ++q) {
+            const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+            gq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                (lds_v4s*)(&Gt[st][krow * LDG + 4 * (r16 & 3)]));
+          }
+          v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
+          ga[st] = __builtin_bit_cast(bf16x8, gv8);
+        }
 #pragma unroll
-        for (int u = 0; u < NU; ++u)
+        for (int u = 0; u < NW; ++u) {
+          v4s hq[2];
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
             const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
-            const int dcol = (nb0 + u) * 16 + 4 * (r16 & 3);
-            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_at<D>(jrow, dcol)));
+            const int dcol = (wave * NW + u) * 16 + 4 * (r16 & 3);
+            hq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_at<D>(jrow, dcol)));
           }
+          v8s yv = {hq[0][0], hq[0][1], hq[0][2], hq[0][3], hq[1][0], hq[1][1], hq[1][2], hq[1][3]};
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          v8s yv = {hq[u][0][0], hq[u][0][1], hq[u][0][2], hq[u][0][3],
-                    hq[u][1][0], hq[u][1][1], hq[u][1][2], hq[u][1][3]};
-          acc_dx[nb0 + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              ga, __builtin_bit_cast(bf16x8, yv), acc_dx[nb0 + u], 0, 0, 0);
+          for (int st = 0; st < 4; ++st)
+            acc_dx[st * NW + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                ga[st], __builtin_bit_cast(bf16x8, yv), acc_dx[st * NW + u], 0, 0, 0);
+        }
+      }
+    } else {
+      // only this wave reads its strip back: a wave-local LDS wait suffices
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+      __builtin_amdgcn_wave_barrier();
+      // dX[16 rows][D] += G[16][64] . Y[64][D]; lane (g, j) needs G[j][8g + 0..7]
+      // and Y[8g + 0..7][d] of column d = nb*16 + j: transpose reads of 4 rows
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        v4s gq[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+          gq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+              (lds_v4s*)(&Gt[wave][krow * LDG + 4 * (r16 & 3)]));
+        }
+        v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
+        const bf16x8 ga = __builtin_bit_cast(bf16x8, gv8);
+        // up to four output blocks at a time: their B fragments read together
+        constexpr int NU = NB < 4 ? NB : 4;
+#pragma unroll
+        for (int nb0 = 0; nb0 < NB; nb0 += NU) {
+          v4s hq[NU][2];
+#pragma unroll
+          for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+              const int dcol = (nb0 + u) * 16 + 4 * (r16 & 3);
+              hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_at<D>(jrow, dcol)));
+            }
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            v8s yv = {hq[u][0][0], hq[u][0][1], hq[u][0][2], hq[u][0][3],
+                      hq[u][1][0], hq[u][1][1], hq[u][1][2], hq[u][1][3]};
+            acc_dx[nb0 + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                ga, __builtin_bit_cast(bf16x8, yv), acc_dx[nb0 + u], 0, 0, 0);
+          }
         }
       }
     }
   }
   // write this split's partials (the two passes use separate halves)
   float* dst = a.dX_part + ((int64_t)TRANS * gridDim.y + blockIdx.y) * B * D;
+  if constexpr (DSPLIT) {
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
+    for (int st = 0; st < 4; ++st)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row_base + 4 * g + r;
-      if (row < B) dst[(int64_t)row * D + nb * 16 + r16] = acc_dx[nb][r];
-    }
+      for (int u = 0; u < NW; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rb * kFRows + st * 16 + 4 * g + r;
+          if (row < B) dst[(int64_t)row * D + (wave * NW + u) * 16 + r16] = acc_dx[st * NW + u][r];
+        }
+  } else {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_base + 4 * g + r;
+        if (row < B) dst[(int64_t)row * D + nb * 16 + r16] = acc_dx[nb][r];
+      }
+  }
   if (L2) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
