@@ -48,6 +48,26 @@ __device__ inline float wave_sum(float v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
+// Sum over the wavefront for code where all 64 lanes are active: a butterfly
+// inside each 16-lane row by DPP moves (pairs within quads, then the half-row
+// and row mirrors), then the four row sums read out of lanes 0, 16, 32 and 48
+// and added in a fixed order.  Every lane gets the same bits; no LDS traffic.
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                               0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum_full(float v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  const int u = __builtin_bit_cast(int, v);
+  const float a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(u, 0));
+  const float b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(u, 16));
+  const float c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(u, 32));
+  const float d = __builtin_bit_cast(float, __builtin_amdgcn_readlane(u, 48));
+  return (a + b) + (c + d);
+}
 __device__ inline float wave_max(float v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));

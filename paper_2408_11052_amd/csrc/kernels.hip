@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void ln_swish_fwd_kernel(LnArgs a, int B, int 
   const int e = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= B) return;
+  if (row >= B) return;  // whole wavefronts: the row sums below see all 64 lanes
   const int nch = N >> 3;
   const T* z = reinterpret_cast<const T*>(a.Z[e]) + (int64_t)row * N;
   T* h = reinterpret_cast<T*>(a.H[e]) + (int64_t)row * N;
@@ -148,14 +148,14 @@ __global__ __launch_bounds__(256) void ln_swish_fwd_kernel(LnArgs a, int B, int 
 #pragma unroll
       for (int i = 0; i < 8; ++i) s += v[c][i];
   const float inv_n = 1.f / (float)N;  // exact for the power-of-two widths
-  const float mean = wave_sum(s) * inv_n;
+  const float mean = wave_sum_full(s) * inv_n;
   float q = 0.f;
 #pragma unroll
   for (int c = 0; c < CH; ++c)
     if (lane + 64 * c < nch)
 #pragma unroll
       for (int i = 0; i < 8; ++i) { float d = v[c][i] - mean; q += d * d; }
-  const float var = wave_sum(q) * inv_n;
+  const float var = wave_sum_full(q) * inv_n;
   const float rstd = __builtin_amdgcn_rsqf(var + eps);  // hardware 1/sqrt (1 ulp)
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int 
   const float inv_n = 1.f / (float)N;
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    if (j >= nr) break;
+    if (j >= nr) break;  // uniform over the wavefront, as the row sums need
     const int row = r0 + j;
     float zh[CH][8], dzh[CH][8];
     float s1 = 0.f, s2 = 0.f;
@@ -269,8 +269,8 @@ __global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int 
     }
     // dz = rstd (dzhat - m1 - zhat m2) = rstd dzhat + (e zhat + k),
     // e = -rstd m2, k = -rstd m1
-    const float k = -rs[j] * (wave_sum(s1) * inv_n);
-    const float e = -rs[j] * (wave_sum(s2) * inv_n);
+    const float k = -rs[j] * (wave_sum_full(s1) * inv_n);
+    const float e = -rs[j] * (wave_sum_full(s2) * inv_n);
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int ch = lane + 64 * c;
