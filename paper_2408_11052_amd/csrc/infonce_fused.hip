@@ -207,10 +207,12 @@ __device__ __forceinline__ float energy_fw(float v, float nx, float ny, float& w
   if (EN == kEnL2) {
     const float t = nx + ny;
     const float d2 = __builtin_fmaf(-2.f, v, t);
-    const bool zero = d2 <= kL2Floor * t;
-    const float r = __builtin_amdgcn_rsqf(d2);
-    w = zero ? 0.f : r;
-    return zero ? -0.f : -(d2 * r);
+    // the masked entries take r = 0, so that f = -(d2 r) is a signed zero:
+    // only exponentials of f are taken, and those do not see the sign (a
+    // squared norm that overflows to inf gives NaN here, as it should)
+    const float r = d2 <= kL2Floor * t ? 0.f : __builtin_amdgcn_rsqf(d2);
+    w = r;
+    return -(d2 * r);
   }
   if (EN == kEnL2sq) {
     const float d2 = __builtin_fmaf(-2.f, v, nx + ny);
