@@ -431,6 +431,18 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
   }
 }
 
+// Element offset of (column c, row e) in a wave's transposed G strip: 64
+// columns of 16 BF16 rows (32 bytes each).  Inside each group of 16 columns,
+// column c8 + 8t (c8 < 8, t = 0 or 1) sits in 32-byte slot (c8 + 4t) mod 8 of
+// the group's t-th 256-byte half, its two 16-byte halves swapped when t = 1.
+// A half-wave's strip store (16 columns, 16 bytes each) and transpose read
+// (columns c..c+3 and c+8..c+11, 32 bytes each) then fall on 64 distinct
+// banks; with plain 32-byte rows both were two-way conflicts.
+__device__ __forceinline__ int gt_at(int c, int e) {
+  const int t = (c >> 3) & 1;
+  return (c & ~15) * 16 + t * 128 + (((c & 7) + 4 * t) & 7) * 16 + (e ^ (8 * t));
+}
+
 // TRANS = 0: rows are phi, streamed operand psi -> partials of dphi.
 // TRANS = 1: rows are psi, streamed operand phi -> partials of dpsi.
 // Per 64-column tile: F (MFMA), G (or H) into the wave's own LDS strip, then
@@ -590,7 +602,7 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
       uint2 w;
       w.x = pack2bf(h[0], h[1]);
       w.y = pack2bf(h[2], h[3]);
-      *reinterpret_cast<uint2*>(&Gt[wave][(jb * 16 + r16) * LDG + 4 * g]) = w;
+      *reinterpret_cast<uint2*>(&Gt[wave][gt_at(jb * 16 + r16, 4 * g)]) = w;
     }
     if constexpr (DSPLIT) {
       // every wave reads all four strips: a workgroup barrier
@@ -607,7 +619,7 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
           for (int q = 0; q < 2; ++q) {
             const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
             gq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-                (lds_v4s*)(&Gt[st][krow * LDG + 4 * (r16 & 3)]));
+                (lds_v4s*)(&Gt[st][gt_at(krow, 4 * (r16 & 3))]));
           }
           v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
           ga[st] = __builtin_bit_cast(bf16x8, gv8);
@@ -641,7 +653,7 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
         for (int q = 0; q < 2; ++q) {
           const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
           gq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-              (lds_v4s*)(&Gt[wave][krow * LDG + 4 * (r16 & 3)]));
+              (lds_v4s*)(&Gt[wave][gt_at(krow, 4 * (r16 & 3))]));
         }
         v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
         const bf16x8 ga = __builtin_bit_cast(bf16x8, gv8);
