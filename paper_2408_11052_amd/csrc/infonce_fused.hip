@@ -139,23 +139,33 @@ __device__ __forceinline__ void tile_load(TileRegs<D>& t, const bf16_t* __restri
   }
 }
 
-// LDS rows of D BF16 values are padded to D + 8 (a row stride of 4 mod 64
-// banks of 4 bytes) and stored in a permuted order: inside each group of 16
-// rows, row 8a + 4b + t (t < 4) sits at 8a + 2t + b.  Two reads then find
-// distinct banks: the MFMA's row operand (a ds_read_b128 pass of 16 lanes,
-// rows r0..r0+15, one 16-byte chunk each: 16 distinct positions, 4 banks
-// apart) and the transpose read (a half-wave: rows 4b + t and 8 + 4b + t,
-// 32 contiguous bytes of each, whose positions 2t + b and 8 + 2t + b lie an
-// even number of rows apart, 8 banks).  The padding alone would give the
-// second pattern 2-way conflicts; a chunk swizzle would cost an address
-// register per column block.  With b a compile-time offset of both reads,
-// every address is one per-lane base plus an immediate.
+// LDS rows of D BF16 values are padded to D + 16 (a stride of 2 mod 16 in
+// 16-byte bank groups; 64 banks of 4 bytes) and, inside each group of 16
+// rows, row r is stored at r with its bits 2 and 3 exchanged.  The three
+// accesses to the tile are then free of bank conflicts, given the lane groups
+// the LDS serves together (measured on gfx950 with the bank-conflict
+// counter): ds_write_b128 serves 8 consecutive lanes, each storing 16
+// contiguous bytes of one row here; ds_read_b128 serves the 16 lanes that
+// share lane bit 5 and the parity of bits 2..4, which for the MFMA row
+// operand (lane (g, j): row j, chunk g) meet 16 distinct bank groups; the
+// 8-byte transpose read serves a half-wave, rows c..c+3 and c+8..c+11 with
+// 32 bytes each, again 16 distinct groups.  The earlier order (padding 8,
+// rows 8a + 4b + t at 8a + 2t + b) left the row operand two-way conflicted.
+// Both reads keep one per-lane base plus compile-time offsets: row 16 m + j
+// (j < 16) is at 16 m + lds_row(j), and row 32 k + 8 g + 4 q + i (g, i < 4)
+// at 32 k + 8 q + lds_row(8 g + i).
 __device__ __forceinline__ int lds_row(int r) {
-  return (r & ~7) | ((r & 3) << 1) | ((r >> 2) & 1);
+  return (r & ~12) | ((r & 4) << 1) | ((r >> 1) & 4);
 }
+// element offset of position p (a permuted row), column d
+template <int D>
+__device__ __forceinline__ int lds_pos(int p, int d) {
+  return p * (D + 16) + d;
+}
+// element offset of row r, column d
 template <int D>
 __device__ __forceinline__ int lds_at(int r, int d) {
-  return lds_row(r) * (D + 8) + d;
+  return lds_pos<D>(lds_row(r), d);
 }
 
 // rows layout Ys[r][d] (row order and stride as above)
@@ -243,7 +253,7 @@ __device__ __forceinline__ void tile_product(floatx4 (&acc)[4], const bf16x8 (&x
     bf16x8 b[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
-      b[jb] = *reinterpret_cast<const bf16x8*>(Ys + lds_at<KS * 32>(jb * 16 + r16, ks * 32 + g * 8));
+      b[jb] = *reinterpret_cast<const bf16x8*>(Ys + lds_pos<KS * 32>(jb * 16 + lds_row(r16), ks * 32 + g * 8));
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
       acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ks], b[jb], acc[jb], 0, 0, 0);
@@ -260,7 +270,7 @@ template <int KS, int EN>
 __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(FusedArgs a, int B, int cps) {
   constexpr bool L2 = EN != kEnDot;
   constexpr int D = KS * 32;
-  constexpr int LDY = D + 8;
+  constexpr int LDY = D + 16;
   constexpr int LDC = kFCols + 16;  // column-partial rows: 64 lanes over 32 banks, 2 per bank
   __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDY];
   // column (max, sum) of each (wave, 4-row group) for the current tile
@@ -469,7 +479,7 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
                                                           float log2b) {
   constexpr bool L2 = EN != kEnDot;
   constexpr int D = KS * 32;
-  constexpr int LDY = D + 8;
+  constexpr int LDY = D + 16;
   constexpr int LDG = 16;     // transposed G strip: [64 columns][16 rows]
   constexpr int NB = D / 16;  // 16-wide output blocks of dX
   // D >= 128: wave w owns columns [w D/4, (w+1) D/4) of dX for all 64 rows
@@ -629,9 +639,9 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
           v4s hq[2];
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+            const int jpos = kk * 32 + 8 * q + lds_row(8 * g + (r16 >> 2));
             const int dcol = (wave * NW + u) * 16 + 4 * (r16 & 3);
-            hq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_at<D>(jrow, dcol)));
+            hq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_pos<D>(jpos, dcol)));
           }
           v8s yv = {hq[0][0], hq[0][1], hq[0][2], hq[0][3], hq[1][0], hq[1][1], hq[1][2], hq[1][3]};
 #pragma unroll
@@ -666,9 +676,9 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
           for (int u = 0; u < NU; ++u)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-              const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+              const int jpos = kk * 32 + 8 * q + lds_row(8 * g + (r16 >> 2));
               const int dcol = (nb0 + u) * 16 + 4 * (r16 & 3);
-              hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_at<D>(jrow, dcol)));
+              hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_pos<D>(jpos, dcol)));
             }
 #pragma unroll
           for (int u = 0; u < NU; ++u) {
@@ -734,8 +744,8 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
                                                                float wf, float wb, float log2b) {
   constexpr bool L2 = EN != kEnDot;
   constexpr int D = 64, KS = 2, NB = 4;
-  constexpr int LDX = D + 8;           // phi / psi rows in LDS (144 B, lds_at order)
-  constexpr int LDGT = kBRows + 8;     // transposed G rows (one per column of the tile)
+  constexpr int LDX = D + 16;          // phi / psi rows in LDS (160 B, lds_at order)
+  constexpr int LDGT = kBRows + 16;    // transposed G rows (one per column of the tile, lds_row order)
   typedef short v4s __attribute__((ext_vector_type(4)));
   typedef short v8s __attribute__((ext_vector_type(8)));
   typedef __attribute__((address_space(3))) v4s lds_v4s;
@@ -846,7 +856,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
       uint2 w;
       w.x = pack2bf(h[0], h[1]);
       w.y = pack2bf(h[2], h[3]);
-      *reinterpret_cast<uint2*>(&Gt[(jb * 16 + r16) * LDGT + wave * 16 + 4 * g]) = w;
+      *reinterpret_cast<uint2*>(&Gt[(jb * 16 + lds_row(r16)) * LDGT + wave * 16 + 4 * g]) = w;
     }
     if (L2) {
 #pragma unroll
@@ -866,9 +876,9 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
       v4s gq[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+        const int kpos = kk * 32 + 8 * q + lds_row(8 * g + (r16 >> 2));
         gq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-            (lds_v4s*)(&Gt[krow * LDGT + wave * 16 + 4 * (r16 & 3)]));
+            (lds_v4s*)(&Gt[kpos * LDGT + wave * 16 + 4 * (r16 & 3)]));
       }
       v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
       const bf16x8 ga = __builtin_bit_cast(bf16x8, gv8);
@@ -881,9 +891,9 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
         for (int u = 0; u < NU; ++u)
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            const int jrow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+            const int jpos = kk * 32 + 8 * q + lds_row(8 * g + (r16 >> 2));
             const int dcol = (nb0 + u) * 16 + 4 * (r16 & 3);
-            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_at<D>(jrow, dcol)));
+            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_pos<D>(jpos, dcol)));
           }
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
@@ -905,13 +915,13 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
 #pragma unroll
       for (int kk = 0; kk < kBRows / 32; ++kk) {
         const bf16x8 av =
-            *reinterpret_cast<const bf16x8*>(&Gt[(cb16 * 16 + r16) * LDGT + kk * 32 + 8 * g]);
+            *reinterpret_cast<const bf16x8*>(&Gt[(cb16 * 16 + lds_row(r16)) * LDGT + kk * 32 + 8 * g]);
         v4s hb[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          const int krow = kk * 32 + 8 * g + 4 * q + (r16 >> 2);
+          const int kpos = kk * 32 + 8 * q + lds_row(8 * g + (r16 >> 2));
           hb[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-              (lds_v4s*)(Xs + lds_at<D>(krow, nb * 16 + 4 * (r16 & 3))));
+              (lds_v4s*)(Xs + lds_pos<D>(kpos, nb * 16 + 4 * (r16 & 3))));
         }
         v8s bv = {hb[0][0], hb[0][1], hb[0][2], hb[0][3], hb[1][0], hb[1][1], hb[1][2], hb[1][3]};
         acc_dy = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, bv),
