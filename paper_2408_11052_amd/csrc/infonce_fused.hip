@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
   constexpr bool L2 = EN != kEnDot;
   constexpr int D = KS * 32;
   constexpr int LDY = D + 16;
-  constexpr int LDC = kFCols + 16;  // column-partial rows: 64 lanes over 32 banks, 2 per bank
+  constexpr int LDC = kFCols + 16;  // column-partial rows
   __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDY];
   // column (max, sum) of each (wave, 4-row group) for the current tile
   __shared__ float cm_s[16][LDC], cs_s[16][LDC];
@@ -445,9 +445,12 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
 // columns of 16 BF16 rows (32 bytes each).  Inside each group of 16 columns,
 // column c8 + 8t (c8 < 8, t = 0 or 1) sits in 32-byte slot (c8 + 4t) mod 8 of
 // the group's t-th 256-byte half, its two 16-byte halves swapped when t = 1.
-// A half-wave's strip store (16 columns, 16 bytes each) and transpose read
-// (columns c..c+3 and c+8..c+11, 32 bytes each) then fall on 64 distinct
-// banks; with plain 32-byte rows both were two-way conflicts.
+// A half-wave's transpose read (columns c..c+3 and c+8..c+11, 32 bytes each)
+// then falls on 64 distinct banks, and a strip store (16 lanes at a time over
+// 32 banks, measured) is two-way conflicted; with plain 32-byte rows they
+// were two-way and four-way.  Permuting each column's four 8-byte chunks by
+// bits 2 and 3 of c as well makes the store conflict-free too, but measured
+// about 1% slower at D = 256, so the simpler form stays.
 __device__ __forceinline__ int gt_at(int c, int e) {
   const int t = (c >> 3) & 1;
   return (c & ~15) * 16 + t * 128 + (((c & 7) + 4 * t) & 7) * 16 + (e ^ (8 * t));
@@ -746,6 +749,11 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
   constexpr int D = 64, KS = 2, NB = 4;
   constexpr int LDX = D + 16;          // phi / psi rows in LDS (160 B, lds_at order)
   constexpr int LDGT = kBRows + 16;    // transposed G rows (one per column of the tile, lds_row order)
+  // for the product energy, columns with bit 3 set swap adjacent 16-byte
+  // chunks: the 8-byte G stores (16 lanes over 32 banks) are then two-way
+  // instead of four-way conflicted, with both reads of the tile still
+  // conflict-free (the distance energies have no registers to spare for it)
+  const int hsw = EN == kEnDot ? 8 * ((threadIdx.x >> 3) & 1) : 0;  // column r16 + 16 m
   typedef short v4s __attribute__((ext_vector_type(4)));
   typedef short v8s __attribute__((ext_vector_type(8)));
   typedef __attribute__((address_space(3))) v4s lds_v4s;
@@ -856,7 +864,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
       uint2 w;
       w.x = pack2bf(h[0], h[1]);
       w.y = pack2bf(h[2], h[3]);
-      *reinterpret_cast<uint2*>(&Gt[(jb * 16 + lds_row(r16)) * LDGT + wave * 16 + 4 * g]) = w;
+      *reinterpret_cast<uint2*>(&Gt[(jb * 16 + lds_row(r16)) * LDGT + ((wave * 16 + 4 * g) ^ hsw)]) = w;
     }
     if (L2) {
 #pragma unroll
@@ -878,7 +886,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
       for (int q = 0; q < 2; ++q) {
         const int kpos = kk * 32 + 8 * q + lds_row(8 * g + (r16 >> 2));
         gq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-            (lds_v4s*)(&Gt[kpos * LDGT + wave * 16 + 4 * (r16 & 3)]));
+            (lds_v4s*)(&Gt[kpos * LDGT + ((wave * 16 + 4 * (r16 & 3)) ^ (EN == kEnDot ? 8 * (g & 1) : 0))]));
       }
       v8s gv8 = {gq[0][0], gq[0][1], gq[0][2], gq[0][3], gq[1][0], gq[1][1], gq[1][2], gq[1][3]};
       const bf16x8 ga = __builtin_bit_cast(bf16x8, gv8);
@@ -915,7 +923,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
 #pragma unroll
       for (int kk = 0; kk < kBRows / 32; ++kk) {
         const bf16x8 av =
-            *reinterpret_cast<const bf16x8*>(&Gt[(cb16 * 16 + lds_row(r16)) * LDGT + kk * 32 + 8 * g]);
+            *reinterpret_cast<const bf16x8*>(&Gt[(cb16 * 16 + lds_row(r16)) * LDGT + ((kk * 32 + 8 * g) ^ hsw)]);
         v4s hb[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
