@@ -1082,6 +1082,53 @@ static int fused_fwd_splits(int B, int D, int en) {
   return (B + cps - 1) / cps;
 }
 
+// Resident workgroups of the rows pass of the two-pass backward (the columns
+// pass has the same resources).
+static int bwd_resident_wgs(int D, int en) {
+  const void* k = nullptr;
+#define CRL_BWD_PTR(KS_)                                                              \
+  k = en == kEnL2 ? reinterpret_cast<const void*>(&infonce_bwd_kernel<KS_, kEnL2, 0>)     \
+    : en == kEnL2sq ? reinterpret_cast<const void*>(&infonce_bwd_kernel<KS_, kEnL2sq, 0>) \
+                    : reinterpret_cast<const void*>(&infonce_bwd_kernel<KS_, kEnDot, 0>)
+  switch (D) {
+    case 32: CRL_BWD_PTR(1); break;
+    case 64: CRL_BWD_PTR(2); break;
+    case 128: CRL_BWD_PTR(4); break;
+    case 256: CRL_BWD_PTR(8); break;
+    default: return 0;
+  }
+#undef CRL_BWD_PTR
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+// Column splits of the two backward passes: each split writes a B x D
+// partial of dX that bwd_reduce_kernel reads back, so take the fewest splits
+// (at most fused_splits(B)) whose busiest workgroup slot carries no more
+// 64-column tiles than with fused_splits(B): rounds of resident workgroups
+// times tiles per workgroup (B=16384, D=256: 2 splits in one round of 512
+// workgroups against 4 in two rounds, half the partials).
+static int fused_bwd2_splits(int B, int D, int en) {
+  const int S = fused_splits(B);
+  const int nrb = (B + kFRows - 1) / kFRows;
+  const int cap = bwd_resident_wgs(D, en);
+  if (cap <= 0) return S;
+  auto load = [&](int s) {
+    const int64_t rounds = ((int64_t)nrb * s + cap - 1) / cap;
+    return rounds * (cols_per_split(B, s) / kFCols);
+  };
+  const int64_t target = load(S);
+  int best = S;
+  for (int s = S - 1; s >= 1; --s)
+    if (load(s) <= target) best = s;
+  const int cps = cols_per_split(B, best);
+  return (B + cps - 1) / cps;
+}
+
 #define CRL_EN_DISPATCH(EN_, BODY)                                  \
   switch (en) {                                                      \
     case kEnL2:   { constexpr int EN_ = kEnL2; BODY; } break;        \
@@ -1136,7 +1183,7 @@ hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int energy, int lo
   const int64_t n = (int64_t)B * D;
   const float l2b = (float)std::log2((double)B);
   const bool one = fused_bwd_one_pass(B, D);
-  int S = fused_splits(B);
+  int S = one ? 0 : fused_bwd2_splits(B, D, en);
   if (one) {  // one pass for both gradients
     S = fused_bwd_splits(B);
     const dim3 grid(S, S);
