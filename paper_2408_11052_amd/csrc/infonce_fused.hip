@@ -232,6 +232,14 @@ __device__ __forceinline__ float energy_fw(float v, float nx, float ny, float& w
   w = 1.f;
   return v;
 }
+// The maxima of the online log-sum-exp: IEEE maximum, which returns NaN if
+// either operand is NaN and needs no canonicalising of its operands (two
+// three-operand instructions for a row's four entries and its running max,
+// where fmaxf took seven).  A NaN entry makes its row's and column's LSE NaN
+// either way: with fmaxf it was skipped by the max but reached the sum.
+__device__ __forceinline__ float max_nan(float a, float b) {
+  return __builtin_elementwise_maximum(a, b);
+}
 __device__ __forceinline__ float exp_diff(float x, float m) {
   return __builtin_amdgcn_exp2f((x - m) * kL2E);
 }
@@ -315,9 +323,9 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
     float mv[4], sv[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) { mv[i] = cm_s[4 * g + i][cl]; sv[i] = cs_s[4 * g + i][cl]; }
-    float cm = fmaxf(__builtin_fmaxf(mv[0], mv[1]), __builtin_fmaxf(mv[2], mv[3]));
-    cm = fmaxf(cm, __shfl_xor(cm, 16, 64));
-    cm = fmaxf(cm, __shfl_xor(cm, 32, 64));
+    float cm = max_nan(max_nan(mv[0], mv[1]), max_nan(mv[2], mv[3]));
+    cm = max_nan(cm, __shfl_xor(cm, 16, 64));
+    cm = max_nan(cm, __shfl_xor(cm, 32, 64));
     float cs = 0.f;
 #pragma unroll
     for (int i = 0; i < 4; ++i) cs += sv[i] == 0.f ? 0.f : sv[i] * exp_diff(mv[i], cm);
@@ -387,8 +395,7 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
     // rows: online (max, sum)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const float ml = fmaxf(__builtin_fmaxf(f[0][r], f[1][r]), __builtin_fmaxf(f[2][r], f[3][r]));
-      const float nm = fmaxf(rm[r], ml);
+      const float nm = max_nan(rm[r], max_nan(max_nan(f[0][r], f[1][r]), max_nan(f[2][r], f[3][r])));
       float sr = rsum[r] * exp_diff(rm[r], nm);
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb) sr += exp_diff(f[jb][r], nm);
@@ -400,7 +407,7 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
     // group); the merge runs after the next barrier
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
-      const float cm = fmaxf(__builtin_fmaxf(f[jb][0], f[jb][1]), __builtin_fmaxf(f[jb][2], f[jb][3]));
+      const float cm = max_nan(max_nan(f[jb][0], f[jb][1]), max_nan(f[jb][2], f[jb][3]));
       float cs = 0.f;
 #pragma unroll
       for (int r = 0; r < 4; ++r) cs += exp_diff(f[jb][r], cm);
@@ -422,7 +429,7 @@ __global__ __launch_bounds__(256, fwd_waves<KS>()) void infonce_fwd_kernel(Fused
 #pragma unroll
   for (int o = 1; o <= 8; o <<= 1)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) mrow[r] = fmaxf(mrow[r], __shfl_xor(mrow[r], o, 64));
+    for (int r = 0; r < 4; ++r) mrow[r] = max_nan(mrow[r], __shfl_xor(mrow[r], o, 64));
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     srow[r] = rsum[r] == 0.f ? 0.f : rsum[r] * exp_diff(rm[r], mrow[r]);
