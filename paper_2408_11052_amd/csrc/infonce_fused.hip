@@ -498,7 +498,8 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
   typedef short v4s __attribute__((ext_vector_type(4)));
   typedef short v8s __attribute__((ext_vector_type(8)));
   typedef __attribute__((address_space(3))) v4s lds_v4s;
-  __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDY];
+  // two tile buffers: the next tile is stored while this one is in use
+  __shared__ __attribute__((aligned(16))) bf16_t Ys[2][kFCols * LDY];
   __shared__ __attribute__((aligned(16))) bf16_t Gt[4][kFCols * LDG];
 
   const bf16_t* Xb = TRANS ? a.psi_b : a.phi_b;
@@ -570,19 +571,30 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
     }
   };
 
+  // tile j0 sits in Ys[buf]; pf holds tile j0 + 64 (stored into the other
+  // buffer at the top of the iteration) and cpf its column values
   const int jlast = c0 + ((c1 - c0 - 1) / kFCols) * kFCols;
   TileRegs<D> pf;
-  ColVals cpf;
-  if (c0 < c1) { tile_load<D>(pf, Yb, c0, B, tid); col_load(cpf, c0); }
-  for (int j0 = c0; j0 < c1; j0 += kFCols) {
+  ColVals cvals, cpf;
+  if (c0 < c1) {
+    tile_load<D>(pf, Yb, c0, B, tid);
+    col_load(cvals, c0);
+    tile_store_rows<D, LDY>(Ys[0], pf, tid);
+    tile_load<D>(pf, Yb, min(c0 + kFCols, jlast), B, tid);
+    col_load(cpf, min(c0 + kFCols, jlast));
+  }
+  int buf = 0;
+  for (int j0 = c0; j0 < c1; j0 += kFCols, buf ^= 1) {
+    // Ys[buf] is complete, and every wave is past the previous tile's reads
+    // of Ys[buf ^ 1] and of the G strips
     __syncthreads();
-    tile_store_rows<D, LDY>(Ys, pf, tid);
-    const ColVals cvals = cpf;
-    tile_load<D>(pf, Yb, min(j0 + kFCols, jlast), B, tid);
-    col_load(cpf, min(j0 + kFCols, jlast));
-    __syncthreads();
+    if (j0 + kFCols < c1) {
+      tile_store_rows<D, LDY>(Ys[buf ^ 1], pf, tid);
+      tile_load<D>(pf, Yb, min(j0 + 2 * kFCols, jlast), B, tid);
+    }
+    const bf16_t* __restrict__ Yt = Ys[buf];
     floatx4 acc[4];
-    tile_product<KS>(acc, xa, Ys, r16, g);
+    tile_product<KS>(acc, xa, Yt, r16, g);
     float sh_b[4], k_b[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
@@ -651,7 +663,7 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
           for (int q = 0; q < 2; ++q) {
             const int jpos = kk * 32 + 8 * q + lds_row(8 * g + (r16 >> 2));
             const int dcol = (wave * NW + u) * 16 + 4 * (r16 & 3);
-            hq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_pos<D>(jpos, dcol)));
+            hq[q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Yt + lds_pos<D>(jpos, dcol)));
           }
           v8s yv = {hq[0][0], hq[0][1], hq[0][2], hq[0][3], hq[1][0], hq[1][1], hq[1][2], hq[1][3]};
 #pragma unroll
@@ -688,7 +700,7 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
             for (int q = 0; q < 2; ++q) {
               const int jpos = kk * 32 + 8 * q + lds_row(8 * g + (r16 >> 2));
               const int dcol = (nb0 + u) * 16 + 4 * (r16 & 3);
-              hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_pos<D>(jpos, dcol)));
+              hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Yt + lds_pos<D>(jpos, dcol)));
             }
 #pragma unroll
           for (int u = 0; u < NU; ++u) {
@@ -700,6 +712,8 @@ __global__ __launch_bounds__(256, bwd_waves<KS>()) void infonce_bwd_kernel(Fused
         }
       }
     }
+    cvals = cpf;
+    col_load(cpf, min(j0 + 2 * kFCols, jlast));
   }
   // write this split's partials (the two passes use separate halves)
   float* dst = a.dX_part + ((int64_t)TRANS * gridDim.y + blockIdx.y) * B * D;
