@@ -779,7 +779,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
   typedef short v8s __attribute__((ext_vector_type(8)));
   typedef __attribute__((address_space(3))) v4s lds_v4s;
   __shared__ __attribute__((aligned(16))) bf16_t Xs[kBRows * LDX];
-  __shared__ __attribute__((aligned(16))) bf16_t Ys[kFCols * LDX];
+  __shared__ __attribute__((aligned(16))) bf16_t Ys[2][kFCols * LDX];  // this tile and the next
   __shared__ __attribute__((aligned(16))) bf16_t Gt[kFCols * LDGT];
   __shared__ float csum[16][kFCols];
 
@@ -834,12 +834,21 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
     return val;
   };
   const int ntiles = min(kBRows, B - cb0 + kFCols - 1) / kFCols;
+  // tile t sits in Ys[t & 1]; ypf holds tile t + 1, stored into the other
+  // buffer at the top of iteration t
   u32x4 ypf = y_load(cb0);
+  if (tid < 512) *reinterpret_cast<u32x4*>(Ys[0] + lds_at<D>(tid >> 3, (tid & 7) * 8)) = ypf;
+  if (ntiles > 1) ypf = y_load(cb0 + kFCols);
   for (int t = 0; t < ntiles; ++t) {
     const int j0 = cb0 + t * kFCols;
-    __syncthreads();  // previous tile's Ys and Gt reads are done (and Xs is written)
-    if (tid < 512) *reinterpret_cast<u32x4*>(Ys + lds_at<D>(tid >> 3, (tid & 7) * 8)) = ypf;
-    if (t + 1 < ntiles) ypf = y_load(j0 + kFCols);
+    // Ys[t & 1] and Xs are written; the previous tile's reads of Ys[(t + 1) & 1]
+    // and of the G tile are done
+    __syncthreads();
+    if (t + 1 < ntiles) {
+      if (tid < 512) *reinterpret_cast<u32x4*>(Ys[(t + 1) & 1] + lds_at<D>(tid >> 3, (tid & 7) * 8)) = ypf;
+      if (t + 2 < ntiles) ypf = y_load(j0 + 2 * kFCols);
+    }
+    const bf16_t* __restrict__ Yt = Ys[t & 1];
     float sh_c[4], ny[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
@@ -848,9 +857,8 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
       sh_c[jb] = (wb != 0.f && cv) ? __builtin_fmaf(a.c[col], kL2E, log2b) : INFINITY;
       ny[jb] = (L2 && cv) ? a.npsi[col] : 0.f;
     }
-    __syncthreads();
     floatx4 acc[4];
-    tile_product<KS>(acc, xa, Ys, r16, g);
+    tile_product<KS>(acc, xa, Yt, r16, g);
     // G (or H = G / d) of the wave's 16 rows, one 16-column block at a time;
     // row and column sums of H for L2
     const bool edge = !rows_full || j0 + kFCols > B;
@@ -922,7 +930,7 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
           for (int q = 0; q < 2; ++q) {
             const int jpos = kk * 32 + 8 * q + lds_row(8 * g + (r16 >> 2));
             const int dcol = (nb0 + u) * 16 + 4 * (r16 & 3);
-            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Ys + lds_pos<D>(jpos, dcol)));
+            hq[u][q] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(Yt + lds_pos<D>(jpos, dcol)));
           }
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
