@@ -370,6 +370,31 @@ CRL_API int crl_actor_step(crl_ctx* ctx, const float* params,
                            const int64_t* step, void* ws, float* actor_grads,
                            float* alpha_grad, float* loss_out, void* stream);
 
+/* The policy's gradient step in one call (Algorithm 1, the policy update):
+ * crl_actor_step with each element of the policy gradient fed to the Adam
+ * step of crl_adam_step as it is formed (the gradient vector is not read
+ * back).
+ *   actor_params, actor_params_bf16   updated in place (the BF16 copy may be
+ *                 NULL for FP32)
+ *   actor_grads   device FP32 [crl_actor_param_count] out, or NULL: then the
+ *                 gradient is not kept
+ *   actor_m, actor_v, adam_step, lr, b1, b2, eps   as for crl_adam_step, over
+ *                 the whole policy vector (adam_step is the Adam step count t,
+ *                 step the batch counter n of the noise draw)
+ * Other arguments as for crl_actor_step.  actor_params, actor_m, actor_v and
+ * the BF16 copy come out bit-identical to crl_actor_step followed by
+ * crl_adam_step on the policy vector; alpha_grad is written as there (the
+ * temperature's one-element Adam step stays with crl_adam_step). */
+CRL_API int crl_actor_step_adam(crl_ctx* ctx, const float* params,
+                                const uint16_t* params_bf16, float* actor_params,
+                                uint16_t* actor_params_bf16,
+                                const float* log_alpha, const void* x_sa,
+                                const void* x_g, const void* x_sg, uint64_t seed,
+                                const int64_t* step, void* ws, float* actor_grads,
+                                float* alpha_grad, float* loss_out, float* actor_m,
+                                float* actor_v, const int64_t* adam_step, double lr,
+                                double b1, double b2, double eps, void* stream);
+
 /* Step 4: Adam (Kingma & Ba) on n floats, the optimiser read into the
  * gradient steps of Algorithm 1:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;

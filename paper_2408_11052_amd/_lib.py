@@ -67,6 +67,8 @@ SIGNATURES = {
     "crl_infonce_fwd_noalloc": (C.c_int, [P, P, P, P, P, P, P, P]),
     "crl_check_finite": (C.c_int, [P, P]),
     "crl_actor_step": (C.c_int, [P, P, P, P, P, P, P, P, P, U64, P, P, P, P, P, P]),
+    "crl_actor_step_adam": (C.c_int, [P, P, P, P, P, P, P, P, P, U64, P, P, P, P, P, P, P, P,
+                                      C.c_double, C.c_double, C.c_double, C.c_double, P]),
     "crl_adam_step": (C.c_int, [P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_double,
                                 C.c_double, P]),
     "crl_counter_add": (C.c_int, [P, I64, P]),

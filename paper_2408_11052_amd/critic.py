@@ -247,6 +247,21 @@ class Critic:
                                    _ptr(step), _ptr(ws), _ptr(actor_grads), _ptr(alpha_grad),
                                    _ptr(loss_out), _stream(stream)))
 
+    def crl_actor_step_adam(self, params, params_bf16, actor_params, actor_params_bf16,
+                            log_alpha, x_sa, x_g, x_sg, seed: int, step, ws, actor_grads,
+                            alpha_grad, loss_out, actor_m, actor_v, adam_step, lr: float,
+                            b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, stream=None):
+        """crl_actor_step with the policy gradient fed straight into its Adam
+        step (actor_params, actor_params_bf16, actor_m, actor_v updated in
+        place; actor_grads may be None)."""
+        check(lib().crl_actor_step_adam(self.ctx, _ptr(params), _ptr(params_bf16),
+                                        _ptr(actor_params), _ptr(actor_params_bf16),
+                                        _ptr(log_alpha), _ptr(x_sa), _ptr(x_g), _ptr(x_sg), seed,
+                                        _ptr(step), _ptr(ws), _ptr(actor_grads),
+                                        _ptr(alpha_grad), _ptr(loss_out), _ptr(actor_m),
+                                        _ptr(actor_v), _ptr(adam_step), lr, b1, b2, eps,
+                                        _stream(stream)))
+
 
 def crl_replay_insert(obs, act, traj, new_obs, new_act, new_traj, count, stream=None):
     """Append new_* ([U][E][...], time-major) to the ring obs/act/traj ([E][C][...])."""

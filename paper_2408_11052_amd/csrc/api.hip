@@ -1398,26 +1398,15 @@ CRL_API int crl_check_finite(const float* loss_out, void* stream) {
   return CRL_OK;
 }
 
-CRL_API int crl_actor_step(crl_ctx* x, const float* params, const uint16_t* params_bf16,
-                           const float* actor_params, const uint16_t* actor_params_bf16,
-                           const float* log_alpha, const void* x_sa, const void* x_g,
-                           const void* x_sg, uint64_t seed, const int64_t* step, void* ws,
-                           float* actor_grads, float* alpha_grad, float* loss_out,
-                           void* stream) {
-  if (!x) return fail(CRL_EINVAL, "NULL context");
-  if (!x->actor) return fail(CRL_EINVAL, "this context has no actor (actor_n_hidden = 0)");
-  if (!params || !actor_params || !log_alpha || !x_sa || !x_g || !x_sg || !step || !ws ||
-      !actor_grads || !alpha_grad || !loss_out)
-    return fail(CRL_EINVAL, "NULL buffer argument");
-  if (x->bf16 && (!params_bf16 || !actor_params_bf16))
-    return fail(CRL_EINVAL, "BF16 precision needs params_bf16 and actor_params_bf16");
-  if (!aligned16(params) || !aligned16(actor_params) || !aligned16(x_sa) || !aligned16(x_g) ||
-      !aligned16(x_sg) || !aligned16(ws) || !aligned16(actor_grads) ||
-      (params_bf16 && !aligned16(params_bf16)) ||
-      (actor_params_bf16 && !aligned16(actor_params_bf16)))
-    return fail(CRL_EINVAL, "buffers must be 16-byte aligned");
-  CRL_TRY(check_device(x));
-  hipStream_t s = (hipStream_t)stream;
+// The policy step (both entry points): the arguments are checked by the
+// caller; adam, if not NULL, takes the policy gradient into its Adam step as
+// the gradient is reduced.
+static int actor_step(crl_ctx* x, const float* params, const uint16_t* params_bf16,
+                      const float* actor_params, const uint16_t* actor_params_bf16,
+                      const float* log_alpha, const void* x_sa, const void* x_g,
+                      const void* x_sg, uint64_t seed, const int64_t* step, void* ws,
+                      float* actor_grads, float* alpha_grad, float* loss_out,
+                      const AdamArgs* adam, hipStream_t s) {
   const int B = x->B;
   const bf16_t* pb = reinterpret_cast<const bf16_t*>(params_bf16);
   const bf16_t* apb = reinterpret_cast<const bf16_t*>(actor_params_bf16);
@@ -1453,10 +1442,69 @@ CRL_API int crl_actor_step(crl_ctx* x, const float* params, const uint16_t* para
   CRL_HIP(launch_actor_head_bwd(pout, x->P, x->A, eps, dact, x->ldd, log_alpha,
                                 WF(ws, x->sl[2].dout), W(ws, x->sl[2].dout_t), B, x->bf16, s),
           "policy head backward");
-  CRL_TRY(mlp_backward(x, &pol, 1, ws, s));
+  CRL_TRY(mlp_backward(x, &pol, 1, ws, s, false, adam));
   CRL_HIP(launch_actor_loss(logpi, fpol, B, log_alpha, x->cfg.target_entropy, loss_out,
                             alpha_grad, s), "actor loss");
   return CRL_OK;
+}
+
+CRL_API int crl_actor_step(crl_ctx* x, const float* params, const uint16_t* params_bf16,
+                           const float* actor_params, const uint16_t* actor_params_bf16,
+                           const float* log_alpha, const void* x_sa, const void* x_g,
+                           const void* x_sg, uint64_t seed, const int64_t* step, void* ws,
+                           float* actor_grads, float* alpha_grad, float* loss_out,
+                           void* stream) {
+  if (!x) return fail(CRL_EINVAL, "NULL context");
+  if (!x->actor) return fail(CRL_EINVAL, "this context has no actor (actor_n_hidden = 0)");
+  if (!params || !actor_params || !log_alpha || !x_sa || !x_g || !x_sg || !step || !ws ||
+      !actor_grads || !alpha_grad || !loss_out)
+    return fail(CRL_EINVAL, "NULL buffer argument");
+  if (x->bf16 && (!params_bf16 || !actor_params_bf16))
+    return fail(CRL_EINVAL, "BF16 precision needs params_bf16 and actor_params_bf16");
+  if (!aligned16(params) || !aligned16(actor_params) || !aligned16(x_sa) || !aligned16(x_g) ||
+      !aligned16(x_sg) || !aligned16(ws) || !aligned16(actor_grads) ||
+      (params_bf16 && !aligned16(params_bf16)) ||
+      (actor_params_bf16 && !aligned16(actor_params_bf16)))
+    return fail(CRL_EINVAL, "buffers must be 16-byte aligned");
+  CRL_TRY(check_device(x));
+  return actor_step(x, params, params_bf16, actor_params, actor_params_bf16, log_alpha, x_sa, x_g,
+                    x_sg, seed, step, ws, actor_grads, alpha_grad, loss_out, nullptr,
+                    (hipStream_t)stream);
+}
+
+CRL_API int crl_actor_step_adam(crl_ctx* x, const float* params, const uint16_t* params_bf16,
+                                float* actor_params, uint16_t* actor_params_bf16,
+                                const float* log_alpha, const void* x_sa, const void* x_g,
+                                const void* x_sg, uint64_t seed, const int64_t* step, void* ws,
+                                float* actor_grads, float* alpha_grad, float* loss_out,
+                                float* actor_m, float* actor_v, const int64_t* adam_step,
+                                double lr, double b1, double b2, double eps, void* stream) {
+  if (!x) return fail(CRL_EINVAL, "NULL context");
+  if (!x->actor) return fail(CRL_EINVAL, "this context has no actor (actor_n_hidden = 0)");
+  if (!params || !actor_params || !log_alpha || !x_sa || !x_g || !x_sg || !step || !ws ||
+      !alpha_grad || !loss_out || !actor_m || !actor_v || !adam_step)
+    return fail(CRL_EINVAL, "NULL buffer argument");
+  if (x->bf16 && (!params_bf16 || !actor_params_bf16))
+    return fail(CRL_EINVAL, "BF16 precision needs params_bf16 and actor_params_bf16");
+  if (!aligned16(params) || !aligned16(actor_params) || !aligned16(x_sa) || !aligned16(x_g) ||
+      !aligned16(x_sg) || !aligned16(ws) || (actor_grads && !aligned16(actor_grads)) ||
+      !aligned16(actor_m) || !aligned16(actor_v) ||
+      (params_bf16 && !aligned16(params_bf16)) ||
+      (actor_params_bf16 && !aligned16(actor_params_bf16)))
+    return fail(CRL_EINVAL, "buffers must be 16-byte aligned");
+  if (!(b1 > 0.0 && b1 < 1.0 && b2 > 0.0 && b2 < 1.0 && eps >= 0.0 && std::isfinite(lr)))
+    return fail(CRL_EINVAL, "Adam hyperparameters out of range");
+  CRL_TRY(check_device(x));
+  AdamArgs A{};
+  A.p = actor_params;
+  A.m = actor_m;
+  A.v = actor_v;
+  A.pb = reinterpret_cast<bf16_t*>(actor_params_bf16);
+  A.step = adam_step;
+  A.c = adam_coef(lr, b1, b2, eps);
+  return actor_step(x, params, params_bf16, actor_params, actor_params_bf16, log_alpha, x_sa, x_g,
+                    x_sg, seed, step, ws, actor_grads, alpha_grad, loss_out, &A,
+                    (hipStream_t)stream);
 }
 
 CRL_API int crl_adam_step(float* p, const float* g, float* m, float* v, uint16_t* p_bf16,

@@ -123,7 +123,9 @@ class CriticUpdate:
 
 
 class FullUpdate(CriticUpdate):
-    """Critic update, then the policy and entropy-coefficient steps.
+    """Critic update, then the policy and entropy-coefficient steps (the
+    policy's Adam step taken inside its gradient reduction; with keep_grads
+    the policy gradient is stored in self.agrads as well).
 
     log alpha and its Adam moments are 4-float vectors so that they meet the
     16-byte alignment of crl_adam_step; only element 0 is used (the others
@@ -162,11 +164,10 @@ class FullUpdate(CriticUpdate):
         self._critic_fwd(self.x_sg)
         crl_counter_add(self.t, 1)
         self._critic_step()
-        c.crl_actor_step(self.params, self.pbf, self.aparams, self.apbf, self.log_alpha,
-                         self.x_sa, self.x_g, self.x_sg, self.seed, self.n, self.ws,
-                         self.agrads, self.alpha_grad, self.actor_loss)
-        crl_adam_step(self.aparams, self.agrads, self.am, self.av, self.apbf, self.t,
-                      self.policy_lr)
+        c.crl_actor_step_adam(self.params, self.pbf, self.aparams, self.apbf, self.log_alpha,
+                              self.x_sa, self.x_g, self.x_sg, self.seed, self.n, self.ws,
+                              self.agrads if self.keep_grads else None, self.alpha_grad,
+                              self.actor_loss, self.am, self.av, self.t, self.policy_lr)
         crl_adam_step(self.log_alpha, self.alpha_grad, self.m_alpha, self.v_alpha, None,
                       self.t, self.alpha_lr)
         crl_counter_add(self.n, 1)

@@ -22,7 +22,7 @@ def _declared():
 def test_header_declares_the_hot_path_calls():
     names = _declared()
     for n in ("crl_sample_relabel", "crl_critic_fwd", "crl_critic_bwd", "crl_adam_step",
-              "crl_critic_bwd_adam", "crl_actor_step"):
+              "crl_critic_bwd_adam", "crl_actor_step", "crl_actor_step_adam"):
         assert n in names
 
 
@@ -175,6 +175,9 @@ def test_null_arguments_rejected_without_device():
     assert L.crl_check_finite(None, None) == _lib.CRL_EINVAL
     assert L.crl_critic_bwd_adam(None, None, None, None, None, None, None, None, None, None,
                                  1e-3, 0.9, 0.999, 1e-8, None) == _lib.CRL_EINVAL
+    assert L.crl_actor_step_adam(None, None, None, None, None, None, None, None, None, 0, None,
+                                 None, None, None, None, None, None, None, 1e-3, 0.9, 0.999,
+                                 1e-8, None) == _lib.CRL_EINVAL
     n = C.c_int32()
     assert L.crl_timing_count(C.byref(n)) == _lib.CRL_OK
 

@@ -272,6 +272,78 @@ def test_full_update_steps_b4096_bf16():
     gu.close()
 
 
+ADAM_CASES = {
+    "fp32": SMALL,
+    "bf16_unsplit": CASES["bf16_dot_ln"],
+    # B = 2048: the policy's dW launches are split along the batch, so their
+    # partials are reduced by the fused Adam reduction
+    "bf16_split": CASES["bf16_dot_ln"].with_(name="actor_adam_split", batch_size=2048,
+                                             num_envs=64, episode_len=64),
+    "bf16_wide_action_random_goals": CASES["bf16_dot_ln_wide_action"].with_(
+        name="actor_adam_wide", random_goal_ratio=0.3),
+}
+
+
+@pytest.mark.parametrize("case", list(ADAM_CASES))
+def test_actor_step_adam_equals_step_then_adam(case):
+    """crl_actor_step_adam against crl_actor_step followed by crl_adam_step on
+    the policy vector, on the same batches: policy parameters, BF16 copy, m
+    and v bit for bit over three steps; the policy gradient (when kept), dlog
+    alpha and the loss terms equal as values."""
+    from paper_2408_11052_amd import Critic, crl_adam_step, crl_cast_bf16
+    w = ADAM_CASES[case]
+    obs, act, phi, psi = setup(w, perturb=0.1)
+    actor = _actor_layers(w)
+    log(f"[actor_adam] {case}: B={w.batch_size} hidden={w.actor_hidden} prec={w.precision}")
+    crit = Critic(w, max_episode_len=obs.shape[1])
+    params = torch.from_numpy(crit.pack(phi, psi)).to(DEV)
+    pbf = None
+    if w.precision == "bf16":
+        pbf = torch.empty(crit.nparam, dtype=torch.bfloat16, device=DEV)
+        crl_cast_bf16(params, pbf)
+    packed = torch.from_numpy(crit.pack_actor(actor)).to(DEV)
+
+    def state():
+        s = {"p": packed.clone(), "pb": None, "m": torch.zeros_like(packed),
+             "v": torch.zeros_like(packed), "g": torch.full_like(packed, float("nan")),
+             "ag": torch.zeros(4, device=DEV), "loss": torch.zeros(4, device=DEV)}
+        if w.precision == "bf16":
+            s["pb"] = torch.empty(crit.nparam_actor, dtype=torch.bfloat16, device=DEV)
+            crl_cast_bf16(s["p"], s["pb"])
+        return s
+
+    a, b = state(), state()
+    x_sa, x_g, x_sg = crit.inputs(DEV)
+    ws = crit.workspace(DEV)
+    idx = torch.zeros(w.batch_size, 3, dtype=torch.int32, device=DEV)
+    la = torch.tensor([0.3, 0, 0, 0], dtype=torch.float32, device=DEV)
+    d_obs, d_act = torch.from_numpy(obs).to(DEV), torch.from_numpy(act).to(DEV)
+    t = torch.zeros(1, dtype=torch.int64, device=DEV)
+    lr = 6e-4
+    bits = lambda x: x.view(torch.int32) if x.dtype == torch.float32 else x.view(torch.int16)
+    for step in range(3):
+        n = torch.tensor([step], dtype=torch.int64, device=DEV)
+        t.fill_(step + 1)
+        keep = step != 1
+        crit.crl_sample_relabel(d_obs, d_act, SEED_PHILOX, n, idx, x_sa, x_g, x_sg)
+        crit.crl_actor_step(params, pbf, a["p"], a["pb"], la, x_sa, x_g, x_sg, SEED_PHILOX, n,
+                            ws, a["g"], a["ag"], a["loss"])
+        crl_adam_step(a["p"], a["g"], a["m"], a["v"], a["pb"], t, lr)
+        crit.crl_sample_relabel(d_obs, d_act, SEED_PHILOX, n, idx, x_sa, x_g, x_sg)
+        crit.crl_actor_step_adam(params, pbf, b["p"], b["pb"], la, x_sa, x_g, x_sg, SEED_PHILOX,
+                                 n, ws, b["g"] if keep else None, b["ag"], b["loss"], b["m"],
+                                 b["v"], t, lr)
+        torch.cuda.synchronize()
+        if keep:
+            assert torch.equal(a["g"], b["g"]), step
+        assert torch.equal(a["ag"], b["ag"]) and torch.equal(a["loss"], b["loss"]), step
+        for k in ("p", "m", "v", "pb"):
+            if a[k] is not None:
+                assert torch.equal(bits(a[k]), bits(b[k])), (step, k)
+    assert float(a["m"].abs().max()) > 0.0
+    crit.close()
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp32"])
 def test_full_update_graph_replay_equals_eager(prec):
     from paper_2408_11052_amd.update import FullUpdate
