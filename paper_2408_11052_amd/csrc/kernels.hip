@@ -188,7 +188,8 @@ hipError_t launch_ln_swish_fwd(const LnArgs& a, int count, int B, int N, float e
 }
 
 // Backward of h = Swish(g * zhat + b), zhat = (z - mu) * rstd.  Each
-// workgroup owns kLnRows rows (kLnRows / 4 per wavefront, one row at a time):
+// workgroup owns `rows` rows (a multiple of kLnRows, taken kLnRows at a time,
+// kLnRows / 4 per wavefront, one row at a time):
 //   dy = dh * Swish'(y), dzhat = g * dy,
 //   dz = rstd * (dzhat - mean(dzhat) - zhat * mean(dzhat * zhat)),
 // and it accumulates the column sums dg = sum dy*zhat, db_ln = sum dy,
@@ -197,7 +198,7 @@ hipError_t launch_ln_swish_fwd(const LnArgs& a, int count, int B, int N, float e
 constexpr int kLnRows = 16;
 
 template <typename T, int CH>
-__global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int N) {
+__global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int N, int rows) {
   extern __shared__ float red[];  // [4 waves][3][N]
   constexpr int R = kLnRows / 4;  // rows per wavefront
   const int e = blockIdx.y;
@@ -206,27 +207,6 @@ __global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int 
   const T* Zb = reinterpret_cast<const T*>(a.Z[e]);
   const T* dHb = reinterpret_cast<const T*>(a.dH[e]);
   T* dZb = reinterpret_cast<T*>(a.dZ[e]);
-  const int r0 = blockIdx.x * kLnRows + wave * R;
-  const int nr = max(0, min(R, B - r0));
-  // all rows of this wavefront are requested before any is used
-  RawChunk<T> zr[R][CH], hr[R][CH];
-  float mu[R], rs[R];
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    mu[j] = rs[j] = 0.f;
-    if (j < nr) {
-      mu[j] = a.mu[e][r0 + j];
-      rs[j] = a.rstd[e][r0 + j];
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int ch = lane + 64 * c;
-        if (ch < nch) {
-          zr[j][c].load(Zb + (int64_t)(r0 + j) * N + ch * 8);
-          hr[j][c].load(dHb + (int64_t)(r0 + j) * N + ch * 8);
-        }
-      }
-    }
-  }
   float gv[CH][8], bv[CH][8], cg[CH][8], cb[CH][8], cz[CH][8];
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
@@ -236,52 +216,78 @@ __global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int 
     if (ch < nch) { load8(a.g[e] + ch * 8, gv[c]); load8(a.b[e] + ch * 8, bv[c]); }
   }
   const float inv_n = 1.f / (float)N;
+  // rounds of kLnRows rows (R per wavefront) over the workgroup's rows; the
+  // column sums run on across the rounds
+  const int wg_end = min(B, (blockIdx.x + 1) * rows);
+  for (int base = blockIdx.x * rows; base < wg_end; base += kLnRows) {
+    const int r0 = base + wave * R;
+    const int nr = max(0, min(R, B - r0));
+    // all rows of this wavefront are requested before any is used
+    RawChunk<T> zr[R][CH], hr[R][CH];
+    float mu[R], rs[R];
 #pragma unroll
-  for (int j = 0; j < R; ++j) {
-    if (j >= nr) break;  // uniform over the wavefront, as the row sums need
-    const int row = r0 + j;
-    float zh[CH][8], dzh[CH][8];
-    float s1 = 0.f, s2 = 0.f;
+    for (int j = 0; j < R; ++j) {
+      mu[j] = rs[j] = 0.f;
+      if (j < nr) {
+        mu[j] = a.mu[e][r0 + j];
+        rs[j] = a.rstd[e][r0 + j];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int ch = lane + 64 * c;
-      if (ch < nch) {
-        float z[8], dh[8];
-        zr[j][c].get(z);
-        hr[j][c].get(dh);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const float xh = (z[i] - mu[j]) * rs[j];
-          const float y = __builtin_fmaf(gv[c][i], xh, bv[c][i]);
-          const float sg = sigmoidf_(y);
-          // Swish'(y) = sg (1 + y (1 - sg)) = sg + y sg (1 - sg)
-          const float q = __builtin_fmaf(-sg, sg, sg);
-          const float dy = dh[i] * __builtin_fmaf(y, q, sg);
-          cg[c][i] += dy * xh;
-          cb[c][i] += dy;
-          const float d = dy * gv[c][i];
-          zh[c][i] = xh;
-          dzh[c][i] = d;
-          s1 += d;
-          s2 += d * xh;
+        for (int c = 0; c < CH; ++c) {
+          const int ch = lane + 64 * c;
+          if (ch < nch) {
+            zr[j][c].load(Zb + (int64_t)(r0 + j) * N + ch * 8);
+            hr[j][c].load(dHb + (int64_t)(r0 + j) * N + ch * 8);
+          }
         }
       }
     }
-    // dz = rstd (dzhat - m1 - zhat m2) = rstd dzhat + (e zhat + k),
-    // e = -rstd m2, k = -rstd m1
-    const float k = -rs[j] * (wave_sum_full(s1) * inv_n);
-    const float e = -rs[j] * (wave_sum_full(s2) * inv_n);
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int ch = lane + 64 * c;
-      if (ch < nch) {
-        float o[8];
+    for (int j = 0; j < R; ++j) {
+      if (j >= nr) break;  // uniform over the wavefront, as the row sums need
+      const int row = r0 + j;
+      float zh[CH][8], dzh[CH][8];
+      float s1 = 0.f, s2 = 0.f;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          o[i] = __builtin_fmaf(rs[j], dzh[c][i], __builtin_fmaf(e, zh[c][i], k));
-          cz[c][i] += o[i];
+      for (int c = 0; c < CH; ++c) {
+        const int ch = lane + 64 * c;
+        if (ch < nch) {
+          float z[8], dh[8];
+          zr[j][c].get(z);
+          hr[j][c].get(dh);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const float xh = (z[i] - mu[j]) * rs[j];
+            const float y = __builtin_fmaf(gv[c][i], xh, bv[c][i]);
+            const float sg = sigmoidf_(y);
+            // Swish'(y) = sg (1 + y (1 - sg)) = sg + y sg (1 - sg)
+            const float q = __builtin_fmaf(-sg, sg, sg);
+            const float dy = dh[i] * __builtin_fmaf(y, q, sg);
+            cg[c][i] += dy * xh;
+            cb[c][i] += dy;
+            const float d = dy * gv[c][i];
+            zh[c][i] = xh;
+            dzh[c][i] = d;
+            s1 += d;
+            s2 += d * xh;
+          }
         }
-        store8(dZb + (int64_t)row * N + ch * 8, o);
+      }
+      // dz = rstd (dzhat - m1 - zhat m2) = rstd dzhat + (e zhat + k),
+      // e = -rstd m2, k = -rstd m1
+      const float k = -rs[j] * (wave_sum_full(s1) * inv_n);
+      const float e = -rs[j] * (wave_sum_full(s2) * inv_n);
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int ch = lane + 64 * c;
+        if (ch < nch) {
+          float o[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            o[i] = __builtin_fmaf(rs[j], dzh[c][i], __builtin_fmaf(e, zh[c][i], k));
+            cz[c][i] += o[i];
+          }
+          store8(dZb + (int64_t)row * N + ch * 8, o);
+        }
       }
     }
   }
@@ -311,17 +317,26 @@ __global__ __launch_bounds__(256) void ln_swish_bwd_kernel(LnArgs a, int B, int 
   }
 }
 
-int ln_bwd_partials(int B, int) { return (B + kLnRows - 1) / kLnRows; }
+// Rows per workgroup: kLnRows up to B = 4096 (one round of at most 512
+// workgroups for two encoders), then more rounds per workgroup instead of
+// more workgroups, so the column partials (3 N floats per workgroup, summed
+// again in the gradient reduction) stop growing with B.
+int ln_bwd_rows(int B) { return kLnRows * std::max(1, (B + 4095) / 4096); }
+int ln_bwd_partials(int B, int) {
+  const int rows = ln_bwd_rows(B);
+  return (B + rows - 1) / rows;
+}
 
 hipError_t launch_ln_swish_bwd(const LnArgs& a, int count, int B, int N, bool bf16, int,
                                hipStream_t s) {
   const int ch = (N / 8 + 63) / 64;
+  const int rows = ln_bwd_rows(B);
   const int nparts = ln_bwd_partials(B, 0);
   dim3 grid(nparts, count), block(256);
   const size_t lds = (size_t)4 * 3 * N * sizeof(float);
   const double bytes = (double)count * ((double)B * N * 3.0 * (bf16 ? 2 : 4) + 12.0 * nparts * N);
 #define LNB(T, C) CRL_TIMED("ln_swish_bwd_kernel", 0.0, bytes, s, \
-                            ln_swish_bwd_kernel<T, C><<<grid, block, lds, s>>>(a, B, N))
+                            ln_swish_bwd_kernel<T, C><<<grid, block, lds, s>>>(a, B, N, rows))
   if (bf16) { if (ch <= 1) LNB(bf16_t, 1); else LNB(bf16_t, 2); }
   else      { if (ch <= 1) LNB(float, 1);  else LNB(float, 2); }
 #undef LNB
