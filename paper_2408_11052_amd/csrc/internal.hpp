@@ -123,9 +123,9 @@ struct RedJob {
   int32_t nparts, n;
   int32_t M, N, tiles_n, bn;
 };
-// float4 outputs per block of the reduction with the Adam epilogue: half of a
-// 128 x 128 fragment-order tile (64 rows), or one 128 x 64 tile
-constexpr int kRedChunk4 = 2048;
+// float4 outputs per block of the reduction with the Adam epilogue: a 64 x 64
+// block of a fragment-order tile (two of its waves)
+constexpr int kRedChunk4 = 1024;
 struct AdamArgs;
 // few-part jobs (total4 float4 outputs) and many-part jobs (nblocks blocks of
 // 16 outputs) in one launch.  With A, each gradient element goes straight

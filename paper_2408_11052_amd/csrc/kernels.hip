@@ -549,11 +549,17 @@ __device__ inline int find_job_chunk(const RedJob* __restrict__ jobs, int njobs,
 }
 
 // Few parts with the Adam epilogue: block blk takes chunk c of one job
-// (kRedChunk4 float4 outputs, 8 per thread).  Dense jobs step their float4s
-// in place.  Fragment-order jobs sum their partials into an LDS copy of the
-// chunk's rows (64 rows of a 128-wide tile, or a whole 64-wide tile) and then
-// step the parameters row by row, so that p, m, v move in whole rows.
-constexpr int kRedLdsFloats = 128 * (64 + 4);  // >= 64 * (128 + 4)
+// (kRedChunk4 float4 outputs, 4 per thread).  Dense jobs step their float4s
+// in place.  Fragment-order jobs hold each tile wave by wave (64 x 32 per
+// wave, bn / 32 waves per 64-row half); a chunk is two consecutive waves, a
+// 64 x 64 block of the tile, whose partials are summed into an LDS copy of
+// the block and then stepped row by row, so that p, m, v move in 256-byte
+// row runs.  (Half-tile chunks took half the blocks, too few to fill the
+// chip when the vector is small.)
+constexpr int kRedWaves = kRedChunk4 * 4 / 2048;  // waves of a tile per chunk
+constexpr int kRedCols = 32 * kRedWaves;          // block columns
+constexpr int kRedLdsFloats = 64 * (kRedCols + 4);
+static_assert(kRedWaves == 2, "a chunk is two waves: a 64 x 64 block of a 64- or 128-wide tile");
 __device__ __forceinline__ void reduce_few_adam(const char* __restrict__ ws,
                                                 float* __restrict__ g,
                                                 const RedJob* __restrict__ jobs, int njobs,
@@ -576,11 +582,13 @@ __device__ __forceinline__ void reduce_few_adam(const char* __restrict__ ws,
     }
     return;
   }
-  // the chunk: tile t, rows [r0, r0 + R) of it (R = 64 for bn = 128, else 128)
-  const int bn = J.bn, ld = bn + 4, wpr = bn / 32;
+  // the chunk: tile t, waves [w0, w0 + 2): rows [R0, R0 + 64), columns
+  // [C0, C0 + 64) of the tile
+  const int bn = J.bn, wpr = bn / 32, ld = kRedCols + 4;
   const int64_t tsz4 = 32 * (int64_t)bn;  // float4s per tile
   const int t = (int)((c * kRedChunk4) / tsz4);
-  const int r0 = 64 * ((int)((c * kRedChunk4) % tsz4) / (16 * bn));  // 0 or 64
+  const int w0 = (int)(((c * kRedChunk4) % tsz4) / kRedChunk4) * kRedWaves;
+  const int R0 = (w0 / wpr) * 64, C0 = (w0 % wpr) * 32;
 #pragma unroll
   for (int k = 0; k < kRedChunk4 / 256; ++k) {
     const int64_t i4 = c * kRedChunk4 + k * 256 + tid;
@@ -588,16 +596,16 @@ __device__ __forceinline__ void reduce_few_adam(const char* __restrict__ ws,
     // float4 i4 = lane's 4 accumulator rows of fragment f of wave w of tile t
     const int rem = (int)(i4 * 4 - (int64_t)t * tsz4 * 4);
     const int w = rem >> 11, f = (rem >> 8) & 7, lane = (rem >> 2) & 63;
-    const int rl = (w / wpr) * 64 + (f >> 1) * 16 + (lane >> 4) * 4 - r0;
-    const int cl = (w % wpr) * 32 + (f & 1) * 16 + (lane & 15);
+    const int rl = (w / wpr) * 64 + (f >> 1) * 16 + (lane >> 4) * 4 - R0;
+    const int cl = (w % wpr) * 32 + (f & 1) * 16 + (lane & 15) - C0;
     T[rl * ld + cl] = r.x;
     T[(rl + 1) * ld + cl] = r.y;
     T[(rl + 2) * ld + cl] = r.z;
     T[(rl + 3) * ld + cl] = r.w;
   }
   __syncthreads();
-  const int q4 = bn / 4;  // float4s per chunk row
-  const int row0 = (t / J.tiles_n) * 128 + r0, col0 = (t % J.tiles_n) * bn;
+  constexpr int q4 = kRedCols / 4;  // float4s per block row
+  const int row0 = (t / J.tiles_n) * 128 + R0, col0 = (t % J.tiles_n) * bn + C0;
 #pragma unroll
   for (int k = 0; k < kRedChunk4 / 256; ++k) {
     const int v = k * 256 + tid;
