@@ -1006,49 +1006,55 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
 // the column sums of each block's 256 / D rows (the output layer's
 // bias-gradient partials).  en: 0 dot, 1 distance, 2 cosine.
 template <typename OutT, int D>
-__global__ __launch_bounds__(256) void bwd_reduce_kernel(FusedArgs a, int S, int B, int en) {
-  constexpr int TR = 256 / D;  // rows per block
+__global__ __launch_bounds__(256) void bwd_reduce_kernel(FusedArgs a, int S, int B, int en, int rounds) {
+  constexpr int TR = 256 / D;  // rows per round; a block takes `rounds` rounds
   __shared__ float red[256];
   const int side = blockIdx.y;
   const int c = threadIdx.x % D;
-  const int row = blockIdx.x * TR + threadIdx.x / D;
   const int64_t n = (int64_t)B * D;
-  const int64_t idx = (int64_t)row * D + c;
   const bf16_t* __restrict__ Xb = side ? a.psi_b : a.phi_b;
-  float s = 0.f;
-  if (row < B) {
-    const float* __restrict__ part = a.dX_part + (int64_t)side * S * n + idx;
+  float bsum = 0.f;  // the bias partial of this thread's column over the block's rows
 #pragma unroll 4
-    for (int i = 0; i < S; ++i) s += part[i * n];
-    if (en == 1) {
-      const float* __restrict__ rs = a.rs_part + (int64_t)side * S * B + row;
-      float h = 0.f;
-      for (int i = 0; i < S; ++i) h += rs[(int64_t)i * B];
-      s -= h * bf2f(Xb[idx]);
-    }
-  }
-  if (en == 2) {  // the row's dot product with its unit vector, a tree over its D threads
-    const float u = row < B ? bf2f(Xb[idx]) : 0.f;
-    red[threadIdx.x] = s * u;
-    __syncthreads();
-    for (int o = D / 2; o > 0; o >>= 1) {
-      if (c < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
-    }
-    const float dot = red[threadIdx.x - c];
-    __syncthreads();
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int row = (blockIdx.x * rounds + rd) * TR + threadIdx.x / D;
+    const int64_t idx = (int64_t)row * D + c;
+    float s = 0.f;
     if (row < B) {
-      const float nr = (side ? a.npsi : a.nphi)[row];
-      s = nr > 0.f ? (s - dot * u) / nr : 0.f;
+      const float* __restrict__ part = a.dX_part + (int64_t)side * S * n + idx;
+#pragma unroll 4
+      for (int i = 0; i < S; ++i) s += part[i * n];
+      if (en == 1) {
+        const float* __restrict__ rs = a.rs_part + (int64_t)side * S * B + row;
+        float h = 0.f;
+        for (int i = 0; i < S; ++i) h += rs[(int64_t)i * B];
+        s -= h * bf2f(Xb[idx]);
+      }
     }
-  }
-  if (row < B) {
-    (side ? a.dpsi : a.dphi)[idx] = s;
-    reinterpret_cast<OutT*>(side ? a.dpsi_t : a.dphi_t)[idx] = Store<OutT>::from_f(s);
+    if (en == 2) {  // the row's dot product with its unit vector, a tree over its D threads
+      const float u = row < B ? bf2f(Xb[idx]) : 0.f;
+      red[threadIdx.x] = s * u;
+      __syncthreads();
+      for (int o = D / 2; o > 0; o >>= 1) {
+        if (c < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+      }
+      const float dot = red[threadIdx.x - c];
+      __syncthreads();
+      if (row < B) {
+        const float nr = (side ? a.npsi : a.nphi)[row];
+        s = nr > 0.f ? (s - dot * u) / nr : 0.f;
+      }
+    }
+    if (row < B) {
+      (side ? a.dpsi : a.dphi)[idx] = s;
+      reinterpret_cast<OutT*>(side ? a.dpsi_t : a.dphi_t)[idx] = Store<OutT>::from_f(s);
+    }
+    bsum += row < B ? s : 0.f;  // rows past B add 0
   }
   float* bias = a.bias_part[side];
   if (bias == nullptr) return;
-  red[threadIdx.x] = row < B ? s : 0.f;  // rows past B add 0
+  __syncthreads();  // the cosine path's last use of red
+  red[threadIdx.x] = bsum;
   __syncthreads();
   if (threadIdx.x < D) {
     float t = red[threadIdx.x];
@@ -1058,7 +1064,20 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(FusedArgs a, int S, int
   }
 }
 
-int fused_bias_chunks(int B, int D) { return (int)(((int64_t)B * D + 255) / 256); }
+// Rounds of 256 / D rows per block of the backward reduction: enough that
+// the output layer's bias keeps at most 512 partial rows.  With one round it
+// had 16384 at B = 16384, D = 256, which the gradient reduction sums serially
+// per column (103 us for the reduction, 43.7 us with 512); capped at 256 the
+// rounds left this kernel too few blocks (91 us against 56).
+static int fused_bias_rounds(int B, int D) {
+  const int tr = 256 / D;
+  const int blocks = (B + tr - 1) / tr;
+  return std::max(1, (blocks + 511) / 512);
+}
+int fused_bias_chunks(int B, int D) {
+  const int rows = (256 / D) * fused_bias_rounds(B, D);
+  return (B + rows - 1) / rows;
+}
 
 #define CRL_FUSED_DISPATCH(KS_, BODY)                      \
   switch (D) {                                              \
@@ -1246,13 +1265,14 @@ hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int energy, int lo
   }
   const int ren = energy == CRL_ENERGY_COS ? 2 : (en != kEnDot ? 1 : 0);
   const dim3 rgrid(fused_bias_chunks(B, D), 2);
+  const int rounds = fused_bias_rounds(B, D);
   const double rb = 2.0 * (4.0 * (double)n * (S + 1.0) + (double)n * (out_bf16 ? 2 : 4));
   if (out_bf16) {
     CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
-              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<bf16_t, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, ren))));
+              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<bf16_t, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, ren, rounds))));
   } else {
     CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
-              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<float, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, ren))));
+              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<float, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, ren, rounds))));
   }
   return hipGetLastError();
 }
