@@ -235,6 +235,10 @@ CRL_API int crl_ring_sample_relabel(crl_ctx* ctx, const float* obs, const float*
  *                activations that crl_critic_bwd needs
  *   loss_out     device FP32 [8] out: {total, L_fwd, L_bwd, L_pen,
  *                mean_i r_i, mean_j c_j, #non-finite row/col terms, L_obj}
+ *   advance      device int64 (8-byte aligned) or NULL: if given, *advance
+ *                is incremented by 1 on the stream after everything above
+ *                has read its inputs, in the forward's last kernel (the
+ *                update's step counter without a crl_counter_add launch)
  * with F_ij = energy(phi_i, psi_j) (CRL_ENERGY_*), r_i = LSE_j F_ij,
  * c_j = LSE_i F_ij, L_fwd = mean_i (r_i - F_ii), L_bwd = mean_j (c_j - F_jj)
  * (the two InfoNCE directions, reported for every objective),
@@ -243,7 +247,7 @@ CRL_API int crl_ring_sample_relabel(crl_ctx* ctx, const float* obs, const float*
 CRL_API int crl_critic_fwd(crl_ctx* ctx, const float* params,
                            const uint16_t* params_bf16, const void* x_sa,
                            const void* x_g, void* ws, float* loss_out,
-                           void* stream);
+                           int64_t* advance, void* stream);
 
 /* Step 3: gradient of loss_out[0] w.r.t. every parameter, written (not
  * accumulated) into grads (device FP32, crl_param_count floats, padding set

@@ -58,7 +58,7 @@ SIGNATURES = {
     "crl_sample_relabel": (C.c_int, [P, P, P, I32, I32, U64, P, P, P, P, P, P]),
     "crl_replay_insert": (C.c_int, [P, P, P, I32, I32, I32, I32, P, P, P, I32, P, P]),
     "crl_ring_sample_relabel": (C.c_int, [P, P, P, P, I32, I32, P, U64, P, P, P, P, P, P]),
-    "crl_critic_fwd": (C.c_int, [P, P, P, P, P, P, P, P]),
+    "crl_critic_fwd": (C.c_int, [P, P, P, P, P, P, P, P, P]),
     "crl_critic_bwd": (C.c_int, [P, P, P, P, P, P, P, P]),
     "crl_critic_bwd_adam": (C.c_int, [P, P, P, P, P, P, P, P, P, P, C.c_double, C.c_double,
                                       C.c_double, C.c_double, P]),

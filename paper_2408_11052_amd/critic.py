@@ -207,9 +207,13 @@ class Critic:
                                             _ptr(x_sa), _ptr(x_g), _ptr(x_sg),
                                             _stream(stream)))
 
-    def crl_critic_fwd(self, params, params_bf16, x_sa, x_g, ws, loss_out, stream=None):
+    def crl_critic_fwd(self, params, params_bf16, x_sa, x_g, ws, loss_out, advance=None,
+                       stream=None):
+        """advance: optional int64 device counter incremented by the forward's
+        last kernel (in place of a crl_counter_add after the call)."""
         check(lib().crl_critic_fwd(self.ctx, _ptr(params), _ptr(params_bf16), _ptr(x_sa),
-                                   _ptr(x_g), _ptr(ws), _ptr(loss_out), _stream(stream)))
+                                   _ptr(x_g), _ptr(ws), _ptr(loss_out), _ptr(advance),
+                                   _stream(stream)))
 
     def crl_critic_bwd(self, params, params_bf16, x_sa, x_g, ws, grads, stream=None):
         check(lib().crl_critic_bwd(self.ctx, _ptr(params), _ptr(params_bf16), _ptr(x_sa),

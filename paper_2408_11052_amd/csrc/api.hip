@@ -887,8 +887,10 @@ int mlp_backward(crl_ctx* x, const NetCall* nc, int count, void* ws, hipStream_t
 // log-sum-exps and diagonal, and the loss parts, for the context's energy and
 // objective, with its buffers at the offsets o inside ws.  top (fused logits): the output layer's deferred split-K launch,
 // whose sum the prep kernel takes (phi and psi are then its outputs).
+// advance (may be NULL): a step counter that the loss kernel advances by one.
 int contrastive_fwd(crl_ctx* x, const float* phi, const float* psi, void* ws, const LossWs& o,
-                    float* loss_out, const GemmParams* top, hipStream_t s) {
+                    float* loss_out, const GemmParams* top, hipStream_t s,
+                    int64_t* advance = nullptr) {
   const int B = x->B, D = x->D;
   float* r = WF(ws, o.r);
   float* c = WF(ws, o.c);
@@ -940,7 +942,8 @@ int contrastive_fwd(crl_ctx* x, const float* phi, const float* psi, void* ws, co
     CRL_HIP(launch_fused_fwd(a, B, D, x->energy, (top && top->splits > 1) ? top : nullptr, s),
             "fused InfoNCE forward");
   }
-  CRL_HIP(launch_loss(r, c, dg, term, B, x->loss, x->cfg.logsumexp_penalty, loss_out, s), "loss");
+  CRL_HIP(launch_loss(r, c, dg, term, B, x->loss, x->cfg.logsumexp_penalty, loss_out, advance, s),
+          "loss");
   return CRL_OK;
 }
 
@@ -1250,9 +1253,11 @@ CRL_API int crl_ring_sample_relabel(crl_ctx* x, const float* obs, const float* a
 
 CRL_API int crl_critic_fwd(crl_ctx* x, const float* params, const uint16_t* params_bf16,
                            const void* x_sa, const void* x_g, void* ws, float* loss_out,
-                           void* stream) {
+                           int64_t* advance, void* stream) {
   if (!x) return fail(CRL_EINVAL, "NULL context");
   if (!params || !x_sa || !x_g || !ws || !loss_out) return fail(CRL_EINVAL, "NULL buffer argument");
+  if (reinterpret_cast<uintptr_t>(advance) % alignof(int64_t))
+    return fail(CRL_EINVAL, "advance must be 8-byte aligned");
   if (x->bf16 && !params_bf16) return fail(CRL_EINVAL, "BF16 precision needs params_bf16");
   if (!aligned16(params) || !aligned16(x_sa) || !aligned16(x_g) || !aligned16(ws) ||
       (params_bf16 && !aligned16(params_bf16)))
@@ -1269,7 +1274,7 @@ CRL_API int crl_critic_fwd(crl_ctx* x, const float* params, const uint16_t* para
   CRL_TRY(mlp_forward(x, nc, 2, ws, s, x->fused ? &top : nullptr));
 
   return contrastive_fwd(x, WF(ws, x->sl[0].out), WF(ws, x->sl[1].out), ws, loss_ws(x),
-                         loss_out, x->fused ? &top : nullptr, s);
+                         loss_out, x->fused ? &top : nullptr, s, advance);
 }
 
 CRL_API int crl_critic_bwd(crl_ctx* x, const float* params, const uint16_t* params_bf16,

@@ -167,9 +167,11 @@ struct LseMergeArgs {
 hipError_t launch_lse_merge(const LseMergeArgs& a, int count, int B, hipStream_t s);
 hipError_t launch_lse_merge(const float* pm, const float* ps, int nparts, int B,
                             float* out, hipStream_t s);
-// loss_out[8] from r, c, diag and (pairwise objectives) the per-row terms
+// loss_out[8] from r, c, diag and (pairwise objectives) the per-row terms;
+// then *advance += 1 if advance is not NULL (one workgroup, so no fence)
 hipError_t launch_loss(const float* r, const float* c, const float* diag, const float* term,
-                       int B, int loss, float beta, float* loss_out, hipStream_t s);
+                       int B, int loss, float beta, float* loss_out, int64_t* advance,
+                       hipStream_t s);
 hipError_t launch_l2_fix(float* dX, const float* X, const float* rs, int B, int D,
                          hipStream_t s);
 

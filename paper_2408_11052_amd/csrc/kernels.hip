@@ -925,7 +925,8 @@ __global__ __launch_bounds__(1024) void loss_kernel(const float* __restrict__ r,
                                                     const float* __restrict__ diag,
                                                     const float* __restrict__ term, int B,
                                                     int loss, float beta,
-                                                    float* __restrict__ loss_out) {
+                                                    float* __restrict__ loss_out,
+                                                    int64_t* __restrict__ advance) {
   __shared__ float sh[7][1024];
   float acc[6] = {0, 0, 0, 0, 0, 0}, cmp[6] = {0, 0, 0, 0, 0, 0};
   float bad = 0.f;
@@ -967,12 +968,14 @@ __global__ __launch_bounds__(1024) void loss_kernel(const float* __restrict__ r,
     loss_out[5] = sh[4][0] * inv;
     loss_out[6] = sh[6][0];
     loss_out[7] = obj;
+    if (advance) *advance += 1;
   }
 }
 hipError_t launch_loss(const float* r, const float* c, const float* diag, const float* term,
-                       int B, int loss, float beta, float* loss_out, hipStream_t s) {
+                       int B, int loss, float beta, float* loss_out, int64_t* advance,
+                       hipStream_t s) {
   CRL_TIMED("loss_kernel", 0.0, 16.0 * B, s,
-            loss_kernel<<<1, 1024, 0, s>>>(r, c, diag, term, B, loss, beta, loss_out));
+            loss_kernel<<<1, 1024, 0, s>>>(r, c, diag, term, B, loss, beta, loss_out, advance));
   return hipGetLastError();
 }
 

@@ -7,8 +7,9 @@ the entropy coefficient.  The batch counter
 n (the Philox counter word) and the Adam step t live in device memory and are
 advanced by the library on the stream, so the same enqueued sequence can be
 captured once into a HIP graph and replayed for consecutive updates.  In the
-critic-only update t is n itself: n is advanced once the relabelling has read
-it, so the Adam step of update k sees k + 1, as a separate step counter would.
+critic-only update t is n itself: the critic forward's last kernel advances n
+after the relabelling has read it, so the Adam step of update k sees k + 1, as
+a separate step counter would (the full update's forward advances its own t).
 
 The batch comes either from a static buffer of one episode per environment
 row, or from a ReplayRing; with a ring, ``capture_iteration`` records one
@@ -60,14 +61,16 @@ class CriticUpdate:
         self.n = torch.zeros(1, dtype=torch.int64, device=self.dev)  # batch counter
         self.t = self.n  # Adam step (the full update keeps its own)
 
-    def _critic_fwd(self, x_sg):
+    def _critic_fwd(self, x_sg, advance):
+        """Relabel (reads n), then the critic forward, whose last kernel
+        advances the counter `advance`."""
         c = self.crit
         if self.ring is not None:
             self.ring.sample_relabel(c, self.seed, self.n, self.idx, self.x_sa, self.x_g, x_sg)
         else:
             c.crl_sample_relabel(self.obs, self.act, self.seed, self.n, self.idx, self.x_sa,
                                  self.x_g, x_sg)
-        c.crl_critic_fwd(self.params, self.pbf, self.x_sa, self.x_g, self.ws, self.loss)
+        c.crl_critic_fwd(self.params, self.pbf, self.x_sa, self.x_g, self.ws, self.loss, advance)
 
     def _critic_step(self):
         """The critic gradient fed into its Adam step (step t)."""
@@ -77,8 +80,7 @@ class CriticUpdate:
 
     def enqueue(self):
         """Enqueue one critic update on the current stream (no host sync)."""
-        self._critic_fwd(None)
-        crl_counter_add(self.n, 1)  # also the Adam step
+        self._critic_fwd(None, self.n)  # n is also the Adam step
         self._critic_step()
 
     def capture(self, steps: int = 1) -> torch.cuda.CUDAGraph:
@@ -161,8 +163,7 @@ class FullUpdate(CriticUpdate):
     def enqueue(self):
         """Enqueue one full update (critic, policy, alpha) on the current stream."""
         c = self.crit
-        self._critic_fwd(self.x_sg)
-        crl_counter_add(self.t, 1)
+        self._critic_fwd(self.x_sg, self.t)
         self._critic_step()
         c.crl_actor_step_adam(self.params, self.pbf, self.aparams, self.apbf, self.log_alpha,
                               self.x_sa, self.x_g, self.x_sg, self.seed, self.n, self.ws,
