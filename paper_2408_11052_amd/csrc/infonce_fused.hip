@@ -1003,12 +1003,13 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
 //   dX = sum_s part[s]  (- (sum_s rs[s]) * X_bf16 for the distance energies;
 //   for the cosine energy, with U the BF16 unit rows: (dX - (dX . U) U) / |X|),
 // FP32 and storage copies, one element per thread; with bias_part set, also
-// the column sums of each block's 256 / D rows (the output layer's
-// bias-gradient partials).  en: 0 dot, 1 distance, 2 cosine.
-template <typename OutT, int D>
-__global__ __launch_bounds__(256) void bwd_reduce_kernel(FusedArgs a, int S, int B, int en, int rounds) {
-  constexpr int TR = 256 / D;  // rows per round; a block takes `rounds` rounds
-  __shared__ float red[256];
+// the column sums of each block's rows (the output layer's bias-gradient
+// partials).  en: 0 dot, 1 distance, 2 cosine.  NT threads per block:
+// red_threads(D).
+template <typename OutT, int D, int NT>
+__global__ __launch_bounds__(NT) void bwd_reduce_kernel(FusedArgs a, int S, int B, int en, int rounds) {
+  constexpr int TR = NT / D;  // rows per round; a block takes `rounds` rounds
+  __shared__ float red[NT];
   const int side = blockIdx.y;
   const int c = threadIdx.x % D;
   const int64_t n = (int64_t)B * D;
@@ -1064,18 +1065,23 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(FusedArgs a, int S, int
   }
 }
 
-// Rounds of 256 / D rows per block of the backward reduction: enough that
-// the output layer's bias keeps at most 512 partial rows.  With one round it
-// had 16384 at B = 16384, D = 256, which the gradient reduction sums serially
-// per column (103 us for the reduction, 43.7 us with 512); capped at 256 the
-// rounds left this kernel too few blocks (91 us against 56).
+// Threads per block of the backward reduction: 1024 at D >= 128, so that a
+// block's rounds (below) stay few and each SIMD holds eight wavefronts of
+// them; 256 below.
+static constexpr int red_threads(int D) { return D >= 128 ? 1024 : 256; }
+
+// Rounds of red_threads(D) / D rows per block of the backward reduction:
+// enough that the output layer's bias keeps at most 512 partial rows.  With
+// one round it had 16384 at B = 16384, D = 256, which the gradient reduction
+// sums serially per column (103 us for the reduction, 43.7 us with 512);
+// capped at 256 the rounds left this kernel too few blocks (91 us against 56).
 static int fused_bias_rounds(int B, int D) {
-  const int tr = 256 / D;
+  const int tr = red_threads(D) / D;
   const int blocks = (B + tr - 1) / tr;
   return std::max(1, (blocks + 511) / 512);
 }
 int fused_bias_chunks(int B, int D) {
-  const int rows = (256 / D) * fused_bias_rounds(B, D);
+  const int rows = (red_threads(D) / D) * fused_bias_rounds(B, D);
   return (B + rows - 1) / rows;
 }
 
@@ -1269,10 +1275,12 @@ hipError_t launch_fused_bwd(const FusedArgs& a, int B, int D, int energy, int lo
   const double rb = 2.0 * (4.0 * (double)n * (S + 1.0) + (double)n * (out_bf16 ? 2 : 4));
   if (out_bf16) {
     CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
-              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<bf16_t, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, ren, rounds))));
+              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<bf16_t, KS * 32, red_threads(KS * 32)>
+                                      <<<rgrid, red_threads(KS * 32), 0, s>>>(a, S, B, ren, rounds))));
   } else {
     CRL_TIMED("bwd_reduce_kernel", 0.0, rb, s,
-              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<float, KS * 32><<<rgrid, 256, 0, s>>>(a, S, B, ren, rounds))));
+              CRL_FUSED_DISPATCH(KS, (bwd_reduce_kernel<float, KS * 32, red_threads(KS * 32)>
+                                      <<<rgrid, red_threads(KS * 32), 0, s>>>(a, S, B, ren, rounds))));
   }
   return hipGetLastError();
 }
