@@ -1002,40 +1002,53 @@ __global__ __launch_bounds__(1024) void infonce_bwd_both_kernel(FusedArgs a, int
 // dphi and dpsi (blockIdx.y) from the S split partials:
 //   dX = sum_s part[s]  (- (sum_s rs[s]) * X_bf16 for the distance energies;
 //   for the cosine energy, with U the BF16 unit rows: (dX - (dX . U) U) / |X|),
-// FP32 and storage copies, one element per thread; with bias_part set, also
-// the column sums of each block's rows (the output layer's bias-gradient
-// partials).  en: 0 dot, 1 distance, 2 cosine.  NT threads per block:
-// red_threads(D).
+// FP32 and storage copies, four consecutive columns per thread (16-byte
+// loads and stores); with bias_part set, also the column sums of each
+// block's rows (the output layer's bias-gradient partials).  en: 0 dot,
+// 1 distance, 2 cosine.  NT threads per block: red_threads(D).
+constexpr int kRedVec = 4;  // columns per thread
 template <typename OutT, int D, int NT>
 __global__ __launch_bounds__(NT) void bwd_reduce_kernel(FusedArgs a, int S, int B, int en, int rounds) {
-  constexpr int TR = NT / D;  // rows per round; a block takes `rounds` rounds
+  constexpr int TPR = D / kRedVec;  // threads per row
+  constexpr int TR = NT / TPR;      // rows per round; a block takes `rounds` rounds
   __shared__ float red[NT];
+  __shared__ float4 redv[NT];
   const int side = blockIdx.y;
-  const int c = threadIdx.x % D;
+  const int c = threadIdx.x % TPR;
   const int64_t n = (int64_t)B * D;
   const bf16_t* __restrict__ Xb = side ? a.psi_b : a.phi_b;
-  float bsum = 0.f;  // the bias partial of this thread's column over the block's rows
-#pragma unroll 4
+  float4 bsum = make_float4(0.f, 0.f, 0.f, 0.f);  // this thread's columns over the block's rows
+#pragma unroll 2
   for (int rd = 0; rd < rounds; ++rd) {
-    const int row = (blockIdx.x * rounds + rd) * TR + threadIdx.x / D;
-    const int64_t idx = (int64_t)row * D + c;
-    float s = 0.f;
+    const int row = (blockIdx.x * rounds + rd) * TR + threadIdx.x / TPR;
+    const int64_t idx = (int64_t)row * D + c * kRedVec;
+    float v[kRedVec] = {0.f, 0.f, 0.f, 0.f}, u[kRedVec] = {0.f, 0.f, 0.f, 0.f};
     if (row < B) {
       const float* __restrict__ part = a.dX_part + (int64_t)side * S * n + idx;
-#pragma unroll 4
-      for (int i = 0; i < S; ++i) s += part[i * n];
+#pragma unroll 2
+      for (int i = 0; i < S; ++i) {
+        const float4 p = *reinterpret_cast<const float4*>(part + i * n);
+        v[0] += p.x; v[1] += p.y; v[2] += p.z; v[3] += p.w;
+      }
+      if (en != 0) {
+        const uint2 xw = *reinterpret_cast<const uint2*>(Xb + idx);
+        u[0] = __builtin_bit_cast(float, xw.x << 16);
+        u[1] = __builtin_bit_cast(float, xw.x & 0xffff0000u);
+        u[2] = __builtin_bit_cast(float, xw.y << 16);
+        u[3] = __builtin_bit_cast(float, xw.y & 0xffff0000u);
+      }
       if (en == 1) {
         const float* __restrict__ rs = a.rs_part + (int64_t)side * S * B + row;
         float h = 0.f;
         for (int i = 0; i < S; ++i) h += rs[(int64_t)i * B];
-        s -= h * bf2f(Xb[idx]);
+#pragma unroll
+        for (int k = 0; k < kRedVec; ++k) v[k] -= h * u[k];
       }
     }
-    if (en == 2) {  // the row's dot product with its unit vector, a tree over its D threads
-      const float u = row < B ? bf2f(Xb[idx]) : 0.f;
-      red[threadIdx.x] = s * u;
+    if (en == 2) {  // the row's dot product with its unit vector, a tree over its TPR threads
+      red[threadIdx.x] = (v[0] * u[0] + v[1] * u[1]) + (v[2] * u[2] + v[3] * u[3]);
       __syncthreads();
-      for (int o = D / 2; o > 0; o >>= 1) {
+      for (int o = TPR / 2; o > 0; o >>= 1) {
         if (c < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
       }
@@ -1043,25 +1056,32 @@ __global__ __launch_bounds__(NT) void bwd_reduce_kernel(FusedArgs a, int S, int 
       __syncthreads();
       if (row < B) {
         const float nr = (side ? a.npsi : a.nphi)[row];
-        s = nr > 0.f ? (s - dot * u) / nr : 0.f;
+#pragma unroll
+        for (int k = 0; k < kRedVec; ++k) v[k] = nr > 0.f ? (v[k] - dot * u[k]) / nr : 0.f;
       }
     }
     if (row < B) {
-      (side ? a.dpsi : a.dphi)[idx] = s;
-      reinterpret_cast<OutT*>(side ? a.dpsi_t : a.dphi_t)[idx] = Store<OutT>::from_f(s);
+      *reinterpret_cast<float4*>((side ? a.dpsi : a.dphi) + idx) = make_float4(v[0], v[1], v[2], v[3]);
+      OutT* t = reinterpret_cast<OutT*>(side ? a.dpsi_t : a.dphi_t) + idx;
+      if constexpr (sizeof(OutT) == 2)
+        *reinterpret_cast<uint2*>(t) = make_uint2(pack2bf(v[0], v[1]), pack2bf(v[2], v[3]));
+      else
+        *reinterpret_cast<float4*>(t) = make_float4(v[0], v[1], v[2], v[3]);
+      bsum.x += v[0]; bsum.y += v[1]; bsum.z += v[2]; bsum.w += v[3];  // rows past B add nothing
     }
-    bsum += row < B ? s : 0.f;  // rows past B add 0
   }
   float* bias = a.bias_part[side];
   if (bias == nullptr) return;
-  __syncthreads();  // the cosine path's last use of red
-  red[threadIdx.x] = bsum;
+  redv[threadIdx.x] = bsum;
   __syncthreads();
-  if (threadIdx.x < D) {
-    float t = red[threadIdx.x];
+  if (threadIdx.x < TPR) {
+    float4 t = redv[threadIdx.x];
 #pragma unroll
-    for (int q = 1; q < TR; ++q) t += red[q * D + threadIdx.x];
-    bias[(int64_t)blockIdx.x * D + threadIdx.x] = t;
+    for (int q = 1; q < TR; ++q) {
+      const float4 w = redv[q * TPR + threadIdx.x];
+      t.x += w.x; t.y += w.y; t.z += w.z; t.w += w.w;
+    }
+    *reinterpret_cast<float4*>(bias + (int64_t)blockIdx.x * D + threadIdx.x * kRedVec) = t;
   }
 }
 
@@ -1070,18 +1090,18 @@ __global__ __launch_bounds__(NT) void bwd_reduce_kernel(FusedArgs a, int S, int 
 // them; 256 below.
 static constexpr int red_threads(int D) { return D >= 128 ? 1024 : 256; }
 
-// Rounds of red_threads(D) / D rows per block of the backward reduction:
+// Rounds of red_threads(D) * kRedVec / D rows per block of the backward reduction:
 // enough that the output layer's bias keeps at most 512 partial rows.  With
 // one round it had 16384 at B = 16384, D = 256, which the gradient reduction
 // sums serially per column (103 us for the reduction, 43.7 us with 512);
 // capped at 256 the rounds left this kernel too few blocks (91 us against 56).
 static int fused_bias_rounds(int B, int D) {
-  const int tr = red_threads(D) / D;
+  const int tr = red_threads(D) * kRedVec / D;
   const int blocks = (B + tr - 1) / tr;
   return std::max(1, (blocks + 511) / 512);
 }
 int fused_bias_chunks(int B, int D) {
-  const int rows = (red_threads(D) / D) * fused_bias_rounds(B, D);
+  const int rows = (red_threads(D) * kRedVec / D) * fused_bias_rounds(B, D);
   return (B + rows - 1) / rows;
 }
 
