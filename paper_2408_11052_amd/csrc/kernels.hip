@@ -408,7 +408,19 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(ColSumArgs a, int B
   float acc[4] = {0, 0, 0, 0};
   if (n0 < N) {
     const T* X = reinterpret_cast<const T*>(a.X[e]);
-    for (int row = r0 + wave; row < r1; row += 4) {
+    // the wavefront's rows r0 + wave, + 4, + 8, ... in that order, eight
+    // rows' loads in flight before they are added
+    int row = r0 + wave;
+    for (; row + 28 < r1; row += 32) {
+      float v[8][4];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) load4(X + (int64_t)(row + 4 * k) * ld + n0, v[k]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += v[k][i];
+    }
+    for (; row < r1; row += 4) {
       float v[4];
       load4(X + (int64_t)row * ld + n0, v);
 #pragma unroll
