@@ -881,17 +881,17 @@ hipError_t launch_col_lse_partial(const float* F, int B, int ld, int rchunks, fl
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void lse_merge_kernel(LseMergeArgs a, int B) {
-  // problem blockIdx.y; 16 columns per workgroup, the parts split over 16
-  // groups (p = grp, grp + 16, ...), then a fixed-order tree over the groups
-  // in LDS
-  __shared__ float sm[16][17], ss[16][17];
+__global__ __launch_bounds__(1024) void lse_merge_kernel(LseMergeArgs a, int B) {
+  // problem blockIdx.y; 64 columns per workgroup (a wavefront reads 256
+  // contiguous bytes of one part), the parts split over the 16 wavefronts
+  // (p = grp, grp + 16, ...), then a fixed-order tree over them in LDS
+  __shared__ float sm[16][65], ss[16][65];
   const int e = blockIdx.y;
   const float* __restrict__ pm = a.pm[e];
   const float* __restrict__ ps = a.ps[e];
   const int nparts = a.nparts[e];
-  const int col = threadIdx.x & 15, grp = threadIdx.x >> 4;
-  const int j = blockIdx.x * 16 + col;
+  const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + col;
   float m = -INFINITY, s = 0.f;
   if (j < B)
     for (int p = grp; p < nparts; p += 16)
@@ -914,7 +914,7 @@ hipError_t launch_lse_merge(const LseMergeArgs& a, int count, int B, hipStream_t
   double parts = 0.0;
   for (int e = 0; e < count; ++e) parts += a.nparts[e];
   CRL_TIMED("lse_merge_kernel", 0.0, 4.0 * B * (2.0 * parts + count), s,
-            lse_merge_kernel<<<dim3((B + 15) / 16, count), 256, 0, s>>>(a, B));
+            lse_merge_kernel<<<dim3((B + 63) / 64, count), 1024, 0, s>>>(a, B));
   return hipGetLastError();
 }
 hipError_t launch_lse_merge(const float* pm, const float* ps, int nparts, int B, float* out,
