@@ -504,7 +504,7 @@ void plan_group(crl_ctx* x, int gi, int64_t& off) {
   G.many_bytes = 0;
   for (RedJob& j : G.many) {
     j.first = G.nblocks;
-    G.nblocks += (j.n + 15) / 16;
+    G.nblocks += (j.n + kManyCols - 1) / kManyCols;
     G.many_bytes += 4.0 * j.n * (j.nparts + 1.0);
   }
   (void)B;

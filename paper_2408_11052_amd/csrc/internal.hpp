@@ -126,6 +126,7 @@ struct RedJob {
 // float4 outputs per block of the reduction with the Adam epilogue: a 64 x 64
 // block of a fragment-order tile (two of its waves)
 constexpr int kRedChunk4 = 1024;
+constexpr int kManyCols = 32;  // outputs per workgroup of a many-part reduction job
 struct AdamArgs;
 // few-part jobs (total4 float4 outputs) and many-part jobs (nblocks blocks of
 // 16 outputs) in one launch.  With A, each gradient element goes straight

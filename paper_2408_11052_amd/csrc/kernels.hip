@@ -701,17 +701,19 @@ __device__ __forceinline__ void reduce_few(const char* __restrict__ ws, float* _
   }
 }
 
-// many parts (per-chunk column partials): 16 outputs per workgroup, the parts
-// over 16 groups, then a fixed-order tree in LDS.  A job with no parts writes
+// many parts (per-chunk column partials): kManyCols = 32 outputs per
+// workgroup (a wavefront reads two whole 128-byte lines per load), the parts
+// over 8 groups, then a fixed-order tree in LDS.  A job with no parts writes
 // zeros (the padding between parameter tensors).
 template <bool ADAM>
 __device__ __forceinline__ void reduce_many(const char* __restrict__ ws, float* __restrict__ g,
                                             const RedJob* __restrict__ jobs, int njobs,
                                             int64_t blk, const AdamArgs& A, float c1, float c2) {
-  __shared__ float red[16][17];
+  constexpr int NG = 256 / kManyCols;  // groups
+  __shared__ float red[NG][kManyCols + 1];
   const RedJob J = jobs[find_job(jobs, njobs, blk)];
-  const int col = threadIdx.x & 15, grp = threadIdx.x >> 4;
-  const int64_t i = (blk - J.first) * 16 + col;
+  const int col = threadIdx.x % kManyCols, grp = threadIdx.x / kManyCols;
+  const int64_t i = (blk - J.first) * kManyCols + col;
   // eight running sums: eight loads in flight per thread
   float sk[8];
 #pragma unroll
@@ -719,15 +721,15 @@ __device__ __forceinline__ void reduce_many(const char* __restrict__ ws, float* 
   if (i < J.n) {
     const float* p = reinterpret_cast<const float*>(ws + J.src) + i;
     int k = grp;
-    for (; k + 112 < J.nparts; k += 128) {
+    for (; k + 7 * NG < J.nparts; k += 8 * NG) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sk[q] += p[(k + 16 * q) * J.stride];
+      for (int q = 0; q < 8; ++q) sk[q] += p[(k + NG * q) * J.stride];
     }
-    for (; k < J.nparts; k += 16) sk[0] += p[k * J.stride];
+    for (; k < J.nparts; k += NG) sk[0] += p[k * J.stride];
   }
   red[grp][col] = ((sk[0] + sk[1]) + (sk[2] + sk[3])) + ((sk[4] + sk[5]) + (sk[6] + sk[7]));
   __syncthreads();
-  for (int h = 8; h >= 1; h >>= 1) {
+  for (int h = NG / 2; h >= 1; h >>= 1) {
     if (grp < h) red[grp][col] += red[grp + h][col];
     __syncthreads();
   }
