@@ -203,7 +203,8 @@ def _bwd_adam_case(case):
 def test_bwd_adam_equals_bwd_then_adam(case):
     """crl_critic_bwd_adam against crl_critic_bwd followed by crl_adam_step on
     the same batch: parameters, BF16 copy, m and v bit for bit over three
-    steps, the gradient (when kept) equal as values."""
+    steps, the gradient (when kept) equal as values; the second forward also
+    advances a step counter (advance=), once per call, with the same loss."""
     from paper_2408_11052_amd import Critic, crl_adam_step, crl_cast_bf16
     w = _bwd_adam_case(case)
     obs, act, phi, psi = setup(w, perturb=0.1)
@@ -226,7 +227,9 @@ def test_bwd_adam_equals_bwd_then_adam(case):
     ws = crit.workspace(DEV)
     idx = torch.zeros(w.batch_size, 3, dtype=torch.int32, device=DEV)
     loss = torch.zeros(8, dtype=torch.float32, device=DEV)
+    loss_b = torch.zeros(8, dtype=torch.float32, device=DEV)
     t = torch.zeros(1, dtype=torch.int64, device=DEV)
+    adv = torch.full((1,), 40, dtype=torch.int64, device=DEV)  # advanced by b's forward
     lr = 3e-4
     bits = lambda x: x.view(torch.int32) if x.dtype == torch.float32 else x.view(torch.int16)
     for step in range(3):
@@ -238,10 +241,12 @@ def test_bwd_adam_equals_bwd_then_adam(case):
         crit.crl_critic_bwd(a["p"], a["pb"], x_sa, x_g, ws, a["g"])
         crl_adam_step(a["p"], a["g"], a["m"], a["v"], a["pb"], t, lr)
         crit.crl_sample_relabel(d_obs, d_act, 2, d_step, idx, x_sa, x_g, x_sg)
-        crit.crl_critic_fwd(b["p"], b["pb"], x_sa, x_g, ws, loss)
+        crit.crl_critic_fwd(b["p"], b["pb"], x_sa, x_g, ws, loss_b, advance=adv)
         crit.crl_critic_bwd_adam(b["p"], b["pb"], x_sa, x_g, ws, b["g"] if keep else None,
                                  b["m"], b["v"], t, lr)
         torch.cuda.synchronize()
+        assert torch.equal(bits(loss), bits(loss_b)), step
+        assert int(adv.item()) == 41 + step  # one increment per forward
         if keep:
             assert torch.equal(a["g"], b["g"]), step
         for k in ("p", "m", "v", "pb"):
